@@ -1,0 +1,232 @@
+"""CPU oracle of the entropy-stable DGSEM shallow-water right-hand side.
+
+TEST INFRASTRUCTURE ONLY: this package is the plain FP64 reference that the
+GPU library is checked against.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import it; the product path never does.
+
+The arithmetic lives in ``esdg_oracle.c`` (plain C, built with
+``gcc -O2 -ffp-contract=off``); this module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "esdg_oracle.c")
+_LIB = os.path.join(_HERE, "libesdg_oracle.so")
+
+OK, EINVAL, ENOMEM, ENEGMEAN = 0, -1, -2, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library in place (gcc, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                               "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("g", C.c_double), ("h_tol", C.c_double), ("eps0", C.c_double),
+                ("sigma_min", C.c_double), ("sigma_max", C.c_double), ("cfl", C.c_double),
+                ("cfl_visc", C.c_double), ("surface_flux", C.c_int), ("av_on", C.c_int),
+                ("limiter_on", C.c_int), ("integrator", C.c_int), ("max_dt_retries", C.c_int)]
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("N", C.c_int), ("K", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p),
+                ("nbr_elem", C.c_void_p), ("nbr_side", C.c_void_p), ("flip", C.c_void_p)]
+
+
+class _Parts(C.Structure):
+    _fields_ = [("Lvol", C.c_void_p * 3), ("S", C.c_void_p * 3), ("Lv", C.c_void_p * 3),
+                ("grad", C.c_void_p * 4)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P, I, I64 = C.c_void_p, C.c_int, C.c_int64
+        L.orc_operators.argtypes = [I, P, P, P, P, P, P]
+        L.orc_geometry.argtypes = [I, I64, P, P, P, P, P, P, P]
+        L.orc_volume_flux.argtypes = [C.c_double, C.c_double, P, P, P, P]
+        L.orc_volume_flux.restype = None
+        L.orc_surface_flux.argtypes = [P, P, C.c_double, P, C.c_double, C.c_double, C.c_double, P]
+        L.orc_surface_flux.restype = None
+        L.orc_indicator.argtypes = [P, I, I64, P, P]
+        L.orc_rhs.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_limit.argtypes = [P, P, P, P, P, P]
+        L.orc_dt.argtypes = [P, P, P, P, P, P, P]
+        L.orc_step.argtypes = [P, P, P, P, P, P, I, C.c_double, P, P]
+        L.orc_diagnostics.argtypes = [P, P, P, P, P, P, P]
+        L.orc_lsrk_coefficients.argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_sigma(N: int):
+    """Indicator thresholds s0 -+ 1 with s0 = -4 log10(N) (the paper gives no
+    values; this follows the N^-4 scaling of the indicator it cites)."""
+    s0 = -4.0 * math.log10(N)
+    return s0 - 1.0, s0 + 1.0
+
+
+def params(N: int = 3, **kw) -> Params:
+    smin, smax = default_sigma(N)
+    d = dict(g=9.81, h_tol=1e-4, eps0=0.0, sigma_min=smin, sigma_max=smax, cfl=0.5,
+             cfl_visc=0.5, surface_flux=0, av_on=0, limiter_on=0, integrator=0,
+             max_dt_retries=0)
+    d.update(kw)
+    return Params(**d)
+
+
+class _MeshRef:
+    """Keeps the contiguous arrays alive while C holds pointers to them."""
+
+    def __init__(self, mesh):
+        self.N = int(mesh.N)
+        self.x = _f64(mesh.x)
+        self.y = _f64(mesh.y)
+        self.ne = np.ascontiguousarray(mesh.nbr_elem, dtype=np.int32)
+        self.ns = np.ascontiguousarray(mesh.nbr_side, dtype=np.int8)
+        self.fl = np.ascontiguousarray(mesh.flip, dtype=np.int8)
+        self.K = self.x.shape[0]
+        self.c = _Mesh(self.N, self.K, _p(self.x), _p(self.y), _p(self.ne), _p(self.ns), _p(self.fl))
+
+
+def _check(st, what):
+    if st not in (OK,):
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+def operators(N: int) -> dict:
+    n1 = N + 1
+    out = {k: np.zeros((n1, n1)) for k in ("D", "Dtilde", "Dhat", "Vinv")}
+    xi, w = np.zeros(n1), np.zeros(n1)
+    _check(lib().orc_operators(N, _p(xi), _p(w), _p(out["D"]), _p(out["Dtilde"]),
+                               _p(out["Dhat"]), _p(out["Vinv"])), "operators")
+    out["xi"], out["w"] = xi, w
+    return out
+
+
+def geometry(mesh) -> dict:
+    M = _MeshRef(mesh)
+    out = {k: np.zeros_like(M.x) for k in ("xxi", "xeta", "yxi", "yeta", "J")}
+    _check(lib().orc_geometry(M.N, M.K, _p(M.x), _p(M.y), _p(out["xxi"]), _p(out["xeta"]),
+                              _p(out["yxi"]), _p(out["yeta"]), _p(out["J"])), "geometry")
+    return out
+
+
+def volume_flux(g, h_tol, wa, wb):
+    wa, wb = _f64(wa), _f64(wb)
+    F, G = np.zeros(3), np.zeros(3)
+    lib().orc_volume_flux(g, h_tol, _p(wa), _p(wb), _p(F), _p(G))
+    return F, G
+
+
+def surface_flux(P: Params, wm, bm, wp, bp, nx, ny):
+    wm, wp = _f64(wm), _f64(wp)
+    F = np.zeros(3)
+    lib().orc_surface_flux(C.byref(P), _p(wm), float(bm), _p(wp), float(bp), float(nx),
+                           float(ny), _p(F))
+    return F
+
+
+def indicator(P: Params, N: int, h) -> np.ndarray:
+    h = _f64(h)
+    K = h.shape[0]
+    eps = np.zeros(K)
+    _check(lib().orc_indicator(C.byref(P), N, K, _p(h), _p(eps)), "indicator")
+    return eps
+
+
+def rhs(P: Params, mesh, b, h, hu, hv, need=None, parts: bool = False):
+    """R = dW/dt.  ``need``: optional boolean [K] mask of elements to
+    evaluate (others are left zero).  With ``parts`` also returns the volume
+    + surface operator L, the source S, the viscous term L^v and the BR1
+    gradients (U1, U2, V1, V2)."""
+    M = _MeshRef(mesh)
+    b, h, hu, hv = _f64(b), _f64(h), _f64(hu), _f64(hv)
+    Rh, Rhu, Rhv = np.zeros_like(h), np.zeros_like(h), np.zeros_like(h)
+    eps = np.zeros(M.K)
+    nd = None if need is None else np.ascontiguousarray(need, dtype=np.uint8)
+    pr, keep = None, None
+    if parts:
+        keep = {k: [np.zeros_like(h) for _ in range(n)] for k, n in
+                (("L", 3), ("S", 3), ("Lv", 3), ("grad", 4))}
+        pr = _Parts((C.c_void_p * 3)(*[a.ctypes.data for a in keep["L"]]),
+                    (C.c_void_p * 3)(*[a.ctypes.data for a in keep["S"]]),
+                    (C.c_void_p * 3)(*[a.ctypes.data for a in keep["Lv"]]),
+                    (C.c_void_p * 4)(*[a.ctypes.data for a in keep["grad"]]))
+    st = lib().orc_rhs(C.byref(P), C.byref(M.c), _p(b), _p(h), _p(hu), _p(hv), _p(Rh),
+                       _p(Rhu), _p(Rhv), _p(eps), _p(nd), C.byref(pr) if pr is not None else None)
+    _check(st, "rhs")
+    if parts:
+        return Rh, Rhu, Rhv, eps, keep
+    return Rh, Rhu, Rhv, eps
+
+
+def limit(P: Params, mesh, h, hu, hv):
+    M = _MeshRef(mesh)
+    h, hu, hv = _f64(h).copy(), _f64(hu).copy(), _f64(hv).copy()
+    nl = C.c_int64(0)
+    st = lib().orc_limit(C.byref(P), C.byref(M.c), _p(h), _p(hu), _p(hv), C.byref(nl))
+    if st not in (OK, ENEGMEAN):
+        _check(st, "limit")
+    return h, hu, hv, int(nl.value), st
+
+
+def dt(P: Params, mesh, b, h, hu, hv):
+    M = _MeshRef(mesh)
+    out = np.zeros(4)
+    _check(lib().orc_dt(C.byref(P), C.byref(M.c), _p(_f64(b)), _p(_f64(h)), _p(_f64(hu)),
+                        _p(_f64(hv)), _p(out)), "dt")
+    return out  # dt, dt_cfl, dt_visc, dt_pos
+
+
+def step(P: Params, mesh, b, h, hu, hv, nsteps: int, dt_fixed: float = 0.0, t0: float = 0.0):
+    M = _MeshRef(mesh)
+    h, hu, hv = _f64(h).copy(), _f64(hu).copy(), _f64(hv).copy()
+    t = C.c_double(t0)
+    last = C.c_double(0.0)
+    st = lib().orc_step(C.byref(P), C.byref(M.c), _p(_f64(b)), _p(h), _p(hu), _p(hv),
+                        int(nsteps), float(dt_fixed), C.byref(t), C.byref(last))
+    if st not in (OK, ENEGMEAN):
+        _check(st, "step")
+    return h, hu, hv, t.value, st
+
+
+def diagnostics(P: Params, mesh, b, h, hu, hv):
+    """mass, mom_x, mom_y, entropy E, dE/dt, min h, max h, #dry nodes."""
+    M = _MeshRef(mesh)
+    out = np.zeros(8)
+    _check(lib().orc_diagnostics(C.byref(P), C.byref(M.c), _p(_f64(b)), _p(_f64(h)),
+                                 _p(_f64(hu)), _p(_f64(hv)), _p(out)), "diagnostics")
+    return out
+
+
+def lsrk_coefficients():
+    a, b = np.zeros(5), np.zeros(5)
+    lib().orc_lsrk_coefficients(_p(a), _p(b))
+    return a, b

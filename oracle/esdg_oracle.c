@@ -1,0 +1,1056 @@
+/*
+ * Plain FP64 CPU oracle of the entropy-stable nodal DGSEM for the 2D shallow
+ * water equations with artificial viscosity and the positivity limiter
+ * (Wintermeyer, Winters, Gassner, Warburton, arXiv:1804.02221).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference the GPU library is checked against.  It shares no code, header,
+ * table or helper with the HIP path; only tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  Build: gcc -O2 -ffp-contract=off
+ * (no fast-math), no OpenMP.
+ *
+ * Every function follows the paper's equations in the paper's order and
+ * notation.  Where the printed formula is garbled or silent, the reading
+ * taken is stated at the spot (the full list is kept with the design notes).
+ *
+ * Conventions.  Arrays are [K][(N+1)^2], node p = i*(N+1)+j, i <-> xi,
+ * j <-> eta.  Local sides 0..3 are the paper's s=1..4: eta=-1, xi=+1,
+ * eta=+1, xi=-1.  Face node k runs along increasing xi (sides 0,2) or eta
+ * (sides 1,3).  nbr_elem/nbr_side/flip give the element and side sharing
+ * each side; flip=1 reverses the neighbour's face-node order.
+ *
+ * Parity status of each part is listed in the test suite; functions whose
+ * result no property of the paper fixes say so below ("parity unpinned").
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NMAX 16
+
+typedef struct {
+    double g;          /* gravitational constant                              */
+    double h_tol;      /* velocity cut-off height, section 6.1 (1e-4)         */
+    double eps0;       /* artificial-viscosity amplitude, appendix A          */
+    double sigma_min;  /* indicator thresholds, appendix A (reading A12)      */
+    double sigma_max;
+    double cfl;        /* advective CFL number                                */
+    double cfl_visc;   /* safety factor of the viscous time-step bound        */
+    int surface_flux;  /* 0 = entropy stable (ES), 1 = entropy conservative   */
+    int av_on;         /* artificial viscosity on                             */
+    int limiter_on;    /* positivity limiter on                               */
+    int integrator;    /* 0 = LSRK(5,4) 2N-storage, 1 = SSPRK(3,3)            */
+    int max_dt_retries;
+} orc_params;
+
+typedef struct {
+    int N;
+    int64_t K;
+    const double *x, *y;          /* nodal coordinates [K][np]             */
+    const int32_t *nbr_elem;      /* [K][4]                                */
+    const int8_t *nbr_side;       /* [K][4]                                */
+    const int8_t *flip;           /* [K][4]                                */
+} orc_mesh;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENEGMEAN = -5 };
+
+/* ------------------------------------------------------------------------ */
+/* Operators: LGL nodes and weights, derivative matrix, SBP matrices,        */
+/* Vandermonde (section 2.2 and appendix A)                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int N;
+    double xi[ORC_NMAX + 1], w[ORC_NMAX + 1];
+    double D[ORC_NMAX + 1][ORC_NMAX + 1];   /* D_ij = l_j'(xi_i)             */
+    double Dt[ORC_NMAX + 1][ORC_NMAX + 1];  /* D~ = 2D + S                   */
+    double Dh[ORC_NMAX + 1][ORC_NMAX + 1];  /* D^ = -M^{-1} D^T M            */
+    double Vinv[ORC_NMAX + 1][ORC_NMAX + 1];/* nodal -> orthonormal modal    */
+} orc_ops;
+
+/* Legendre polynomial L_n(x) and its derivative, three-term recurrence. */
+static void legendre(int n, long double x, long double *L, long double *dL)
+{
+    long double l0 = 1.0L, l1 = x;
+    if (n == 0) { *L = 1.0L; *dL = 0.0L; return; }
+    for (int k = 1; k < n; ++k) {
+        long double l2 = ((2 * k + 1) * x * l1 - k * l0) / (k + 1);
+        l0 = l1;
+        l1 = l2;
+    }
+    *L = l1;
+    /* (1 - x^2) L_n' = n (L_{n-1} - x L_n) */
+    if (fabsl(1.0L - x * x) > 0.0L)
+        *dL = n * (l0 - x * l1) / (1.0L - x * x);
+    else
+        *dL = (x > 0 ? 1.0L : ((n % 2) ? 1.0L : -1.0L)) * 0.5L * n * (n + 1);
+}
+
+static void lgl_nodes_weights(int N, double *xi, double *w)
+{
+    /* Nodes: -1, +1 and the roots of L_N' (Newton, long double).
+     * Weights: w_j = 2 / (N (N+1) L_N(xi_j)^2). */
+    long double X[ORC_NMAX + 1];
+    X[0] = -1.0L;
+    X[N] = 1.0L;
+    for (int j = 1; j < N; ++j) {
+        long double x = -cosl(3.14159265358979323846264338327950288L * j / N);
+        for (int it = 0; it < 100; ++it) {
+            long double L, dL;
+            legendre(N, x, &L, &dL);
+            /* Legendre ODE: (1-x^2) L'' = 2 x L' - N(N+1) L */
+            long double d2L = (2.0L * x * dL - (long double)N * (N + 1) * L) / (1.0L - x * x);
+            long double dx = dL / d2L;
+            x -= dx;
+            if (fabsl(dx) < 1e-30L) break;
+        }
+        X[j] = x;
+    }
+    for (int j = 0; j <= N; ++j) {
+        long double L, dL;
+        legendre(N, X[j], &L, &dL);
+        xi[j] = (double)X[j];
+        w[j] = (double)(2.0L / ((long double)N * (N + 1) * L * L));
+    }
+}
+
+static void gauss_nodes_weights(int n, long double *x, long double *w)
+{
+    /* n-point Legendre-Gauss rule: roots of L_n, w = 2/((1-x^2) L_n'(x)^2). */
+    for (int l = 0; l < n; ++l) {
+        long double t = -cosl(3.14159265358979323846264338327950288L * (l + 0.75L) / (n + 0.5L));
+        for (int it = 0; it < 100; ++it) {
+            long double L, dL;
+            legendre(n, t, &L, &dL);
+            long double dt = L / dL;
+            t -= dt;
+            if (fabsl(dt) < 1e-30L) break;
+        }
+        long double L, dL;
+        legendre(n, t, &L, &dL);
+        x[l] = t;
+        w[l] = 2.0L / ((1.0L - t * t) * dL * dL);
+    }
+}
+
+/* Lagrange basis l_j on the LGL nodes, evaluated at t (definition). */
+static long double lagrange(int N, const double *xi, int j, long double t)
+{
+    long double p = 1.0L;
+    for (int i = 0; i <= N; ++i)
+        if (i != j) p *= (t - xi[i]) / ((long double)xi[j] - xi[i]);
+    return p;
+}
+
+static void build_ops(int N, orc_ops *op)
+{
+    memset(op, 0, sizeof(*op));
+    op->N = N;
+    lgl_nodes_weights(N, op->xi, op->w);
+    /* D_ij = l_j'(xi_i) (eq. DmatDef), barycentric form; the diagonal makes
+     * every row sum to zero (derivative of a constant). */
+    long double lam[ORC_NMAX + 1];
+    for (int j = 0; j <= N; ++j) {
+        long double p = 1.0L;
+        for (int k = 0; k <= N; ++k)
+            if (k != j) p *= ((long double)op->xi[j] - op->xi[k]);
+        lam[j] = 1.0L / p;
+    }
+    for (int i = 0; i <= N; ++i) {
+        long double diag = 0.0L;
+        for (int j = 0; j <= N; ++j) {
+            if (j == i) continue;
+            long double d = (lam[j] / lam[i]) / ((long double)op->xi[i] - op->xi[j]);
+            op->D[i][j] = (double)d;
+            diag -= d;
+        }
+        op->D[i][i] = (double)diag;
+    }
+    /* S = diag(1/w_0, 0, ..., 0, -1/w_N); D~ = 2D + S (eq. Dmat_modification);
+     * D^ = -M^{-1} D^T M (reading: the printed -M^{-1} D M is not the
+     * matrix that satisfies D = -S + D^). */
+    for (int i = 0; i <= N; ++i)
+        for (int j = 0; j <= N; ++j) {
+            double S = 0.0;
+            if (i == j && i == 0) S = 1.0 / op->w[0];
+            if (i == j && i == N) S = -1.0 / op->w[N];
+            op->Dt[i][j] = 2.0 * op->D[i][j] + S;
+            op->Dh[i][j] = -(op->w[j] / op->w[i]) * op->D[j][i];
+        }
+    /* Vandermonde inverse by Gauss quadrature (appendix A, eq. Vandermonde):
+     * Vinv_ij = sum_l Lt_i(xg_l) l_j(xg_l) wg_l with Lt_i = sqrt(i+1/2) L_i.
+     * (Reading: the printed l_j(x^G_i) means the quadrature node x^G_l.) */
+    long double xg[ORC_NMAX + 1], wg[ORC_NMAX + 1];
+    gauss_nodes_weights(N + 1, xg, wg);
+    for (int i = 0; i <= N; ++i)
+        for (int j = 0; j <= N; ++j) {
+            long double s = 0.0L;
+            for (int l = 0; l <= N; ++l) {
+                long double Li, dLi;
+                legendre(i, xg[l], &Li, &dLi);
+                s += Li * lagrange(N, op->xi, j, xg[l]) * wg[l];
+            }
+            op->Vinv[i][j] = (double)(s * sqrtl(i + 0.5L));
+        }
+}
+
+int orc_operators(int N, double *xi, double *w, double *D, double *Dtilde,
+                  double *Dhat, double *Vinv)
+{
+    if (N < 1 || N > ORC_NMAX) return ORC_EINVAL;
+    orc_ops op;
+    build_ops(N, &op);
+    int n1 = N + 1;
+    for (int i = 0; i < n1; ++i) {
+        if (xi) xi[i] = op.xi[i];
+        if (w) w[i] = op.w[i];
+        for (int j = 0; j < n1; ++j) {
+            if (D) D[i * n1 + j] = op.D[i][j];
+            if (Dtilde) Dtilde[i * n1 + j] = op.Dt[i][j];
+            if (Dhat) Dhat[i * n1 + j] = op.Dh[i][j];
+            if (Vinv) Vinv[i * n1 + j] = op.Vinv[i][j];
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry (section 2.1): metric terms by the derivative matrix, Jacobian   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double *xxi, *xeta, *yxi, *yeta, *J;   /* [K][np] */
+} orc_geom;
+
+static int geom_alloc(orc_geom *G, int64_t n)
+{
+    G->xxi = malloc(sizeof(double) * n);
+    G->xeta = malloc(sizeof(double) * n);
+    G->yxi = malloc(sizeof(double) * n);
+    G->yeta = malloc(sizeof(double) * n);
+    G->J = malloc(sizeof(double) * n);
+    return (G->xxi && G->xeta && G->yxi && G->yeta && G->J) ? 0 : -1;
+}
+
+static void geom_free(orc_geom *G)
+{
+    free(G->xxi); free(G->xeta); free(G->yxi); free(G->yeta); free(G->J);
+}
+
+static void geometry(const orc_ops *op, const orc_mesh *m, orc_geom *G)
+{
+    int N = op->N, n1 = N + 1, np = n1 * n1;
+    for (int64_t e = 0; e < m->K; ++e) {
+        const double *x = m->x + e * np, *y = m->y + e * np;
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                double xx = 0, xe = 0, yx = 0, ye = 0;
+                for (int mm = 0; mm <= N; ++mm) {
+                    xx += op->D[i][mm] * x[mm * n1 + j];
+                    yx += op->D[i][mm] * y[mm * n1 + j];
+                    xe += op->D[j][mm] * x[i * n1 + mm];
+                    ye += op->D[j][mm] * y[i * n1 + mm];
+                }
+                int64_t q = e * np + i * n1 + j;
+                G->xxi[q] = xx; G->xeta[q] = xe; G->yxi[q] = yx; G->yeta[q] = ye;
+                G->J[q] = xx * ye - xe * yx;                 /* eq. JacobianDef */
+            }
+    }
+}
+
+int orc_geometry(int N, int64_t K, const double *x, const double *y, double *xxi,
+                 double *xeta, double *yxi, double *yeta, double *J)
+{
+    if (N < 1 || N > ORC_NMAX || K < 0) return ORC_EINVAL;
+    orc_ops op;
+    build_ops(N, &op);
+    orc_mesh m = {N, K, x, y, NULL, NULL, NULL};
+    orc_geom G = {xxi, xeta, yxi, yeta, J};
+    geometry(&op, &m, &G);
+    return ORC_OK;
+}
+
+/* Face node k of local side s -> local (i, j). */
+static void side_node(int N, int s, int k, int *i, int *j)
+{
+    switch (s) {
+    case 0: *i = k; *j = 0; break;
+    case 1: *i = N; *j = k; break;
+    case 2: *i = k; *j = N; break;
+    default: *i = 0; *j = k; break;
+    }
+}
+
+/* Outward scaled normal of side s at node q: the contravariant direction
+ * (+-xi or +-eta) written with the metric terms; its length is the surface
+ * Jacobian of eq. SurfJac. */
+static void scaled_normal(const orc_geom *G, int s, int64_t q, double *nx, double *ny)
+{
+    switch (s) {
+    case 0: *nx = G->yxi[q]; *ny = -G->xxi[q]; break;     /* eta = -1 */
+    case 1: *nx = G->yeta[q]; *ny = -G->xeta[q]; break;   /* xi  = +1 */
+    case 2: *nx = -G->yxi[q]; *ny = G->xxi[q]; break;     /* eta = +1 */
+    default: *nx = -G->yeta[q]; *ny = G->xeta[q]; break;  /* xi  = -1 */
+    }
+}
+
+/* The neighbour node matched to face node k of side s of element e. */
+static int64_t nbr_node(const orc_mesh *m, int64_t e, int s, int k)
+{
+    int N = m->N, n1 = N + 1, np = n1 * n1;
+    int64_t en = m->nbr_elem[e * 4 + s];
+    int sn = m->nbr_side[e * 4 + s];
+    int kk = m->flip[e * 4 + s] ? N - k : k;
+    int i, j;
+    side_node(N, sn, kk, &i, &j);
+    return en * np + i * n1 + j;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Point-wise fluxes                                                         */
+/* ------------------------------------------------------------------------ */
+/* Velocity with the dry cut-off of section 6.1: zero where h <= h_tol. */
+static double velocity(double hq, double h, double h_tol)
+{
+    return (h > h_tol) ? hq / h : 0.0;
+}
+
+/* Entropy-conservative two-point volume fluxes F#, G# (eq. volumeFluxes). */
+void orc_volume_flux(double g, double h_tol, const double *wa, const double *wb,
+                     double *Fs, double *Gs)
+{
+    double ha = wa[0], hb = wb[0];
+    double ua = velocity(wa[1], ha, h_tol), ub = velocity(wb[1], hb, h_tol);
+    double va = velocity(wa[2], ha, h_tol), vb = velocity(wb[2], hb, h_tol);
+    double avg_h = 0.5 * (ha + hb);
+    double avg_h2 = 0.5 * (ha * ha + hb * hb);
+    double avg_hu = 0.5 * (wa[1] + wb[1]);
+    double avg_hv = 0.5 * (wa[2] + wb[2]);
+    double avg_u = 0.5 * (ua + ub);
+    double avg_v = 0.5 * (va + vb);
+    double p = g * avg_h * avg_h - 0.5 * g * avg_h2;
+    Fs[0] = avg_hu;
+    Fs[1] = avg_hu * avg_u + p;
+    Fs[2] = avg_hu * avg_v;
+    Gs[0] = avg_hv;
+    Gs[1] = avg_hv * avg_u;
+    Gs[2] = avg_hv * avg_v + p;
+}
+
+/* Numerical interface flux in the direction of the unit normal n (pointing
+ * from the '-' state into the '+' state), evaluated in the rotated frame
+ * (appendix B, eqs. rotatingVelocities, surfaceFlux2DRotated,
+ * surfaceFlux2DCurved, RightEigenvectors2DCurved, ScalingMatrix2DCurved).
+ * Entropy-stable: the EC flux minus 1/2 R|Lambda|R^T [[q~]], evaluated as
+ * the matrix product; entropy-conservative: the first term only
+ * (eq. surfaceFluxes).  Reading: {c} is the mean of c = sqrt(g h). */
+void orc_surface_flux(const orc_params *P, const double *wm, double bm, const double *wp,
+                      double bp, double nx, double ny, double *F)
+{
+    double g = P->g;
+    double hm = wm[0], hp = wp[0];
+    double um = velocity(wm[1], hm, P->h_tol), vm = velocity(wm[2], hm, P->h_tol);
+    double up = velocity(wp[1], hp, P->h_tol), vp = velocity(wp[2], hp, P->h_tol);
+    /* rotate: u~ = n.u, v~ = t.u with t = (-ny, nx) */
+    double utm = nx * um + ny * vm, vtm = -ny * um + nx * vm;
+    double utp = nx * up + ny * vp, vtp = -ny * up + nx * vp;
+    double cm = sqrt(g * fmax(hm, 0.0)), cp = sqrt(g * fmax(hp, 0.0));
+    double ah = 0.5 * (hm + hp), au = 0.5 * (utm + utp), av = 0.5 * (vtm + vtp);
+    double ah2 = 0.5 * (hm * hm + hp * hp), ac = 0.5 * (cm + cp);
+    double Fr[3];
+    Fr[0] = ah * au;
+    Fr[1] = ah * au * au + 0.5 * g * ah2;
+    Fr[2] = ah * au * av;
+    if (P->surface_flux == 0) {
+        /* jump of the entropy variables q = (g(h+b) - (u^2+v^2)/2, u, v) */
+        double qm[3] = {g * (hm + bm) - 0.5 * (utm * utm + vtm * vtm), utm, vtm};
+        double qp[3] = {g * (hp + bp) - 0.5 * (utp * utp + vtp * vtp), utp, vtp};
+        double dq[3] = {qp[0] - qm[0], qp[1] - qm[1], qp[2] - qm[2]};
+        double R[3][3] = {{1.0, 0.0, 1.0},
+                          {au + ac, 0.0, au - ac},
+                          {av, 1.0, av}};
+        double Lam[3] = {fabs(au + ac) / (2.0 * g),
+                         2.0 * g * fabs(ah * au) / (2.0 * g),
+                         fabs(au - ac) / (2.0 * g)};
+        double RTdq[3], dis[3];
+        for (int a = 0; a < 3; ++a) {
+            RTdq[a] = 0.0;
+            for (int c = 0; c < 3; ++c) RTdq[a] += R[c][a] * dq[c];
+            RTdq[a] *= Lam[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            dis[a] = 0.0;
+            for (int c = 0; c < 3; ++c) dis[a] += R[a][c] * RTdq[c];
+            Fr[a] -= 0.5 * dis[a];
+        }
+    }
+    /* rotate back */
+    F[0] = Fr[0];
+    F[1] = nx * Fr[1] - ny * Fr[2];
+    F[2] = ny * Fr[1] + nx * Fr[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shock indicator and viscosity (appendix A)                                */
+/* ------------------------------------------------------------------------ */
+static double viscosity_of_element(const orc_params *P, const orc_ops *op, const double *h)
+{
+    int N = op->N, n1 = N + 1;
+    double hmax = -INFINITY;
+    for (int q = 0; q < n1 * n1; ++q) hmax = fmax(hmax, h[q]);
+    if (!(hmax > P->h_tol)) return 0.0;   /* dry element: no indicator (reading) */
+    /* Q^ = V^{-1} Q V^{-T}, Q = nodal water height (reading A12: Q = h) */
+    double T[ORC_NMAX + 1][ORC_NMAX + 1], Qh[ORC_NMAX + 1][ORC_NMAX + 1];
+    for (int a = 0; a <= N; ++a)
+        for (int j = 0; j <= N; ++j) {
+            double s = 0.0;
+            for (int i = 0; i <= N; ++i) s += op->Vinv[a][i] * h[i * n1 + j];
+            T[a][j] = s;
+        }
+    for (int a = 0; a <= N; ++a)
+        for (int c = 0; c <= N; ++c) {
+            double s = 0.0;
+            for (int j = 0; j <= N; ++j) s += T[a][j] * op->Vinv[c][j];
+            Qh[a][c] = s;
+        }
+    /* energy in the highest mode shell over all modes, and in the next shell
+     * over the modes up to N-1 (eq. sigmadof, simplified form) */
+    double topN = Qh[N][N] * Qh[N][N], all = 0.0;
+    for (int i = 0; i < N; ++i) topN += Qh[i][N] * Qh[i][N] + Qh[N][i] * Qh[N][i];
+    for (int a = 0; a <= N; ++a)
+        for (int c = 0; c <= N; ++c) all += Qh[a][c] * Qh[a][c];
+    double topM = Qh[N - 1][N - 1] * Qh[N - 1][N - 1], allM = 0.0;
+    for (int i = 0; i < N - 1; ++i)
+        topM += Qh[i][N - 1] * Qh[i][N - 1] + Qh[N - 1][i] * Qh[N - 1][i];
+    for (int a = 0; a < N; ++a)
+        for (int c = 0; c < N; ++c) allM += Qh[a][c] * Qh[a][c];
+    double r1 = all > 0 ? topN / all : 0.0;
+    double r2 = allM > 0 ? topM / allM : 0.0;
+    double rmax = fmax(r1, r2);
+    if (!(rmax > 0.0)) return 0.0;          /* sigma = -infinity */
+    double sigma = log10(rmax);
+    /* piecewise ramp; reading: the middle branch is sigma_min < sigma < sigma_max */
+    if (sigma <= P->sigma_min) return 0.0;
+    if (sigma >= P->sigma_max) return P->eps0;
+    double pi = 3.14159265358979323846;
+    double Delta = 1.0 + sin(pi * (sigma - 0.5 * (P->sigma_max + P->sigma_min)) /
+                             (P->sigma_max - P->sigma_min));
+    return 0.5 * P->eps0 * Delta;
+}
+
+int orc_indicator(const orc_params *P, int N, int64_t K, const double *h, double *eps)
+{
+    if (N < 1 || N > ORC_NMAX) return ORC_EINVAL;
+    orc_ops op;
+    build_ops(N, &op);
+    int np = (N + 1) * (N + 1);
+    for (int64_t e = 0; e < K; ++e) eps[e] = viscosity_of_element(P, &op, h + e * np);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side R = -(1/J)(L_xi + L_eta - S - L^v_xi - L^v_eta)           */
+/* (Lemma 1, eq. RKSSP operator, Theorem 1)                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double *Lvol[3];   /* optional [K][np]: L_xi + L_eta (volume + surface)  */
+    double *S[3];      /* optional: source S~                                */
+    double *Lv[3];     /* optional: L^v_xi + L^v_eta                         */
+    double *grad[4];   /* optional: U1, U2, V1, V2 (physical gradients)      */
+} orc_parts;
+
+/* need: NULL (all elements) or a [K] mask of elements whose R is wanted. */
+static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
+                    const orc_geom *G, const double *b, const double *h, const double *hu,
+                    const double *hv, double *Rh, double *Rhu, double *Rhv, double *eps_out,
+                    const uint8_t *need, orc_parts *parts)
+{
+    const int N = op->N, n1 = N + 1, np = n1 * n1;
+    const int64_t K = m->K, n = K * np;
+    const double g = P->g, htol = P->h_tol;
+    double *u = malloc(sizeof(double) * n), *v = malloc(sizeof(double) * n);
+    double *eps = calloc((size_t)K, sizeof(double));
+    uint8_t *needv = NULL;     /* elements whose viscous fluxes are needed */
+    double *Fv2 = NULL, *Fv3 = NULL, *Gv2 = NULL, *Gv3 = NULL;
+    if (!u || !v || !eps) { free(u); free(v); free(eps); return ORC_ENOMEM; }
+    for (int64_t q = 0; q < n; ++q) {
+        u[q] = velocity(hu[q], h[q], htol);
+        v[q] = velocity(hv[q], h[q], htol);
+    }
+    if (P->av_on) {
+        needv = calloc((size_t)K, 1);
+        Fv2 = calloc((size_t)n, sizeof(double));
+        Fv3 = calloc((size_t)n, sizeof(double));
+        Gv2 = calloc((size_t)n, sizeof(double));
+        Gv3 = calloc((size_t)n, sizeof(double));
+        if (!needv || !Fv2 || !Fv3 || !Gv2 || !Gv3) {
+            free(u); free(v); free(eps); free(needv);
+            free(Fv2); free(Fv3); free(Gv2); free(Gv3);
+            return ORC_ENOMEM;
+        }
+        for (int64_t e = 0; e < K; ++e) {
+            if (need && !need[e]) continue;
+            needv[e] = 1;
+            for (int s = 0; s < 4; ++s) needv[m->nbr_elem[e * 4 + s]] = 1;
+        }
+        /* viscosity per element from the stage state (appendix A) */
+        for (int64_t e = 0; e < K; ++e)
+            if (needv[e]) eps[e] = viscosity_of_element(P, op, h + e * np);
+        /* BR1 gradients of the gradient variables u, v (eq. BR1).  Readings:
+         * the printed formula lacks the division by J; the lifted reference
+         * derivative (D^ w)_i + (delta_iN W*_N - delta_i0 W*_0)/w_i enters the
+         * chain rule of eq. NablaRelation with the same metric signs as the
+         * volume part (the printed signs of the eta-surface term in U1/V1 and
+         * the xi-surface term in U2/V2 are inconsistent with it). */
+        for (int64_t e = 0; e < K; ++e) {
+            if (!needv[e]) continue;
+            double Us[4][ORC_NMAX + 1], Vs[4][ORC_NMAX + 1];   /* U* = {u} per side */
+            for (int s = 0; s < 4; ++s)
+                for (int k = 0; k <= N; ++k) {
+                    int i, j;
+                    side_node(N, s, k, &i, &j);
+                    int64_t q = e * np + i * n1 + j, qn = nbr_node(m, e, s, k);
+                    Us[s][k] = 0.5 * (u[q] + u[qn]);
+                    Vs[s][k] = 0.5 * (v[q] + v[qn]);
+                }
+            for (int i = 0; i <= N; ++i)
+                for (int j = 0; j <= N; ++j) {
+                    int64_t q = e * np + i * n1 + j;
+                    double dxu = 0, deu = 0, dxv = 0, dev = 0;
+                    for (int mm = 0; mm <= N; ++mm) {
+                        dxu += op->Dh[i][mm] * u[e * np + mm * n1 + j];
+                        dxv += op->Dh[i][mm] * v[e * np + mm * n1 + j];
+                        deu += op->Dh[j][mm] * u[e * np + i * n1 + mm];
+                        dev += op->Dh[j][mm] * v[e * np + i * n1 + mm];
+                    }
+                    /* xi-surface: (delta_iN U*_Nj - delta_i0 U*_0j)/w_i,
+                     * U*_Nj on side 1 (k=j), U*_0j on side 3 (k=j) */
+                    if (i == N) { dxu += Us[1][j] / op->w[i]; dxv += Vs[1][j] / op->w[i]; }
+                    if (i == 0) { dxu -= Us[3][j] / op->w[i]; dxv -= Vs[3][j] / op->w[i]; }
+                    /* eta-surface: U*_iN on side 2 (k=i), U*_i0 on side 0 */
+                    if (j == N) { deu += Us[2][i] / op->w[j]; dev += Vs[2][i] / op->w[j]; }
+                    if (j == 0) { deu -= Us[0][i] / op->w[j]; dev -= Vs[0][i] / op->w[j]; }
+                    double J = G->J[q];
+                    double U1 = (G->yeta[q] * dxu - G->yxi[q] * deu) / J;
+                    double U2 = (-G->xeta[q] * dxu + G->xxi[q] * deu) / J;
+                    double V1 = (G->yeta[q] * dxv - G->yxi[q] * dev) / J;
+                    double V2 = (-G->xeta[q] * dxv + G->xxi[q] * dev) / J;
+                    /* viscous fluxes f^v = h eps (0, U1, V1), g^v = h eps (0, U2, V2) */
+                    double he = h[q] * eps[e];
+                    Fv2[q] = he * U1; Fv3[q] = he * V1;
+                    Gv2[q] = he * U2; Gv3[q] = he * V2;
+                    if (parts && parts->grad[0]) {
+                        parts->grad[0][q] = U1; parts->grad[1][q] = U2;
+                        parts->grad[2][q] = V1; parts->grad[3][q] = V2;
+                    }
+                }
+        }
+    }
+    if (eps_out)
+        for (int64_t e = 0; e < K; ++e) eps_out[e] = eps[e];
+
+    for (int64_t e = 0; e < K; ++e) {
+        if (need && !need[e]) continue;
+        const int64_t o = e * np;
+        double L[3][(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+        double Sx[(ORC_NMAX + 1) * (ORC_NMAX + 1)], Sy[(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+        double Lv2[(ORC_NMAX + 1) * (ORC_NMAX + 1)], Lv3[(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+        /* --- volume: sum_m D~_im F~_(i,m),j + sum_m D~_jm G~_i,(j,m) (Lemma 1,
+         * eqs. fluxDiffFormF and Fmij).  Readings: G~ uses the metric
+         * averages {y_xi}, {x_xi} in the order of the contravariant flux
+         * g~ = -y_xi f + x_xi g (eq. ContravariantFluxes), and L_eta sums over
+         * D~_jm (the node's own row, as in eq. VolInt). */
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                int p = i * n1 + j;
+                double acc[3] = {0, 0, 0};
+                double wij[3] = {h[o + p], hu[o + p], hv[o + p]};
+                for (int mm = 0; mm <= N; ++mm) {
+                    int pm = mm * n1 + j;
+                    double wmj[3] = {h[o + pm], hu[o + pm], hv[o + pm]};
+                    double Fs[3], Gs[3];
+                    orc_volume_flux(g, htol, wij, wmj, Fs, Gs);
+                    double ay = 0.5 * (G->yeta[o + p] + G->yeta[o + pm]);
+                    double ax = 0.5 * (G->xeta[o + p] + G->xeta[o + pm]);
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += op->Dt[i][mm] * (Fs[c] * ay - Gs[c] * ax);
+                }
+                for (int mm = 0; mm <= N; ++mm) {
+                    int pm = i * n1 + mm;
+                    double wim[3] = {h[o + pm], hu[o + pm], hv[o + pm]};
+                    double Fs[3], Gs[3];
+                    orc_volume_flux(g, htol, wij, wim, Fs, Gs);
+                    double ay = 0.5 * (G->yxi[o + p] + G->yxi[o + pm]);
+                    double ax = 0.5 * (G->xxi[o + p] + G->xxi[o + pm]);
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += op->Dt[j][mm] * (-Fs[c] * ay + Gs[c] * ax);
+                }
+                for (int c = 0; c < 3; ++c) L[c][p] = acc[c];
+            }
+        /* --- interface: (1/w_i)(delta_iN F~*_Nj - delta_i0 F~*_0j) and the eta
+         * analogue (Lemma 1).  F~* is the contravariant numerical flux in the
+         * +xi (+eta) direction; it equals J^surf times the numerical flux
+         * along the element's outward unit normal on sides xi=+1 / eta=+1 and
+         * minus that on xi=-1 / eta=-1.  The element's own trace is the '-'
+         * state (the normal points from '-' to '+'). */
+        for (int s = 0; s < 4; ++s)
+            for (int k = 0; k <= N; ++k) {
+                int i, j;
+                side_node(N, s, k, &i, &j);
+                int p = i * n1 + j;
+                int64_t q = o + p, qn = nbr_node(m, e, s, k);
+                double snx, sny;
+                scaled_normal(G, s, q, &snx, &sny);
+                double Js = sqrt(snx * snx + sny * sny);   /* eq. SurfJac */
+                double wm[3] = {h[q], hu[q], hv[q]}, wp[3] = {h[qn], hu[qn], hv[qn]};
+                double Fn[3];
+                orc_surface_flux(P, wm, b[q], wp, b[qn], snx / Js, sny / Js, Fn);
+                for (int c = 0; c < 3; ++c) {
+                    double Fcontra = (s == 1 || s == 2) ? Js * Fn[c] : -Js * Fn[c];
+                    if (s == 1) L[c][p] += Fcontra / op->w[N];   /* + F~*_Nj / w_N */
+                    if (s == 3) L[c][p] -= Fcontra / op->w[0];   /* - F~*_0j / w_0 */
+                    if (s == 2) L[c][p] += Fcontra / op->w[N];   /* + G~*_iN / w_N */
+                    if (s == 0) L[c][p] -= Fcontra / op->w[0];   /* - G~*_i0 / w_0 */
+                }
+            }
+        /* --- source (eq. SourceDisc) with S^{.,*} = 0 (continuous b) and the
+         * split-form bathymetry derivatives.  Readings: the split derivative
+         * carries D (the printed 2D doubles it: lake at rest then fails), and
+         * b_y follows the chain rule J b_y = -x_eta b_xi + x_xi b_eta. */
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                int p = i * n1 + j;
+                double Db_xi = 0, Dyb_xi = 0, Dxb_xi = 0, Db_eta = 0, Dyb_eta = 0, Dxb_eta = 0;
+                for (int mm = 0; mm <= N; ++mm) {
+                    int pa = mm * n1 + j, pb = i * n1 + mm;
+                    Db_xi += op->D[i][mm] * b[o + pa];
+                    Dyb_xi += op->D[i][mm] * (G->yeta[o + pa] * b[o + pa]);
+                    Dxb_xi += op->D[i][mm] * (G->xeta[o + pa] * b[o + pa]);
+                    Db_eta += op->D[j][mm] * b[o + pb];
+                    Dyb_eta += op->D[j][mm] * (G->yxi[o + pb] * b[o + pb]);
+                    Dxb_eta += op->D[j][mm] * (G->xxi[o + pb] * b[o + pb]);
+                }
+                double bx = G->yeta[o + p] * Db_xi + Dyb_xi - G->yxi[o + p] * Db_eta - Dyb_eta;
+                double by = -G->xeta[o + p] * Db_xi - Dxb_xi + G->xxi[o + p] * Db_eta + Dxb_eta;
+                Sx[p] = 0.5 * g * (-h[o + p] * bx);
+                Sy[p] = 0.5 * g * (-h[o + p] * by);
+            }
+        /* --- viscous divergence (Theorem 1, eq. ViscTermsDisc) on the
+         * momentum rows: D applied to the contravariant viscous fluxes plus
+         * (F~v* - F~v)/w at the faces, F~v* = {F~v}.  Reading: the interface
+         * average is the mean of both sides' physical viscous fluxes at the
+         * shared node, contracted with this element's metric terms. */
+        for (int p = 0; p < np; ++p) { Lv2[p] = 0.0; Lv3[p] = 0.0; }
+        if (P->av_on) {
+            for (int i = 0; i <= N; ++i)
+                for (int j = 0; j <= N; ++j) {
+                    int p = i * n1 + j;
+                    double a2 = 0, a3 = 0;
+                    for (int mm = 0; mm <= N; ++mm) {
+                        int64_t qa = o + mm * n1 + j, qb = o + i * n1 + mm;
+                        double Ft2 = G->yeta[qa] * Fv2[qa] - G->xeta[qa] * Gv2[qa];
+                        double Ft3 = G->yeta[qa] * Fv3[qa] - G->xeta[qa] * Gv3[qa];
+                        double Gt2 = -G->yxi[qb] * Fv2[qb] + G->xxi[qb] * Gv2[qb];
+                        double Gt3 = -G->yxi[qb] * Fv3[qb] + G->xxi[qb] * Gv3[qb];
+                        a2 += op->D[i][mm] * Ft2 + op->D[j][mm] * Gt2;
+                        a3 += op->D[i][mm] * Ft3 + op->D[j][mm] * Gt3;
+                    }
+                    Lv2[p] = a2;
+                    Lv3[p] = a3;
+                }
+            for (int s = 0; s < 4; ++s)
+                for (int k = 0; k <= N; ++k) {
+                    int i, j;
+                    side_node(N, s, k, &i, &j);
+                    int p = i * n1 + j;
+                    int64_t q = o + p, qn = nbr_node(m, e, s, k);
+                    double f2a = 0.5 * (Fv2[q] + Fv2[qn]), f3a = 0.5 * (Fv3[q] + Fv3[qn]);
+                    double g2a = 0.5 * (Gv2[q] + Gv2[qn]), g3a = 0.5 * (Gv3[q] + Gv3[qn]);
+                    double t2s, t3s, t2, t3;   /* contravariant fluxes (+xi or +eta) */
+                    if (s == 1 || s == 3) {
+                        t2s = G->yeta[q] * f2a - G->xeta[q] * g2a;
+                        t3s = G->yeta[q] * f3a - G->xeta[q] * g3a;
+                        t2 = G->yeta[q] * Fv2[q] - G->xeta[q] * Gv2[q];
+                        t3 = G->yeta[q] * Fv3[q] - G->xeta[q] * Gv3[q];
+                    } else {
+                        t2s = -G->yxi[q] * f2a + G->xxi[q] * g2a;
+                        t3s = -G->yxi[q] * f3a + G->xxi[q] * g3a;
+                        t2 = -G->yxi[q] * Fv2[q] + G->xxi[q] * Gv2[q];
+                        t3 = -G->yxi[q] * Fv3[q] + G->xxi[q] * Gv3[q];
+                    }
+                    double sg = (s == 1 || s == 2) ? 1.0 : -1.0;   /* delta_N - delta_0 */
+                    double wgt = (s == 1 || s == 2) ? op->w[N] : op->w[0];
+                    Lv2[p] += sg * (t2s - t2) / wgt;
+                    Lv3[p] += sg * (t3s - t3) / wgt;
+                }
+        }
+        /* --- R = -(1/J)(L_xi + L_eta - S) + (1/J) L^v */
+        for (int p = 0; p < np; ++p) {
+            double J = G->J[o + p];
+            Rh[o + p] = -(L[0][p]) / J;
+            Rhu[o + p] = -(L[1][p] - Sx[p] - Lv2[p]) / J;
+            Rhv[o + p] = -(L[2][p] - Sy[p] - Lv3[p]) / J;
+            if (parts) {
+                for (int c = 0; c < 3; ++c)
+                    if (parts->Lvol[c]) parts->Lvol[c][o + p] = L[c][p];
+                if (parts->S[0]) { parts->S[0][o + p] = 0.0; parts->S[1][o + p] = Sx[p]; parts->S[2][o + p] = Sy[p]; }
+                if (parts->Lv[0]) { parts->Lv[0][o + p] = 0.0; parts->Lv[1][o + p] = Lv2[p]; parts->Lv[2][o + p] = Lv3[p]; }
+            }
+        }
+    }
+    free(u); free(v); free(eps); free(needv);
+    free(Fv2); free(Fv3); free(Gv2); free(Gv3);
+    return ORC_OK;
+}
+
+static int check_mesh(const orc_mesh *m)
+{
+    if (!m || m->N < 1 || m->N > ORC_NMAX || m->K < 1 || !m->x || !m->y || !m->nbr_elem ||
+        !m->nbr_side || !m->flip)
+        return ORC_EINVAL;
+    for (int64_t e = 0; e < m->K; ++e)
+        for (int s = 0; s < 4; ++s) {
+            int32_t en = m->nbr_elem[e * 4 + s];
+            int sn = m->nbr_side[e * 4 + s];
+            if (en < 0 || en >= m->K || sn < 0 || sn > 3) return ORC_EINVAL;
+        }
+    return ORC_OK;
+}
+
+int orc_rhs(const orc_params *P, const orc_mesh *m, const double *b, const double *h,
+            const double *hu, const double *hv, double *Rh, double *Rhu, double *Rhv,
+            double *eps_out, const uint8_t *need, orc_parts *parts)
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    orc_ops op;
+    build_ops(m->N, &op);
+    orc_geom G;
+    int64_t n = m->K * (int64_t)(m->N + 1) * (m->N + 1);
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    st = rhs_impl(P, &op, m, &G, b, h, hu, hv, Rh, Rhu, Rhv, eps_out, need, parts);
+    geom_free(&G);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Positivity limiter (eq. PosPres) with the velocity cut-off of 6.1         */
+/* ------------------------------------------------------------------------ */
+static int limit_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
+                      const orc_geom *G, double *h, double *hu, double *hv, int64_t *n_limited)
+{
+    const int N = op->N, n1 = N + 1, np = n1 * n1;
+    int status = ORC_OK;
+    int64_t nl = 0;
+    for (int64_t e = 0; e < m->K; ++e) {
+        const int64_t o = e * np;
+        /* Jacobian-weighted element means and the minimum (eq. AverageTerm) */
+        double area = 0, mh = 0, mhu = 0, mhv = 0, hmin = INFINITY;
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                int64_t q = o + i * n1 + j;
+                double wq = G->J[q] * op->w[i] * op->w[j];
+                area += wq;
+                mh += h[q] * wq;
+                mhu += hu[q] * wq;
+                mhv += hv[q] * wq;
+                hmin = fmin(hmin, h[q]);
+            }
+        mh /= area; mhu /= area; mhv /= area;
+        /* theta = min(1, hbar/(hbar - m)); reading: theta = 1 whenever m >= 0
+         * (no division at m = hbar), theta = 0 and an error flag if hbar < 0. */
+        double theta = 1.0;
+        if (hmin < 0.0) {
+            if (mh < 0.0) { theta = 0.0; status = ORC_ENEGMEAN; }
+            else theta = fmin(1.0, mh / (mh - hmin));
+            ++nl;
+        }
+        for (int p = 0; p < np; ++p) {
+            int64_t q = o + p;
+            if (theta != 1.0) {
+                h[q] = theta * (h[q] - mh) + mh;
+                hu[q] = theta * (hu[q] - mhu) + mhu;
+                hv[q] = theta * (hv[q] - mhv) + mhv;
+            }
+            /* velocities (hence discharges) set to zero below h_tol */
+            if (h[q] < P->h_tol) { hu[q] = 0.0; hv[q] = 0.0; }
+        }
+    }
+    if (n_limited) *n_limited = nl;
+    return status;
+}
+
+int orc_limit(const orc_params *P, const orc_mesh *m, double *h, double *hu, double *hv,
+              int64_t *n_limited)
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    orc_ops op;
+    build_ops(m->N, &op);
+    orc_geom G;
+    int64_t n = m->K * (int64_t)(m->N + 1) * (m->N + 1);
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    st = limit_impl(P, &op, m, &G, h, hu, hv, n_limited);
+    geom_free(&G);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step: advective CFL, viscous bound, Lemma 2 positivity bounds        */
+/* ------------------------------------------------------------------------ */
+/* Spectral radius of the 1D BR1 operator at dx = 1, eps = 1, per N (derived
+ * numerically for N = 2..8; parity unpinned by the paper), and the real-axis
+ * stability limit of LSRK(5,4). */
+static const double ORC_BR1_RADIUS[9] = {0, 0, 25.6, 82.9, 203.0, 425.0, 800.0, 1383.0, 2244.0};
+static const double ORC_LSRK_REAL_LIMIT = 4.6;
+
+static void dt_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
+                    const orc_geom *G, const double *b, const double *h, const double *hu,
+                    const double *hv, double out[4])
+{
+    const int N = op->N, n1 = N + 1, np = n1 * n1;
+    const double g = P->g, htol = P->h_tol;
+    double dt_cfl = INFINITY, dt_visc = INFINITY, dt_pos = INFINITY;
+    (void)b;
+    for (int64_t e = 0; e < m->K; ++e) {
+        const int64_t o = e * np;
+        double gmax = 0.0;
+        for (int p = 0; p < np; ++p) {
+            int64_t q = o + p;
+            double u = velocity(hu[q], h[q], htol), v = velocity(hv[q], h[q], htol);
+            double c = sqrt(g * fmax(h[q], 0.0));
+            double lx = fabs(G->yeta[q] * u - G->xeta[q] * v) +
+                        c * sqrt(G->yeta[q] * G->yeta[q] + G->xeta[q] * G->xeta[q]);
+            double le = fabs(-G->yxi[q] * u + G->xxi[q] * v) +
+                        c * sqrt(G->yxi[q] * G->yxi[q] + G->xxi[q] * G->xxi[q]);
+            if (lx + le > 0.0)
+                dt_cfl = fmin(dt_cfl, P->cfl * (2.0 / n1) * G->J[q] / (lx + le));
+            double J2 = G->J[q] * G->J[q];
+            double gg = (G->yeta[q] * G->yeta[q] + G->xeta[q] * G->xeta[q] +
+                         G->yxi[q] * G->yxi[q] + G->xxi[q] * G->xxi[q]) / J2;
+            gmax = fmax(gmax, gg);
+        }
+        if (P->av_on) {
+            double eps = viscosity_of_element(P, op, h + o);
+            if (eps > 0.0 && N >= 2 && N <= 8)
+                dt_visc = fmin(dt_visc, P->cfl_visc * 4.0 * ORC_LSRK_REAL_LIMIT /
+                                            (ORC_BR1_RADIUS[N] * eps * gmax));
+        }
+        /* Lemma 2 (eq. CFLConstraints), at every face node of every side,
+         * own trace '-', neighbour '+', own outward unit normal, a = J/J^surf,
+         * w_0 = 2/(N(N+1)) (reading: the printed N(N-1)/2 is not the LGL
+         * end weight). */
+        for (int s = 0; s < 4; ++s)
+            for (int k = 0; k <= N; ++k) {
+                int i, j;
+                side_node(N, s, k, &i, &j);
+                int64_t q = o + i * n1 + j, qn = nbr_node(m, e, s, k);
+                double snx, sny;
+                scaled_normal(G, s, q, &snx, &sny);
+                double Js = sqrt(snx * snx + sny * sny);
+                double nx = snx / Js, ny = sny / Js;
+                double a = G->J[q] / Js;
+                double hm = h[q], hp = h[qn];
+                double utm = nx * velocity(hu[q], hm, htol) + ny * velocity(hv[q], hm, htol);
+                double utp = nx * velocity(hu[qn], hp, htol) + ny * velocity(hv[qn], hp, htol);
+                double cm = sqrt(g * fmax(hm, 0.0)), cp = sqrt(g * fmax(hp, 0.0));
+                double au = 0.5 * (utm + utp), ac = 0.5 * (cm + cp);
+                double A = fabs(au + ac) + fabs(au - ac);
+                double B = fabs(au + ac) - fabs(au - ac);
+                double w0 = op->w[0];
+                if (A + 2.0 * au > 0.0) dt_pos = fmin(dt_pos, w0 * a / (A + 2.0 * au));
+                double den = ac * B * (utp - utm);
+                if (hm > 0.0 && den < 0.0) dt_pos = fmin(dt_pos, fabs(w0 * a * g * hm / den));
+            }
+    }
+    double dt = fmin(dt_cfl, dt_visc);
+    if (P->limiter_on) dt = fmin(dt, dt_pos);
+    out[0] = dt; out[1] = dt_cfl; out[2] = dt_visc; out[3] = dt_pos;
+}
+
+int orc_dt(const orc_params *P, const orc_mesh *m, const double *b, const double *h,
+           const double *hu, const double *hv, double out[4])
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    orc_ops op;
+    build_ops(m->N, &op);
+    orc_geom G;
+    int64_t n = m->K * (int64_t)(m->N + 1) * (m->N + 1);
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    dt_impl(P, &op, m, &G, b, h, hu, hv, out);
+    geom_free(&G);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time integration                                                          */
+/* ------------------------------------------------------------------------ */
+/* Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage RK, the
+ * low-storage scheme of the paper's earlier work (section 2.3). */
+static const double LSRK_A[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                                 -2404267990393.0 / 2016746695238.0,
+                                 -3550918686646.0 / 2091501179385.0,
+                                 -1275806237668.0 / 842570457699.0};
+static const double LSRK_B[5] = {1432997174477.0 / 9575080441755.0,
+                                 5161836677717.0 / 13612068292357.0,
+                                 1720146321549.0 / 2090206949498.0,
+                                 3134564353537.0 / 4481467310338.0,
+                                 2277821191437.0 / 14882151754819.0};
+
+int orc_lsrk_coefficients(double *a, double *b)
+{
+    for (int k = 0; k < 5; ++k) { a[k] = LSRK_A[k]; b[k] = LSRK_B[k]; }
+    return ORC_OK;
+}
+
+/* One step of size dt from W (in place); returns ORC_ENEGMEAN if a limiter
+ * call met a negative element mean. */
+static int one_step(const orc_params *P, const orc_ops *op, const orc_mesh *m,
+                    const orc_geom *G, const double *b, double *h, double *hu, double *hv,
+                    double dt, double *work)
+{
+    const int64_t n = m->K * (int64_t)(op->N + 1) * (op->N + 1);
+    double *R0 = work, *R1 = work + n, *R2 = work + 2 * n;
+    int status = ORC_OK, st;
+    if (P->integrator == 0) {
+        double *d0 = work + 3 * n, *d1 = work + 4 * n, *d2 = work + 5 * n;
+        for (int64_t q = 0; q < n; ++q) { d0[q] = 0; d1[q] = 0; d2[q] = 0; }
+        for (int k = 0; k < 5; ++k) {
+            st = rhs_impl(P, op, m, G, b, h, hu, hv, R0, R1, R2, NULL, NULL, NULL);
+            if (st) return st;
+            for (int64_t q = 0; q < n; ++q) {
+                d0[q] = LSRK_A[k] * d0[q] + dt * R0[q];
+                d1[q] = LSRK_A[k] * d1[q] + dt * R1[q];
+                d2[q] = LSRK_A[k] * d2[q] + dt * R2[q];
+                h[q] += LSRK_B[k] * d0[q];
+                hu[q] += LSRK_B[k] * d1[q];
+                hv[q] += LSRK_B[k] * d2[q];
+            }
+            if (P->limiter_on) {
+                st = limit_impl(P, op, m, G, h, hu, hv, NULL);
+                if (st) status = st;
+            }
+        }
+    } else {
+        /* SSPRK(3,3) in the Shu-Osher form of eq. RKSSP */
+        double *W0 = work + 3 * n, *W1 = work + 4 * n, *W2 = work + 5 * n;
+        for (int64_t q = 0; q < n; ++q) { W0[q] = h[q]; W1[q] = hu[q]; W2[q] = hv[q]; }
+        static const double alpha[3] = {0.0, 0.75, 1.0 / 3.0};
+        static const double beta[3] = {1.0, 0.25, 2.0 / 3.0};
+        for (int k = 0; k < 3; ++k) {
+            st = rhs_impl(P, op, m, G, b, h, hu, hv, R0, R1, R2, NULL, NULL, NULL);
+            if (st) return st;
+            for (int64_t q = 0; q < n; ++q) {
+                h[q] = alpha[k] * W0[q] + beta[k] * (h[q] + dt * R0[q]);
+                hu[q] = alpha[k] * W1[q] + beta[k] * (hu[q] + dt * R1[q]);
+                hv[q] = alpha[k] * W2[q] + beta[k] * (hv[q] + dt * R2[q]);
+            }
+            if (P->limiter_on) {
+                st = limit_impl(P, op, m, G, h, hu, hv, NULL);
+                if (st) status = st;
+            }
+        }
+    }
+    return status;
+}
+
+/* nsteps steps; dt_fixed > 0 gives a fixed step, otherwise the step is
+ * min(CFL, viscous, positivity) bound evaluated at the start of each step.
+ * A negative element mean in the limiter restarts the step from W^n with
+ * half the step, at most max_dt_retries times (reading of "adjust it
+ * accordingly", section 6).  t (in/out) accumulates the time. */
+int orc_step(const orc_params *P, const orc_mesh *m, const double *b, double *h, double *hu,
+             double *hv, int nsteps, double dt_fixed, double *t, double *last_dt)
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    orc_ops op;
+    build_ops(m->N, &op);
+    orc_geom G;
+    int64_t n = m->K * (int64_t)(m->N + 1) * (m->N + 1);
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    double *work = malloc(sizeof(double) * 9 * n);
+    if (!work) { geom_free(&G); return ORC_ENOMEM; }
+    double *s0 = work + 6 * n, *s1 = work + 7 * n, *s2 = work + 8 * n;
+    int status = ORC_OK;
+    for (int it = 0; it < nsteps; ++it) {
+        double dt = dt_fixed;
+        if (!(dt > 0.0)) {
+            double o4[4];
+            dt_impl(P, &op, m, &G, b, h, hu, hv, o4);
+            dt = o4[0];
+        }
+        memcpy(s0, h, sizeof(double) * n);
+        memcpy(s1, hu, sizeof(double) * n);
+        memcpy(s2, hv, sizeof(double) * n);
+        int tries = 0;
+        for (;;) {
+            st = one_step(P, &op, m, &G, b, h, hu, hv, dt, work);
+            if (st == ORC_ENEGMEAN && tries < P->max_dt_retries) {
+                memcpy(h, s0, sizeof(double) * n);
+                memcpy(hu, s1, sizeof(double) * n);
+                memcpy(hv, s2, sizeof(double) * n);
+                dt *= 0.5;
+                ++tries;
+                continue;
+            }
+            break;
+        }
+        if (t) *t += dt;
+        if (last_dt) *last_dt = dt;
+        if (st) { status = st; if (st != ORC_ENEGMEAN) break; }
+    }
+    free(work);
+    geom_free(&G);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics: mass, momentum, total energy (the entropy, eq.               */
+/* entropyFunction) and its semi-discrete rate sum J w w q.R                 */
+/* ------------------------------------------------------------------------ */
+int orc_diagnostics(const orc_params *P, const orc_mesh *m, const double *b, const double *h,
+                    const double *hu, const double *hv, double out[8])
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    orc_ops op;
+    build_ops(m->N, &op);
+    orc_geom G;
+    const int N = m->N, n1 = N + 1, np = n1 * n1;
+    int64_t n = m->K * (int64_t)np;
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    double *R = malloc(sizeof(double) * 3 * n);
+    if (!R) { geom_free(&G); return ORC_ENOMEM; }
+    st = rhs_impl(P, &op, m, &G, b, h, hu, hv, R, R + n, R + 2 * n, NULL, NULL, NULL);
+    double mass = 0, mx = 0, my = 0, E = 0, dE = 0, hmin = INFINITY, hmax = -INFINITY;
+    int64_t ndry = 0;
+    for (int64_t e = 0; e < m->K; ++e)
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                int64_t q = e * np + i * n1 + j;
+                double wq = G.J[q] * op.w[i] * op.w[j];
+                double u = velocity(hu[q], h[q], P->h_tol), v = velocity(hv[q], h[q], P->h_tol);
+                double ent = 0.5 * h[q] * (u * u + v * v) + 0.5 * P->g * h[q] * h[q] +
+                             P->g * h[q] * b[q];
+                double q1 = P->g * (h[q] + b[q]) - 0.5 * (u * u + v * v);
+                mass += wq * h[q];
+                mx += wq * hu[q];
+                my += wq * hv[q];
+                E += wq * ent;
+                dE += wq * (q1 * R[q] + u * R[n + q] + v * R[2 * n + q]);
+                hmin = fmin(hmin, h[q]);
+                hmax = fmax(hmax, h[q]);
+                if (!(h[q] > P->h_tol)) ++ndry;
+            }
+    out[0] = mass; out[1] = mx; out[2] = my; out[3] = E; out[4] = dE;
+    out[5] = hmin; out[6] = hmax; out[7] = (double)ndry;
+    free(R);
+    geom_free(&G);
+    return st;
+}
