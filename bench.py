@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the entropy-stable DGSEM shallow-water step on one
+MI355X.
+
+Workload (default): 512 x 512 curvilinear periodic elements on [0,10]^2
+(sin-perturbed map), N = 7 (16.8M LGL nodes), smooth random Fourier state
+(h in [0.5,2], |u|,|v| < 0.5, b in [0,1]), full hot path: artificial
+viscosity (indicator + BR1), split-form volume term, ES interface flux,
+source, LSRK(5,4) stage update with the positivity limiter, adaptive time
+step (CFL + viscous + Lemma 2 bounds) computed on the device every step.
+
+Prints ONE JSON line.  value = DOF-updates per second per RK stage
+(one DOF = one LGL node with its three unknowns) over the timed steps.
+roofline: the fused stage kernel, its algorithmic HBM bytes per launch
+divided by its mean launch time (HIP events on the solver stream), against
+the 8 TB/s HBM peak.  cpu_baseline: the CPU oracle, one full step on a
+256 x 256-element patch of the same recipe, single thread.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per RK stage (FP64) at N=3..8 + % FP64 roofline; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int) -> float:
+    """Algorithmic HBM bytes of one launch of the fused stage kernel: every
+    datum the stage must read or write, counted once.
+    Reads: W (3/node), dU (3/node, not on the first LSRK stage), metric
+    directions (4/node), split bathymetry derivatives (2/node), face
+    bathymetry (4(N+1)/element), with AV the element viscosity (1/element) and
+    the viscous face fluxes (16(N+1)/element).  Writes: W (3/node), dU (3/node)."""
+    nf = N + 1
+    n = K * nf * nf
+    per_node = 3 + (3 if stage_index > 0 else 0) + 4 + 2 + 3 + 3
+    per_elem = 4 * nf + ((1 + 16 * nf) if av else 0)
+    return (per_node * n + per_elem * K) * real_bytes
+
+
+def av_bytes(N: int, K: int, real_bytes: int) -> float:
+    """Algorithmic bytes of the viscosity kernel: W (3/node), the four metric
+    directions on the face nodes (16(N+1)/element); writes the viscosity
+    (1/element) and the viscous face fluxes (16(N+1)/element)."""
+    nf = N + 1
+    return (3 * K * nf * nf + 16 * nf * K + K + 16 * nf * K) * real_bytes
+
+
+def cpu_baseline(N: int, n_patch: int):
+    import oracle
+    from paper_1804_02221_amd.inputs import smooth_sweep
+    w = smooth_sweep(n_patch, N, seed=3)
+    P = oracle.params(N, av_on=1, limiter_on=1, eps0=0.025)
+    t0 = time.perf_counter()
+    oracle.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
+    el = time.perf_counter() - t0
+    nodes = w.mesh.K * (N + 1) ** 2
+    return dict(value=nodes * 5 / el, unit="DOF-updates/s", cores=1, kind="oracle",
+                sample=f"one LSRK(5,4) step (5 stages, AV + limiter + adaptive dt) on a "
+                       f"{n_patch}x{n_patch}-element patch of the same recipe, N={N} "
+                       f"({nodes} nodes), single thread, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=7)
+    ap.add_argument("--n", type=int, default=512, help="elements per side")
+    ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
+    ap.add_argument("--no-av", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-patch", type=int, default=256)
+    ap.add_argument("--sweep", default="", help="comma list of extra N values to time (same mesh)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the halo-exchange design for several GPUs is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from paper_1804_02221_amd import esdg
+    from paper_1804_02221_amd.inputs import smooth_sweep
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    dev = torch.cuda.current_device()
+    stream = torch.cuda.current_stream()
+
+    def run(N):
+        log(f"generating {args.n}x{args.n} workload at N={N}")
+        w = smooth_sweep(args.n, N, seed=3)
+        s = esdg.Solver(dev, args.precision, stream=stream)
+        s.upload_mesh(w.mesh)
+        P = esdg.default_params(N, av_on=0 if args.no_av else 1, limiter_on=1, eps0=0.025)
+        s.set_params(P)
+        s.set_bathymetry(w.b)
+        s.set_state(w.h, w.hu, w.hv)
+        K = w.mesh.K
+        nodes = K * (N + 1) ** 2
+        log(f"uploaded K={K} nodes={nodes}; warmup {args.warmup} steps")
+        s.step(args.warmup, 0.0)
+        torch.cuda.synchronize()
+        s.profile(True)
+        s.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_sim, _ = s.step(args.steps, 0.0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = s.profile_read()
+        s.profile(False)
+        d = s.diagnostics()
+        log(f"N={N}: {args.steps} steps in {el:.3f} s, t={t_sim:.4g}, min h={d[5]:.3g}")
+        rb = 8 if args.precision == 64 else 4
+        av = not args.no_av
+        per_step = sum(stage_bytes(N, K, av, rb, k) for k in range(5))
+        stage_total = per_step * args.steps
+        stage_launch = prof["stage_launches"]
+        stage_mean_ms = prof["stage_ms"] / max(stage_launch, 1)
+        achieved = stage_total / (prof["stage_ms"] * 1e-3) / 1e9
+        res = dict(N=N, K=K, nodes=nodes, elapsed=el, t_sim=t_sim,
+                   value=nodes * 5 * args.steps / el,
+                   ms_per_step=el * 1e3 / args.steps,
+                   stage_mean_ms=stage_mean_ms, stage_launches=stage_launch,
+                   stage_bytes_per_launch=per_step / 5,
+                   stage_GBs=achieved,
+                   av_mean_ms=prof["av_ms"] / max(prof["av_launches"], 1),
+                   av_GBs=(av_bytes(N, K, rb) * prof["av_launches"]) / max(prof["av_ms"] * 1e-3, 1e-12) / 1e9
+                   if av else None)
+        s.close()
+        del w
+        return res
+
+    main_res = run(args.N)
+    sweep = []
+    for tok in [t for t in args.sweep.split(",") if t.strip()]:
+        r = run(int(tok))
+        sweep.append({k: r[k] for k in ("N", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs")})
+
+    cpu = None
+    if rank == 0 and not args.no_cpu_baseline:
+        log(f"CPU oracle baseline on a {args.cpu_patch}^2 patch")
+        cpu = cpu_baseline(args.N, args.cpu_patch)
+
+    frac = main_res["stage_GBs"] / HBM_PEAK_GBS
+    out = {
+        "metric": METRIC,
+        "value": main_res["value"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 64 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"smooth random Fourier state on {args.n}x{args.n} curvilinear periodic "
+                         f"elements of [0,10]^2, N={args.N}, {'AV + ' if not args.no_av else ''}"
+                         f"limiter, ES flux, LSRK(5,4), adaptive dt"),
+            "N": args.N, "elements": main_res["K"], "nodes": main_res["nodes"],
+            "stages_per_step": 5, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": main_res["stage_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": frac, "traffic": None, "kernel": "stage_kernel",
+            "bytes_per_launch": main_res["stage_bytes_per_launch"],
+            "mean_launch_ms": main_res["stage_mean_ms"],
+        },
+        "cpu_baseline": cpu,
+        "av_kernel": {"mean_launch_ms": main_res["av_mean_ms"], "GBs": main_res["av_GBs"]},
+    }
+    if sweep:
+        out["sweep"] = sweep
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * esdg.h -- C ABI of the MI355X (gfx950) entropy-stable DGSEM solver for the
+ * two-dimensional shallow water equations on curvilinear quadrilateral
+ * meshes with wet/dry fronts (Wintermeyer, Winters, Gassner, Warburton,
+ * "An entropy stable discontinuous Galerkin method for the shallow water
+ * equations on curvilinear meshes with wet/dry fronts accelerated by GPUs",
+ * arXiv:1804.02221).
+ *
+ * The library evaluates the semi-discrete operator of Lemma 1 extended by
+ * the artificial-viscosity terms of Theorem 1,
+ *     J W_t = -(L_xi + L_eta) + S + L^v_xi + L^v_eta,
+ * applies the positivity-preserving limiter (eq. PosPres) and advances the
+ * solution with a low-storage Runge-Kutta method (section 2.3) or SSPRK(3,3)
+ * (eq. RKSSP) at a step chosen from a CFL bound, a viscous bound and the
+ * mean-positivity bounds of Lemma 2 (eq. CFLConstraints).  Everything runs
+ * in hand-written HIP kernels on one GPU; the host code only validates
+ * arguments, owns device buffers and launches kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Polynomial degree N in [2, 8]; (N+1)^2 Legendre-Gauss-Lobatto nodes per
+ *    element (section 2.2).  Nodal arrays are structure-of-arrays
+ *    [K][(N+1)^2] float64, node p = i*(N+1) + j, i the xi-index, j the
+ *    eta-index (the coalesced order of the paper's GPU section, version 4).
+ *  - Local sides 0..3 are the paper's s = 1..4: eta=-1, xi=+1, eta=+1, xi=-1
+ *    (Lemma 2).  Face node k runs along increasing xi (sides 0, 2) or
+ *    increasing eta (sides 1, 3): side 0 -> (k,0), 1 -> (N,k), 2 -> (k,N),
+ *    3 -> (0,k).
+ *  - Face map: nbr_elem[e*4+s], nbr_side[e*4+s] name the element and local
+ *    side sharing side s of element e; flip[e*4+s] = 1 when the neighbour's
+ *    face-node order is reversed (its node N-k meets node k).  The mesh must
+ *    be conforming and closed (periodic); every side has a neighbour.
+ *  - mem = 0: the pointer is host memory; mem = 1: device memory of the
+ *    context's GPU (e.g. a torch tensor's data_ptr()).  The library copies
+ *    in and out and never keeps a caller pointer.  Device-pointer transfers
+ *    are asynchronous on the context stream; host-pointer transfers return
+ *    after the data has arrived.
+ *  - The ABI is float64 everywhere.  A precision-32 context converts on
+ *    upload/download and computes in float32.
+ *  - Return value: ESDG_OK or a negative esdg_status; esdg_last_error()
+ *    describes the last failure of a context.  No entry point throws.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef ESDG_H
+#define ESDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esdg_ctx esdg_ctx;
+
+typedef enum {
+    ESDG_OK = 0,
+    ESDG_EINVAL = -1,      /* bad argument, or call out of order            */
+    ESDG_ENOMEM = -2,      /* device allocation failed                      */
+    ESDG_EHIP = -3,        /* HIP runtime error                             */
+    ESDG_EMESH = -4,       /* face map inconsistent or J <= 0 at a node     */
+    ESDG_ENEGMEAN = -5,    /* limiter met a negative element mean (Lemma 2
+                              violated); the state is still finite          */
+    ESDG_EDTPOS = -6,      /* no admissible time step (all bounds infinite
+                              or not positive)                              */
+    ESDG_ENONFINITE = -7   /* non-finite value in the state                 */
+} esdg_status;
+
+/* Run-time parameters.  esdg_default_params() fills the defaults. */
+typedef struct {
+    double g;          /* gravitational constant (9.81)                       */
+    double h_tol;      /* dry cut-off: velocities are zero where h <= h_tol
+                          in every flux; the limiter zeroes hu, hv where
+                          h < h_tol (section 6.1; default 1e-4)             */
+    double eps0;       /* artificial-viscosity amplitude (appendix A)        */
+    double sigma_min;  /* indicator thresholds (appendix A); the paper gives
+                          no values: default s0 -+ 1, s0 = -4 log10(N)      */
+    double sigma_max;
+    double cfl;        /* advective CFL number (0.5)                          */
+    double cfl_visc;   /* safety factor of the viscous bound (0.5)            */
+    int surface_flux;  /* 0: entropy stable (appendix B), 1: entropy
+                          conservative (eq. surfaceFluxes)                   */
+    int av_on;         /* artificial viscosity (Theorem 1)                    */
+    int limiter_on;    /* positivity limiter after every stage (eq. PosPres),
+                          and the Lemma 2 bound enters the adaptive step     */
+    int integrator;    /* 0: LSRK(5,4) 2N-storage, 1: SSPRK(3,3)              */
+    int max_dt_retries;/* on ESDG_ENEGMEAN redo the step with dt/2 this many
+                          times (each retry synchronises with the host)     */
+} esdg_params;
+
+/* Fill *p with the defaults for degree N (N selects sigma_min/sigma_max). */
+void esdg_default_params(esdg_params *p, int N);
+
+/* Create a context on HIP device `device`; precision 64 or 32. */
+int esdg_create(esdg_ctx **out, int device, int precision);
+/* Free every device buffer of the context; ctx may be NULL. */
+int esdg_destroy(esdg_ctx *ctx);
+/* Launch and copy on `hip_stream` (a hipStream_t; NULL = default stream). */
+int esdg_set_stream(esdg_ctx *ctx, void *hip_stream);
+int esdg_set_params(esdg_ctx *ctx, const esdg_params *p);
+int esdg_get_params(const esdg_ctx *ctx, esdg_params *p);
+
+/*
+ * Upload the mesh: nodal coordinates x, y [K][(N+1)^2] and the face map
+ * (int32 [K][4], int8 [K][4], int8 [K][4]).  The metric terms x_xi, x_eta,
+ * y_xi, y_eta are computed on the device by the LGL derivative matrix and
+ * J = x_xi y_eta - x_eta y_xi (eqs. JacobianDef, NablaRelation).
+ * ESDG_EMESH if the map is not symmetric or J <= 0 anywhere.  Replaces any
+ * previous mesh, bathymetry and state.
+ */
+int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const double *y,
+                     const int32_t *nbr_elem, const int8_t *nbr_side, const int8_t *flip,
+                     int mem);
+
+/*
+ * Nodal bathymetry b [K][(N+1)^2].  Builds the split-form derivatives of
+ * eq. SourceDisc (read with D in place of the printed 2D, and with the
+ * chain-rule sign of b_y) and the face traces used by the interface flux.
+ * b should be continuous across faces; the interface penalty S^{.,*} for
+ * discontinuous bathymetry is not applied.
+ */
+int esdg_set_bathymetry(esdg_ctx *ctx, const double *b, int mem);
+
+/* Conservative state h, hu, hv [K][(N+1)^2].  Resets the time to 0. */
+int esdg_set_state(esdg_ctx *ctx, const double *h, const double *hu, const double *hv, int mem);
+int esdg_get_state(esdg_ctx *ctx, double *h, double *hu, double *hv, int mem);
+
+/*
+ * R = dW/dt at the current state: R = -(1/J)(L_xi + L_eta - S - L^v), the
+ * split-form flux-differencing volume term with the entropy-conservative
+ * two-point fluxes (eqs. fluxDiffFormF, Fmij, volumeFluxes), the rotated
+ * ES (or EC) interface flux (appendix B), the bathymetry source and, with
+ * av_on, the BR1 viscous terms with the element viscosity of appendix A.
+ * Outputs [K][(N+1)^2] each.
+ */
+int esdg_rhs(esdg_ctx *ctx, double *rh, double *rhu, double *rhv, int mem);
+
+/* Positivity limiter in place (eq. PosPres, Jacobian-weighted means, theta
+ * = 1 when the minimum is >= 0) followed by the h_tol velocity cut-off.
+ * *n_limited (may be NULL) receives the number of scaled elements.
+ * ESDG_ENEGMEAN if an element mean is negative (that element is set to its
+ * mean). */
+int esdg_limit(esdg_ctx *ctx, int64_t *n_limited);
+
+/*
+ * Time-step bounds at the current state: out[0] = dt (min of the CFL,
+ * viscous and, when limiter_on, Lemma 2 bounds), out[1] = CFL bound,
+ * out[2] = viscous bound (+inf without AV), out[3] = Lemma 2 bound
+ * (eq. CFLConstraints with w_0 = 2/(N(N+1)) and a = J/J^surf).
+ */
+int esdg_compute_dt(esdg_ctx *ctx, double out[4]);
+
+/*
+ * Advance nsteps steps.  dt > 0: fixed step; dt <= 0: adaptive step from
+ * esdg_compute_dt's bounds, evaluated on the device at the start of every
+ * step (no host synchronisation unless max_dt_retries > 0).  With
+ * limiter_on the limiter follows every stage.  *t_out (may be NULL)
+ * receives the accumulated time.  Returns after the last step completed.
+ */
+int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out);
+
+/* Accumulated simulation time, and its reset. */
+int esdg_get_time(esdg_ctx *ctx, double *t);
+int esdg_set_time(esdg_ctx *ctx, double t);
+
+/*
+ * out[8] = total mass sum J w_i w_j h, momentum x, momentum y, total energy
+ * (the entropy, eq. entropyFunction), its semi-discrete rate
+ * sum J w_i w_j q . R (eq. entropyVariables), min h, max h, number of dry
+ * nodes (h <= h_tol).
+ */
+int esdg_diagnostics(esdg_ctx *ctx, double out[8]);
+
+/* Element viscosities eps [K] of the current state (appendix A). */
+int esdg_get_eps(esdg_ctx *ctx, double *eps, int mem);
+
+/* Device-computed metric terms and Jacobian, [K][(N+1)^2] each. */
+int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, double *yeta,
+                      double *J, int mem);
+
+/*
+ * Kernel timing: with enable = 1, esdg_step and esdg_rhs record HIP events
+ * around every launch of the stage kernel (the fused volume + interface +
+ * source + update + limiter kernel) on the context stream.
+ * esdg_profile_read returns the summed event time in milliseconds and the
+ * number of timed launches since the last reset, and resets the counters.
+ */
+int esdg_profile(esdg_ctx *ctx, int enable);
+int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_launches,
+                      double *av_ms, int64_t *av_launches);
+
+/* Last error message of ctx (never NULL). */
+const char *esdg_last_error(const esdg_ctx *ctx);
+
+/* ABI version (major*100 + minor). */
+int esdg_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESDG_H */

@@ -241,14 +241,20 @@ static void geometry(const orc_ops *op, const orc_mesh *m, orc_geom *G)
     int N = op->N, n1 = N + 1, np = n1 * n1;
     for (int64_t e = 0; e < m->K; ++e) {
         const double *x = m->x + e * np, *y = m->y + e * np;
+        /* The metric terms are derivatives of the mapping, so they do not
+         * change when the element is translated: differentiate coordinates
+         * relative to the element's first node, which keeps the sums at the
+         * element's size instead of the domain's (no cancellation against
+         * the absolute position). */
+        const double x0 = x[0], y0 = y[0];
         for (int i = 0; i <= N; ++i)
             for (int j = 0; j <= N; ++j) {
                 double xx = 0, xe = 0, yx = 0, ye = 0;
                 for (int mm = 0; mm <= N; ++mm) {
-                    xx += op->D[i][mm] * x[mm * n1 + j];
-                    yx += op->D[i][mm] * y[mm * n1 + j];
-                    xe += op->D[j][mm] * x[i * n1 + mm];
-                    ye += op->D[j][mm] * y[i * n1 + mm];
+                    xx += op->D[i][mm] * (x[mm * n1 + j] - x0);
+                    yx += op->D[i][mm] * (y[mm * n1 + j] - y0);
+                    xe += op->D[j][mm] * (x[i * n1 + mm] - x0);
+                    ye += op->D[j][mm] * (y[i * n1 + mm] - y0);
                 }
                 int64_t q = e * np + i * n1 + j;
                 G->xxi[q] = xx; G->xeta[q] = xe; G->yxi[q] = yx; G->yeta[q] = ye;

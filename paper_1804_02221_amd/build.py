@@ -1,0 +1,63 @@
+"""Build the HIP library libesdg.so for gfx950 in place.
+
+One object per polynomial degree (the kernel templates are instantiated for
+N = 2..8 in separate translation units that compile in parallel), one object
+for the host runtime, linked into ``paper_1804_02221_amd/libesdg.so``.
+Objects go to ``_build/`` at the repository root.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libesdg.so")
+DEGREES = range(2, 9)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
+         # packed FP32 instructions off (see DESIGN notes on the toolchain)
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", INCLUDE, "-I", CSRC]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+        raise RuntimeError(f"build step failed: {' '.join(cmd)}\n{msg}")
+    return r
+
+
+def build(force: bool = True, jobs: int | None = None) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp"))]
+    newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(INCLUDE, "esdg.h")])
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= newest:
+        return LIB
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    cmds = []
+    objs = []
+    for n in DEGREES:
+        o = os.path.join(BUILD, f"esdg_inst_{n}.o")
+        cmds.append([HIPCC, *FLAGS, f"-DESDG_N={n}", "-c", os.path.join(CSRC, "esdg_inst.hip"), "-o", o])
+        objs.append(o)
+    o = os.path.join(BUILD, "esdg_runtime.o")
+    cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, "esdg_runtime.hip"), "-o", o])
+    objs.append(o)
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(_run, cmds))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--force" in sys.argv or True))

@@ -1,0 +1,182 @@
+// Instantiation of the kernels for one polynomial degree ESDG_N (set by the
+// build, one object file per degree so the degrees compile in parallel).
+#include "esdg_kernels.hpp"
+#include "esdg_launch.hpp"
+
+#ifndef ESDG_N
+#error "ESDG_N must be defined"
+#endif
+
+namespace esdg {
+
+template <typename R>
+static Mesh<R> mesh_view(const Bufs &B)
+{
+    Mesh<R> m;
+    m.K = B.K;
+    m.Ax = (const R *)B.Ax;
+    m.Cx = (const R *)B.Cx;
+    m.Ae = (const R *)B.Ae;
+    m.Ce = (const R *)B.Ce;
+    m.bx = (const R *)B.bx;
+    m.by = (const R *)B.by;
+    m.bface = (const R *)B.bface;
+    m.nbr = B.nbr;
+    m.code = B.code;
+    return m;
+}
+
+template <int N>
+static int64_t ntiles_of(int64_t K)
+{
+    return (K + Shape<N>::E - 1) / Shape<N>::E;
+}
+
+template <int N>
+static dim3 tile_grid(int64_t K)
+{
+    const int64_t nt = ntiles_of<N>(K);
+    return dim3((unsigned)(((nt + kXcds - 1) / kXcds) * kXcds));
+}
+
+template <int N, typename R>
+int Launch<N, R>::threads() { return Shape<N>::T; }
+
+template <int N, typename R>
+int Launch<N, R>::elems_per_block() { return Shape<N>::E; }
+
+template <int N, typename R>
+hipError_t Launch<N, R>::geometry(const Bufs &B, const Tab<double> &td, hipStream_t s)
+{
+    constexpr int np = (N + 1) * (N + 1);
+    const int64_t n = B.K * np;
+    const int bs = 256;
+    hipLaunchKernelGGL((geometry_kernel<N, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, B.K,
+                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.flags + 3, td);
+    return hipGetLastError();
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::bathymetry(const Bufs &B, const double *b, const Tab<double> &td, hipStream_t s)
+{
+    constexpr int np = (N + 1) * (N + 1);
+    const int64_t n = B.K * np;
+    const int bs = 256;
+    hipLaunchKernelGGL((bathymetry_kernel<N, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, B.K,
+                       B.x, B.y, b, (R *)B.bx, (R *)B.by, (R *)B.bface, td);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((convert_kernel<double, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, b,
+                       (R *)B.b, n);
+    return hipGetLastError();
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::av(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
+{
+    AvArgs<N, R> a;
+    a.m = mesh_view<R>(B);
+    a.P = P;
+    a.tab = t;
+    a.h = (const R *)B.W[in][0];
+    a.hu = (const R *)B.W[in][1];
+    a.hv = (const R *)B.W[in][2];
+    a.eps = (R *)B.eps;
+    a.vtr = (R *)B.vtr;
+    a.ntiles = ntiles_of<N>(B.K);
+    hipLaunchKernelGGL((av_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N, typename R, int MODE, bool AV>
+static void launch_stage(const StageArgs<R> &a, int64_t K, hipStream_t s)
+{
+    hipLaunchKernelGGL((stage_kernel<N, R, MODE, AV>), tile_grid<N>(K), dim3(Shape<N>::T), 0, s, a);
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> &P, const Tab<R> &t,
+                               hipStream_t s)
+{
+    StageArgs<R> a;
+    a.m = mesh_view<R>(B);
+    a.P = P;
+    a.tab = t;
+    a.h = (const R *)B.W[c.in][0];
+    a.hu = (const R *)B.W[c.in][1];
+    a.hv = (const R *)B.W[c.in][2];
+    a.h0 = (const R *)B.W[c.base][0];
+    a.hu0 = (const R *)B.W[c.base][1];
+    a.hv0 = (const R *)B.W[c.base][2];
+    void *const *o = c.out_rhs ? B.Rb : B.W[c.out];
+    a.oh = (R *)o[0];
+    a.ohu = (R *)o[1];
+    a.ohv = (R *)o[2];
+    a.dh = (R *)B.dU[0];
+    a.dhu = (R *)B.dU[1];
+    a.dhv = (R *)B.dU[2];
+    a.eps = (const R *)B.eps;
+    a.vtr = (const R *)B.vtr;
+    a.dt = B.dscal;
+    a.ca = (R)c.ca;
+    a.cb = (R)c.cb;
+    a.flags = B.flags;
+    a.ntiles = ntiles_of<N>(B.K);
+    if (c.mode == kModeRhs) {
+        if (c.av) launch_stage<N, R, kModeRhs, true>(a, B.K, s);
+        else launch_stage<N, R, kModeRhs, false>(a, B.K, s);
+    } else if (c.mode == kModeLsrk) {
+        if (c.av) launch_stage<N, R, kModeLsrk, true>(a, B.K, s);
+        else launch_stage<N, R, kModeLsrk, false>(a, B.K, s);
+    } else {
+        if (c.av) launch_stage<N, R, kModeSsp, true>(a, B.K, s);
+        else launch_stage<N, R, kModeSsp, false>(a, B.K, s);
+    }
+    return hipGetLastError();
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::limit(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
+{
+    hipLaunchKernelGGL((limit_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, mesh_view<R>(B), P,
+                       t, (R *)B.W[buf][0], (R *)B.W[buf][1], (R *)B.W[buf][2], B.flags, ntiles_of<N>(B.K));
+    return hipGetLastError();
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, const Phys<R> &P, const Tab<R> &t,
+                            double br1_radius, hipStream_t s)
+{
+    DtArgs<N, R> a;
+    a.m = mesh_view<R>(B);
+    a.P = P;
+    a.tab = t;
+    a.h = (const R *)B.W[in][0];
+    a.hu = (const R *)B.W[in][1];
+    a.hv = (const R *)B.W[in][2];
+    a.eps = av ? (const R *)B.eps : nullptr;
+    a.slots = B.slots;
+    a.br1_radius = br1_radius;
+    a.ntiles = ntiles_of<N>(B.K);
+    hipLaunchKernelGGL((dt_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::diag(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, int64_t *nblocks,
+                              hipStream_t s)
+{
+    constexpr int np = (N + 1) * (N + 1), T = Shape<N>::T;
+    const int64_t nb = (B.K * np + T - 1) / T;
+    *nblocks = nb;
+    if (nb > B.part_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((diag_kernel<N, R>), dim3((unsigned)nb), dim3(T), 0, s, mesh_view<R>(B), P, t,
+                       (const R *)B.W[buf][0], (const R *)B.W[buf][1], (const R *)B.W[buf][2],
+                       (const R *)B.b, (const R *)B.Rb[0], (const R *)B.Rb[1], (const R *)B.Rb[2], B.part);
+    return hipGetLastError();
+}
+
+template struct Launch<ESDG_N, double>;
+template struct Launch<ESDG_N, float>;
+
+}  // namespace esdg

@@ -1,0 +1,911 @@
+// Device kernels of the entropy-stable DGSEM shallow-water solver for gfx950.
+//
+// Work decomposition: a workgroup holds E elements of (N+1)^2 nodes, one
+// thread per node (E ~ 256 / (N+1)^2, so a workgroup is four 64-wide waves);
+// nodal state and the contravariant metric directions are staged in LDS, the
+// state arrays are read and written in the coalesced SoA order
+// [K][(N+1)^2], and the face work of the E elements is spread over the same
+// threads (one face node per thread and pass).  Workgroup -> element-tile
+// mapping is XCD-aware so that each of the eight XCDs sweeps one contiguous
+// block of tiles and neighbour traces mostly hit its own L2.
+//
+// Kernels (per RK stage): av_kernel (artificial viscosity: element
+// viscosity from the modal indicator and the BR1 viscous fluxes on the
+// element faces, only with AV on), stage_kernel (split-form volume term,
+// interface flux, source, viscous divergence, stage update and positivity
+// limiter, fused); per step: dt_kernel + dt_finalize_kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "esdg_tables.hpp"
+
+namespace esdg {
+
+// ------------------------------------------------------------------------
+// Shapes
+// ------------------------------------------------------------------------
+template <int N>
+struct Shape {
+    static constexpr int nf = N + 1;
+    static constexpr int np = nf * nf;
+    static constexpr int E = (256 / np) > 0 ? (256 / np) : 1;    // elements per workgroup
+    static constexpr int T = ((E * np + 63) / 64) * 64;           // threads per workgroup
+    static constexpr int NFACE = E * 4 * nf;                      // face-node slots per workgroup
+};
+
+constexpr int kXcds = 8;
+constexpr int kDtSlots = 64;
+
+// Tile of workgroup b when B = round_up(ntiles, 8) workgroups are launched:
+// hardware places workgroup b on XCD b % 8, so XCD x gets tiles
+// [x*per, (x+1)*per).  Tiles >= ntiles return -1.
+__device__ inline int64_t xcd_tile(int64_t ntiles)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t per = (ntiles + kXcds - 1) / kXcds;
+    const int64_t tile = (b % kXcds) * per + b / kXcds;
+    return tile < ntiles ? tile : -1;
+}
+
+// Face node k of local side s -> local (i, j).
+template <int N>
+__device__ __forceinline__ void side_node(int s, int k, int &i, int &j)
+{
+    i = (s == 0 || s == 2) ? k : (s == 1 ? N : 0);
+    j = (s == 1 || s == 3) ? k : (s == 2 ? N : 0);
+}
+
+// ------------------------------------------------------------------------
+// Arguments
+// ------------------------------------------------------------------------
+template <typename R>
+struct Tab {
+    R D[kMaxNF * kMaxNF];     // derivative matrix, row-major
+    R Vinv[kMaxNF * kMaxNF];  // Vandermonde inverse
+    R w[kMaxNF];              // LGL weights
+};
+
+template <typename R>
+struct Mesh {
+    int64_t K;
+    const R *Ax, *Cx;   // J grad(xi)  = ( y_eta, -x_eta)  [K][np]
+    const R *Ae, *Ce;   // J grad(eta) = (-y_xi,   x_xi)   [K][np]
+    const R *bx, *by;   // split-form bathymetry derivatives (eq. SourceDisc)
+    const R *bface;     // bathymetry on the faces [K][4][nf]
+    const int32_t *nbr; // [K][4] neighbour element
+    const int8_t *code; // [K][4] neighbour side | flip << 2
+};
+
+template <typename R>
+struct Phys {
+    R g, h_tol, eps0, sigma_min, sigma_max, cfl, cfl_visc;
+    int ec, limiter_on;
+};
+
+// Neighbour node of face node (s, k) of element e.
+template <int N, typename R>
+__device__ __forceinline__ int64_t nbr_node(const Mesh<R> &m, int64_t e, int s, int k,
+                                           int64_t &en, int &ns, int &kk)
+{
+    constexpr int nf = N + 1, np = nf * nf;
+    en = m.nbr[e * 4 + s];
+    const int c = m.code[e * 4 + s];
+    ns = c & 3;
+    kk = (c >> 2) ? N - k : k;
+    int i, j;
+    side_node<N>(ns, kk, i, j);
+    return en * np + i * nf + j;
+}
+
+template <typename R>
+__device__ __forceinline__ R rcp_wet(R h, R h_tol)
+{
+    return h > h_tol ? R(1) / h : R(0);
+}
+
+// Rotated numerical interface flux along the unit normal (nx, ny), '-' =
+// own trace, '+' = neighbour (appendix B): EC part plus, for the entropy
+// stable flux, -1/2 R |Lambda| R^T [[q~]] expanded in closed form.
+template <typename R>
+__device__ __forceinline__ void interface_flux(R hm, R hum, R hvm, R bm, R hp, R hup, R hvp, R bp,
+                                               R nx, R ny, const Phys<R> &P, R &F0, R &F1, R &F2)
+{
+    const R g = P.g;
+    const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
+    const R um = hum * im, vm = hvm * im, up = hup * ip, vp = hvp * ip;
+    const R utm = nx * um + ny * vm, vtm = nx * vm - ny * um;
+    const R utp = nx * up + ny * vp, vtp = nx * vp - ny * up;
+    const R cm = sqrt(g * (hm > R(0) ? hm : R(0)));
+    const R cp = sqrt(g * (hp > R(0) ? hp : R(0)));
+    const R ah = R(0.5) * (hm + hp), au = R(0.5) * (utm + utp), av = R(0.5) * (vtm + vtp);
+    const R ah2 = R(0.5) * (hm * hm + hp * hp), ac = R(0.5) * (cm + cp);
+    R f0 = ah * au;
+    R f1 = ah * au * au + R(0.5) * g * ah2;
+    R f2 = ah * au * av;
+    if (!P.ec) {
+        const R dq1 = g * ((hp + bp) - (hm + bm)) -
+                      R(0.5) * ((utp * utp + vtp * vtp) - (utm * utm + vtm * vtm));
+        const R dq2 = utp - utm, dq3 = vtp - vtm;
+        const R i2g = R(0.5) / g;
+        const R lp = fabs(au + ac) * i2g, l2 = fabs(ah * au), lm = fabs(au - ac) * i2g;
+        const R r1 = lp * (dq1 + (au + ac) * dq2 + av * dq3);
+        const R r2 = l2 * dq3;
+        const R r3 = lm * (dq1 + (au - ac) * dq2 + av * dq3);
+        f0 -= R(0.5) * (r1 + r3);
+        f1 -= R(0.5) * ((au + ac) * r1 + (au - ac) * r3);
+        f2 -= R(0.5) * (av * (r1 + r3) + r2);
+    }
+    F0 = f0;
+    F1 = nx * f1 - ny * f2;
+    F2 = ny * f1 + nx * f2;
+}
+
+// ------------------------------------------------------------------------
+// Geometry: metric terms by the derivative matrix (eq. NablaRelation)
+// ------------------------------------------------------------------------
+template <int N, typename R>
+__global__ void geometry_kernel(int64_t K, const double *__restrict__ x, const double *__restrict__ y,
+                                R *Ax, R *Cx, R *Ae, R *Ce, int *bad, Tab<double> tab)
+{
+    constexpr int nf = N + 1, np = nf * nf;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * np) return;
+    const int64_t e = q / np;
+    const int p = (int)(q - e * np), i = p / nf, j = p - i * nf;
+    const double *xe = x + e * np, *ye = y + e * np;
+    // differentiate coordinates relative to the element's first node: the
+    // metric terms are translation invariant and the sums stay at the
+    // element's size (no cancellation against the absolute position)
+    const double x0 = xe[0], y0 = ye[0];
+    double xxi = 0, xeta = 0, yxi = 0, yeta = 0;
+#pragma unroll
+    for (int m = 0; m < nf; ++m) {
+        xxi += tab.D[i * kMaxNF + m] * (xe[m * nf + j] - x0);
+        yxi += tab.D[i * kMaxNF + m] * (ye[m * nf + j] - y0);
+        xeta += tab.D[j * kMaxNF + m] * (xe[i * nf + m] - x0);
+        yeta += tab.D[j * kMaxNF + m] * (ye[i * nf + m] - y0);
+    }
+    const double J = xxi * yeta - xeta * yxi;
+    if (!(J > 0.0)) atomicOr(bad, 1);
+    Ax[q] = (R)yeta;
+    Cx[q] = (R)(-xeta);
+    Ae[q] = (R)(-yxi);
+    Ce[q] = (R)xxi;
+}
+
+// Split-form bathymetry derivatives (eq. SourceDisc, read with D) and face
+// traces of b; metrics recomputed in float64 from the coordinates.
+template <int N, typename R>
+__global__ void bathymetry_kernel(int64_t K, const double *__restrict__ x, const double *__restrict__ y,
+                                  const double *__restrict__ b, R *bx, R *by, R *bface,
+                                  Tab<double> tab)
+{
+    constexpr int nf = N + 1, np = nf * nf;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * np) return;
+    const int64_t e = q / np;
+    const int p = (int)(q - e * np), i = p / nf, j = p - i * nf;
+    const double *xe = x + e * np, *ye = y + e * np, *be = b + e * np;
+    // metric terms at the line nodes are needed inside D(y_eta b) etc.
+    const double x0 = xe[0], y0 = ye[0];
+    auto met = [&](int a, int c, double &xxi, double &xeta, double &yxi, double &yeta) {
+        xxi = xeta = yxi = yeta = 0.0;
+        for (int m = 0; m < nf; ++m) {
+            xxi += tab.D[a * kMaxNF + m] * (xe[m * nf + c] - x0);
+            yxi += tab.D[a * kMaxNF + m] * (ye[m * nf + c] - y0);
+            xeta += tab.D[c * kMaxNF + m] * (xe[a * nf + m] - x0);
+            yeta += tab.D[c * kMaxNF + m] * (ye[a * nf + m] - y0);
+        }
+    };
+    double Db_xi = 0, Dyb_xi = 0, Dxb_xi = 0, Db_eta = 0, Dyb_eta = 0, Dxb_eta = 0;
+    for (int m = 0; m < nf; ++m) {
+        double a0, a1, a2, a3;
+        const double dxi = tab.D[i * kMaxNF + m], deta = tab.D[j * kMaxNF + m];
+        met(m, j, a0, a1, a2, a3);   // node (m, j)
+        const double bm = be[m * nf + j];
+        Db_xi += dxi * bm;
+        Dyb_xi += dxi * (a3 * bm);   // y_eta b
+        Dxb_xi += dxi * (a1 * bm);   // x_eta b
+        met(i, m, a0, a1, a2, a3);   // node (i, m)
+        const double bn = be[i * nf + m];
+        Db_eta += deta * bn;
+        Dyb_eta += deta * (a2 * bn); // y_xi b
+        Dxb_eta += deta * (a0 * bn); // x_xi b
+    }
+    double xxi, xeta, yxi, yeta;
+    met(i, j, xxi, xeta, yxi, yeta);
+    bx[q] = (R)(yeta * Db_xi + Dyb_xi - yxi * Db_eta - Dyb_eta);
+    by[q] = (R)(-xeta * Db_xi - Dxb_xi + xxi * Db_eta + Dxb_eta);
+    // face traces: thread of a face node writes every side the node is on
+    if (j == 0) bface[(e * 4 + 0) * nf + i] = (R)be[p];
+    if (i == N) bface[(e * 4 + 1) * nf + j] = (R)be[p];
+    if (j == N) bface[(e * 4 + 2) * nf + i] = (R)be[p];
+    if (i == 0) bface[(e * 4 + 3) * nf + j] = (R)be[p];
+}
+
+// ------------------------------------------------------------------------
+// Workgroup-level per-element reductions over the nodes of each element.
+// red: LDS scratch of T*NQ reals; returns the element total in every thread.
+// ------------------------------------------------------------------------
+template <int N, typename R, int NQ>
+struct ElemReduce {
+    static constexpr int nf = N + 1, np = nf * nf, E = Shape<N>::E, T = Shape<N>::T;
+    // v[0..NQ-1] summed, except v[NQ-1] which is reduced by min when MINLAST
+    template <bool MINLAST>
+    __device__ __forceinline__ static void run(R (&v)[NQ], R *red, int t, int el, int p)
+    {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) red[c * T + t] = v[c];
+        __syncthreads();
+        R part[NQ];
+        const bool row = (t < E * np) && (p < nf);   // thread (el, p<nf) reduces column p
+        if (row) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                R s = red[c * T + el * np + p];
+#pragma unroll
+                for (int r = 1; r < nf; ++r) {
+                    const R val = red[c * T + el * np + r * nf + p];
+                    if (MINLAST && c == NQ - 1) s = val < s ? val : s;
+                    else s += val;
+                }
+                part[c] = s;
+            }
+        }
+        __syncthreads();
+        if (row) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) red[c * T + el * np + p] = part[c];
+        }
+        __syncthreads();
+        if (t < E * np) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                R s = red[c * T + el * np];
+#pragma unroll
+                for (int r = 1; r < nf; ++r) {
+                    const R val = red[c * T + el * np + r];
+                    if (MINLAST && c == NQ - 1) s = val < s ? val : s;
+                    else s += val;
+                }
+                v[c] = s;
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// ------------------------------------------------------------------------
+// Artificial viscosity: element viscosity (appendix A) and the physical
+// viscous fluxes h eps (U1, V1), h eps (U2, V2) on the element's faces
+// (Theorem 1, BR1 gradients with U* = {u}).  Only face values leave the
+// kernel; the stage kernel recomputes interior gradients itself.
+// ------------------------------------------------------------------------
+template <int N, typename R>
+struct AvArgs {
+    Mesh<R> m;
+    Phys<R> P;
+    Tab<R> tab;
+    const R *h, *hu, *hv;   // stage input state
+    R *eps;                 // [K]
+    R *vtr;                 // [K][4][nf][4]: Fv2, Fv3, Gv2, Gv3 at face nodes
+    int64_t ntiles;
+};
+
+// Viscous physical fluxes at node (i,j) of the element whose u, v are in
+// LDS (su, sv offset to the element), with U*, V* per face slot in us, vs.
+template <int N, typename R>
+__device__ __forceinline__ void viscous_flux_at(int i, int j, const R *su, const R *sv, const R *us,
+                                                const R *vs, R Ax, R Cx, R Ae, R Ce, R he,
+                                                const Tab<R> &tab, R &Fv2, R &Fv3, R &Gv2, R &Gv3)
+{
+    constexpr int nf = N + 1;
+    const R u0 = su[i * nf + j], v0 = sv[i * nf + j];
+    R dxu = 0, dxv = 0, deu = 0, dev = 0;
+#pragma unroll
+    for (int m = 0; m < nf; ++m) {
+        const R di = tab.D[i * kMaxNF + m], dj = tab.D[j * kMaxNF + m];
+        dxu += di * su[m * nf + j];
+        dxv += di * sv[m * nf + j];
+        deu += dj * su[i * nf + m];
+        dev += dj * sv[i * nf + m];
+    }
+    const R iw = R(1) / tab.w[0];
+    // BR1 lift (U* - u)/w on the faces the node lies on
+    if (i == N) { dxu += (us[1 * nf + j] - u0) * iw; dxv += (vs[1 * nf + j] - v0) * iw; }
+    if (i == 0) { dxu -= (us[3 * nf + j] - u0) * iw; dxv -= (vs[3 * nf + j] - v0) * iw; }
+    if (j == N) { deu += (us[2 * nf + i] - u0) * iw; dev += (vs[2 * nf + i] - v0) * iw; }
+    if (j == 0) { deu -= (us[0 * nf + i] - u0) * iw; dev -= (vs[0 * nf + i] - v0) * iw; }
+    // J grad = (y_eta d_xi - y_xi d_eta, -x_eta d_xi + x_xi d_eta) = (Ax dxi + Ae deta, Cx dxi + Ce deta)
+    const R J = Ce * Ax - Cx * Ae;   // x_xi y_eta - x_eta y_xi
+    const R s = he / J;
+    Fv2 = s * (Ax * dxu + Ae * deu);
+    Gv2 = s * (Cx * dxu + Ce * deu);
+    Fv3 = s * (Ax * dxv + Ae * dev);
+    Gv3 = s * (Cx * dxv + Ce * dev);
+}
+
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void av_kernel(AvArgs<N, R> a)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
+    __shared__ R s_h[T], s_u[T], s_v[T], s_red[4 * T];
+    __shared__ R s_us[NF], s_vs[NF], s_eps[E];
+    const int64_t tile = xcd_tile(a.ntiles);
+    if (tile < 0) return;
+    const int t = threadIdx.x;
+    // lanes past the last element's nodes shadow node 0 of the last slot
+    // (all LDS indices stay in range; they never store)
+    const bool lane = t < E * np;
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0, i = p / nf, j = p - i * nf;
+    const int64_t e0 = tile * E, e = e0 + el;
+    const bool act = lane && (e < a.m.K);
+    const int64_t q = e * np + p;
+    R h = 0, u = 0, v = 0;
+    if (act) {
+        h = a.h[q];
+        const R ih = rcp_wet(h, a.P.h_tol);
+        u = a.hu[q] * ih;
+        v = a.hv[q] * ih;
+    }
+    s_h[t] = h;
+    s_u[t] = u;
+    s_v[t] = v;
+    // BR1 interface states U* = {u}, V* = {v}
+    for (int f = t; f < NF; f += T) {
+        const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+        const int64_t fe = e0 + fel;
+        R us = 0, vs = 0;
+        if (fe < a.m.K) {
+            int fi, fj, ns, kk;
+            int64_t en;
+            side_node<N>(s, k, fi, fj);
+            const int64_t qo = fe * np + fi * nf + fj;
+            const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+            const R ho = a.h[qo], hn = a.h[qn];
+            const R io = rcp_wet(ho, a.P.h_tol), in = rcp_wet(hn, a.P.h_tol);
+            us = R(0.5) * (a.hu[qo] * io + a.hu[qn] * in);
+            vs = R(0.5) * (a.hv[qo] * io + a.hv[qn] * in);
+        }
+        s_us[f] = us;
+        s_vs[f] = vs;
+    }
+    __syncthreads();
+    // modal indicator: T = Vinv h (rows), Qh = T Vinv^T
+    R Tq = 0;
+    if (t < E * np) {
+#pragma unroll
+        for (int r = 0; r < nf; ++r) Tq += a.tab.Vinv[i * kMaxNF + r] * s_h[el * np + r * nf + j];
+    }
+    __syncthreads();
+    s_red[t] = Tq;   // reuse as T storage
+    __syncthreads();
+    R Qh = 0;
+    if (t < E * np) {
+#pragma unroll
+        for (int c = 0; c < nf; ++c) Qh += s_red[el * np + i * nf + c] * a.tab.Vinv[j * kMaxNF + c];
+    }
+    __syncthreads();
+    {
+        const R q2 = Qh * Qh;
+        const int mx = i > j ? i : j;
+        R vals[4] = {q2, mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0)};
+        ElemReduce<N, R, 4>::template run<false>(vals, s_red, t, el, p);
+        R hv[1] = {h};
+        // max h over the element through the min of -h
+        R mh[1] = {-h};
+        ElemReduce<N, R, 1>::template run<true>(mh, s_red, t, el, p);
+        (void)hv;
+        if (act && p == 0) {
+            R eps = 0;
+            const R hmax = -mh[0];
+            if (hmax > a.P.h_tol) {
+                const R r1 = vals[0] > R(0) ? vals[1] / vals[0] : R(0);
+                const R r2 = vals[2] > R(0) ? vals[3] / vals[2] : R(0);
+                const R rm = r1 > r2 ? r1 : r2;
+                if (rm > R(0)) {
+                    const R sg = log10(rm);
+                    const R smin = a.P.sigma_min, smax = a.P.sigma_max;
+                    if (sg >= smax) eps = a.P.eps0;
+                    else if (sg > smin)
+                        eps = R(0.5) * a.P.eps0 *
+                              (R(1) + sin(R(3.14159265358979323846) * (sg - R(0.5) * (smax + smin)) /
+                                          (smax - smin)));
+                }
+            }
+            a.eps[e] = eps;
+            s_eps[el] = eps;
+        }
+    }
+    __syncthreads();
+    // viscous fluxes at the face nodes
+    for (int f = t; f < NF; f += T) {
+        const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+        const int64_t fe = e0 + fel;
+        if (fe >= a.m.K) continue;
+        int fi, fj;
+        side_node<N>(s, k, fi, fj);
+        const int lp = fel * np + fi * nf + fj;
+        const int64_t qo = fe * np + fi * nf + fj;
+        const R he = s_h[lp] * s_eps[fel];
+        R Fv2, Fv3, Gv2, Gv3;
+        viscous_flux_at<N, R>(fi, fj, s_u + fel * np, s_v + fel * np, s_us + fel * 4 * nf,
+                              s_vs + fel * 4 * nf, a.m.Ax[qo], a.m.Cx[qo], a.m.Ae[qo], a.m.Ce[qo], he,
+                              a.tab, Fv2, Fv3, Gv2, Gv3);
+        R *o = a.vtr + ((fe * 4 + s) * nf + k) * 4;
+        o[0] = Fv2;
+        o[1] = Fv3;
+        o[2] = Gv2;
+        o[3] = Gv3;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Stage kernel
+// ------------------------------------------------------------------------
+enum StageMode { kModeRhs = 0, kModeLsrk = 1, kModeSsp = 2 };
+
+template <typename R>
+struct StageArgs {
+    Mesh<R> m;
+    Phys<R> P;
+    Tab<R> tab;
+    const R *h, *hu, *hv;        // stage input W
+    const R *h0, *hu0, *hv0;     // SSP: W^n
+    R *oh, *ohu, *ohv;           // output: R (rhs mode) or the new state
+    R *dh, *dhu, *dhv;           // LSRK register dU (in place)
+    const R *eps;                // [K] (AV)
+    const R *vtr;                // [K][4][nf][4] (AV)
+    const double *dt;            // device scalar: current step
+    R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
+    int *flags;                  // [0]: negative mean seen, [1]: limited elements
+    int64_t ntiles;
+};
+
+template <int N, typename R, int MODE, bool AV>
+__global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
+    static_assert((T & (T - 1)) == 0, "workgroup size must be a power of two");
+    // one contiguous staging region: reused as reduction scratch by the limiter
+    __shared__ R s_st[9 * T];
+    R *const s_h = s_st, *const s_hu = s_st + T, *const s_hv = s_st + 2 * T;
+    R *const s_u = s_st + 3 * T, *const s_v = s_st + 4 * T;
+    R *const s_Ax = s_st + 5 * T, *const s_Cx = s_st + 6 * T;
+    R *const s_Ae = s_st + 7 * T, *const s_Ce = s_st + 8 * T;
+    __shared__ R s_fl[3][NF];
+    __shared__ R s_us[AV ? NF : 1], s_vs[AV ? NF : 1], s_vn[AV ? 4 : 1][AV ? NF : 1];
+    __shared__ R s_Fv[AV ? 4 : 1][AV ? T : 1];
+
+    const int64_t tile = xcd_tile(a.ntiles);
+    if (tile < 0) return;
+    const int t = threadIdx.x;
+    // lanes past the last element's nodes shadow node 0 of the last slot
+    // (all LDS indices stay in range; they never store)
+    const bool lane = t < E * np;
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0, i = p / nf, j = p - i * nf;
+    const int64_t e0 = tile * E, e = e0 + el;
+    const bool act = lane && (e < a.m.K);
+    const int64_t q = e * np + p;
+    const Phys<R> &P = a.P;
+
+    R h = 0, hu = 0, hv = 0, Ax = 0, Cx = 0, Ae = 0, Ce = 0;
+    if (act) {
+        h = a.h[q]; hu = a.hu[q]; hv = a.hv[q];
+        Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
+    }
+    const R ih = rcp_wet(h, P.h_tol);
+    const R u = hu * ih, v = hv * ih;
+    s_h[t] = h; s_hu[t] = hu; s_hv[t] = hv; s_u[t] = u; s_v[t] = v;
+    s_Ax[t] = Ax; s_Cx[t] = Cx; s_Ae[t] = Ae; s_Ce[t] = Ce;
+    __syncthreads();
+
+    // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node ----
+    const R iw0 = R(1) / a.tab.w[0];
+    for (int f = t; f < NF; f += T) {
+        const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+        const int64_t fe = e0 + fel;
+        R c0 = 0, c1 = 0, c2 = 0;
+        if (fe < a.m.K) {
+            int fi, fj, ns, kk;
+            int64_t en;
+            side_node<N>(s, k, fi, fj);
+            const int lp = fel * np + fi * nf + fj;
+            const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+            // outward scaled normal: +-J grad(xi) on xi = +-1, +-J grad(eta) on eta = +-1
+            R snx, sny;
+            if (s == 1) { snx = s_Ax[lp]; sny = s_Cx[lp]; }
+            else if (s == 3) { snx = -s_Ax[lp]; sny = -s_Cx[lp]; }
+            else if (s == 2) { snx = s_Ae[lp]; sny = s_Ce[lp]; }
+            else { snx = -s_Ae[lp]; sny = -s_Ce[lp]; }
+            const R js = sqrt(snx * snx + sny * sny);
+            const R ijs = R(1) / js;
+            const R hn = a.h[qn], hun = a.hu[qn], hvn = a.hv[qn];
+            const R bo = a.m.bface[(fe * 4 + s) * nf + k];
+            const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
+            R F0, F1, F2;
+            interface_flux<R>(s_h[lp], s_hu[lp], s_hv[lp], bo, hn, hun, hvn, bn, snx * ijs, sny * ijs, P,
+                              F0, F1, F2);
+            const R sc = js * iw0;
+            c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
+            if constexpr (AV) {
+                const R in = rcp_wet(hn, P.h_tol);
+                s_us[f] = R(0.5) * (s_u[lp] + hun * in);
+                s_vs[f] = R(0.5) * (s_v[lp] + hvn * in);
+                const R *vn = a.vtr + ((en * 4 + ns) * nf + kk) * 4;
+                s_vn[0][f] = vn[0]; s_vn[1][f] = vn[1]; s_vn[2][f] = vn[2]; s_vn[3][f] = vn[3];
+            }
+        } else if constexpr (AV) {
+            s_us[f] = 0; s_vs[f] = 0;
+            s_vn[0][f] = 0; s_vn[1][f] = 0; s_vn[2][f] = 0; s_vn[3][f] = 0;
+        }
+        s_fl[0][f] = c0; s_fl[1][f] = c1; s_fl[2][f] = c2;
+    }
+
+    // ---- volume: sum_m 2 D_im F~(i,m) + sum_m 2 D_jm G~(j,m) (D~ has a zero
+    // diagonal).  Per pair with contravariant direction (A, C):
+    //   F1' = s_hu sA + s_hv sC,  F2' = s_u F1' + 2g h h_m sA,  F3' = s_v F1' + 2g h h_m sC
+    // and 2 D F~ = D (F1'/2, F2'/4, F3'/4).
+    R a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
+    const R h2g = R(2) * P.g * h;
+    {
+        const int base = el * np;
+#pragma unroll
+        for (int mm = 0; mm < nf; ++mm) {
+            if (mm == i) continue;
+            const int qq = base + mm * nf + j;
+            const R d = a.tab.D[i * kMaxNF + mm];
+            const R sA = Ax + s_Ax[qq], sC = Cx + s_Cx[qq];
+            const R f1 = (hu + s_hu[qq]) * sA + (hv + s_hv[qq]) * sC;
+            const R pp = h2g * s_h[qq];
+            a1 += d * f1;
+            a2 += d * ((u + s_u[qq]) * f1 + pp * sA);
+            a3 += d * ((v + s_v[qq]) * f1 + pp * sC);
+        }
+#pragma unroll
+        for (int mm = 0; mm < nf; ++mm) {
+            if (mm == j) continue;
+            const int qq = base + i * nf + mm;
+            const R d = a.tab.D[j * kMaxNF + mm];
+            const R sA = Ae + s_Ae[qq], sC = Ce + s_Ce[qq];
+            const R f1 = (hu + s_hu[qq]) * sA + (hv + s_hv[qq]) * sC;
+            const R pp = h2g * s_h[qq];
+            b1 += d * f1;
+            b2 += d * ((u + s_u[qq]) * f1 + pp * sA);
+            b3 += d * ((v + s_v[qq]) * f1 + pp * sC);
+        }
+    }
+    R L1 = R(0.5) * (a1 + b1), L2 = R(0.25) * (a2 + b2), L3 = R(0.25) * (a3 + b3);
+    __syncthreads();   // face slots complete
+    {
+        const int fb = el * 4 * nf;
+        if (j == 0) { L1 += s_fl[0][fb + 0 * nf + i]; L2 += s_fl[1][fb + 0 * nf + i]; L3 += s_fl[2][fb + 0 * nf + i]; }
+        if (i == N) { L1 += s_fl[0][fb + 1 * nf + j]; L2 += s_fl[1][fb + 1 * nf + j]; L3 += s_fl[2][fb + 1 * nf + j]; }
+        if (j == N) { L1 += s_fl[0][fb + 2 * nf + i]; L2 += s_fl[1][fb + 2 * nf + i]; L3 += s_fl[2][fb + 2 * nf + i]; }
+        if (i == 0) { L1 += s_fl[0][fb + 3 * nf + j]; L2 += s_fl[1][fb + 3 * nf + j]; L3 += s_fl[2][fb + 3 * nf + j]; }
+    }
+    const R J = Ce * Ax - Cx * Ae;
+
+    // ---- viscous divergence (Theorem 1) ----
+    R Lv2 = 0, Lv3 = 0;
+    if constexpr (AV) {
+        const R eps = act ? a.eps[e] : R(0);
+        R Fv2 = 0, Fv3 = 0, Gv2 = 0, Gv3 = 0;
+        if (act)
+            viscous_flux_at<N, R>(i, j, s_u + el * np, s_v + el * np, s_us + el * 4 * nf,
+                                  s_vs + el * 4 * nf, Ax, Cx, Ae, Ce, h * eps, a.tab, Fv2, Fv3, Gv2, Gv3);
+        // contravariant fluxes: F~v = J grad(xi) . (Fv, Gv), G~v = J grad(eta) . (Fv, Gv)
+        s_Fv[0][t] = Ax * Fv2 + Cx * Gv2;
+        s_Fv[1][t] = Ax * Fv3 + Cx * Gv3;
+        s_Fv[2][t] = Ae * Fv2 + Ce * Gv2;
+        s_Fv[3][t] = Ae * Fv3 + Ce * Gv3;
+        __syncthreads();
+        const int base = el * np;
+#pragma unroll
+        for (int mm = 0; mm < nf; ++mm) {
+            const R di = a.tab.D[i * kMaxNF + mm], dj = a.tab.D[j * kMaxNF + mm];
+            Lv2 += di * s_Fv[0][base + mm * nf + j] + dj * s_Fv[2][base + i * nf + mm];
+            Lv3 += di * s_Fv[1][base + mm * nf + j] + dj * s_Fv[3][base + i * nf + mm];
+        }
+        // faces: (1/(2 w_0)) n_s . (Fv_nbr - Fv_own), n_s outward scaled normal
+        const R hw = R(0.5) * iw0;
+        const int fb = el * 4 * nf;
+        auto face = [&](int s, int k, R snx, R sny) {
+            const int f = fb + s * nf + k;
+            Lv2 += hw * (snx * (s_vn[0][f] - Fv2) + sny * (s_vn[2][f] - Gv2));
+            Lv3 += hw * (snx * (s_vn[1][f] - Fv3) + sny * (s_vn[3][f] - Gv3));
+        };
+        if (j == 0) face(0, i, -Ae, -Ce);
+        if (i == N) face(1, j, Ax, Cx);
+        if (j == N) face(2, i, Ae, Ce);
+        if (i == 0) face(3, j, -Ax, -Cx);
+    }
+
+    // ---- R = (1/J)(-L + S + L^v), S = -(g/2) h (b_x, b_y) ----
+    R bxv = 0, byv = 0;
+    if (act) { bxv = a.m.bx[q]; byv = a.m.by[q]; }
+    const R iJ = act ? R(1) / J : R(0);
+    const R hg = R(0.5) * P.g * h;
+    const R R1 = -L1 * iJ;
+    const R R2 = (-L2 - hg * bxv + Lv2) * iJ;
+    const R R3 = (-L3 - hg * byv + Lv3) * iJ;
+
+    if constexpr (MODE == kModeRhs) {
+        if (act) { a.oh[q] = R1; a.ohu[q] = R2; a.ohv[q] = R3; }
+        return;
+    } else {
+        const R dt = (R)(*a.dt);
+        R nh, nhu, nhv;
+        R d0 = 0, d1 = 0, d2 = 0;
+        if constexpr (MODE == kModeLsrk) {
+            // the first stage has a_1 = 0: the register is not read
+            if (act && a.ca != R(0)) { d0 = a.dh[q]; d1 = a.dhu[q]; d2 = a.dhv[q]; }
+            d0 = a.ca * d0 + dt * R1;
+            d1 = a.ca * d1 + dt * R2;
+            d2 = a.ca * d2 + dt * R3;
+            nh = h + a.cb * d0; nhu = hu + a.cb * d1; nhv = hv + a.cb * d2;
+        } else {
+            R w0 = 0, w1 = 0, w2 = 0;
+            if (act) { w0 = a.h0[q]; w1 = a.hu0[q]; w2 = a.hv0[q]; }
+            nh = a.ca * w0 + a.cb * (h + dt * R1);
+            nhu = a.ca * w1 + a.cb * (hu + dt * R2);
+            nhv = a.ca * w2 + a.cb * (hv + dt * R3);
+        }
+        if (P.limiter_on) {
+            // positivity limiter (eq. PosPres) toward the J-weighted means
+            const R wq = act ? J * a.tab.w[i] * a.tab.w[j] : R(0);
+            R vals[5] = {wq, wq * nh, wq * nhu, wq * nhv, act ? nh : R(3.0e38)};
+            // reduce into the (now free) staging region
+            ElemReduce<N, R, 5>::template run<true>(vals, s_st, t, el, p);
+            const R area = vals[0];
+            const R mh = vals[1] / area, mhu = vals[2] / area, mhv = vals[3] / area;
+            const R mn = vals[4];
+            if (act && mn < R(0)) {
+                R th;
+                if (mh < R(0)) {
+                    th = R(0);
+                    if (p == 0) atomicOr(&a.flags[0], 1);
+                } else {
+                    th = mh / (mh - mn);
+                    th = th < R(1) ? th : R(1);
+                }
+                if (p == 0) atomicAdd(&a.flags[1], 1);
+                nh = th * (nh - mh) + mh;
+                nhu = th * (nhu - mhu) + mhu;
+                nhv = th * (nhv - mhv) + mhv;
+            }
+            if (nh < P.h_tol) { nhu = R(0); nhv = R(0); }
+        }
+        if (act) {
+            a.oh[q] = nh; a.ohu[q] = nhu; a.ohv[q] = nhv;
+            if constexpr (MODE == kModeLsrk) { a.dh[q] = d0; a.dhu[q] = d1; a.dhv[q] = d2; }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Standalone limiter (initial data / esdg_limit)
+// ------------------------------------------------------------------------
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void limit_kernel(Mesh<R> m, Phys<R> P, Tab<R> tab, R *h_,
+                                                            R *hu_, R *hv_, int *flags, int64_t ntiles)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T;
+    __shared__ R s_red[5 * T];
+    const int64_t tile = xcd_tile(ntiles);
+    if (tile < 0) return;
+    const int t = threadIdx.x;
+    const bool lane = t < E * np;
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0, i = p / nf, j = p - i * nf;
+    const int64_t e = tile * E + el;
+    const bool act = lane && (e < m.K);
+    const int64_t q = e * np + p;
+    R nh = 0, nhu = 0, nhv = 0, J = 0;
+    if (act) {
+        nh = h_[q]; nhu = hu_[q]; nhv = hv_[q];
+        J = m.Ce[q] * m.Ax[q] - m.Cx[q] * m.Ae[q];
+    }
+    const R wq = act ? J * tab.w[i] * tab.w[j] : R(0);
+    R vals[5] = {wq, wq * nh, wq * nhu, wq * nhv, act ? nh : R(3.0e38)};
+    ElemReduce<N, R, 5>::template run<true>(vals, s_red, t, el, p);
+    const R area = vals[0];
+    const R mh = vals[1] / area, mhu = vals[2] / area, mhv = vals[3] / area, mn = vals[4];
+    if (!act) return;
+    if (mn < R(0)) {
+        R th;
+        if (mh < R(0)) {
+            th = R(0);
+            if (p == 0) atomicOr(&flags[0], 1);
+        } else {
+            th = mh / (mh - mn);
+            th = th < R(1) ? th : R(1);
+        }
+        if (p == 0) atomicAdd(&flags[1], 1);
+        nh = th * (nh - mh) + mh;
+        nhu = th * (nhu - mhu) + mhu;
+        nhv = th * (nhv - mhv) + mhv;
+    }
+    if (nh < P.h_tol) { nhu = R(0); nhv = R(0); }
+    h_[q] = nh; hu_[q] = nhu; hv_[q] = nhv;
+}
+
+// ------------------------------------------------------------------------
+// Time step bounds: CFL, viscous (AV), Lemma 2.  Minima go to 64 slots per
+// bound by atomicMin on the bit patterns of non-negative doubles (which order
+// like unsigned integers); dt_finalize_kernel reduces and resets them.
+// ------------------------------------------------------------------------
+template <int N, typename R>
+struct DtArgs {
+    Mesh<R> m;
+    Phys<R> P;
+    Tab<R> tab;
+    const R *h, *hu, *hv;
+    const R *eps;              // nullptr without AV
+    unsigned long long *slots; // [3][kDtSlots]
+    double br1_radius;         // spectral radius of 1D BR1 at unit width/viscosity
+    int64_t ntiles;
+};
+
+__device__ __forceinline__ void slot_min(unsigned long long *slot, double v)
+{
+    if (v >= 0.0 && v < __builtin_huge_val()) atomicMin(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void dt_kernel(DtArgs<N, R> a)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
+    __shared__ R s_red[3 * T];
+    __shared__ R s_J[T], s_u[T], s_v[T];
+    const int64_t tile = xcd_tile(a.ntiles);
+    if (tile < 0) return;
+    const int t = threadIdx.x;
+    const bool lane = t < E * np;
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0;
+    const int64_t e0 = tile * E, e = e0 + el;
+    const bool act = lane && (e < a.m.K);
+    const int64_t q = e * np + p;
+    const Phys<R> &P = a.P;
+    R cflb = R(3.0e38), gg = 0, J = 0, u = 0, v = 0;
+    if (act) {
+        const R h = a.h[q], ih = rcp_wet(h, P.h_tol);
+        u = a.hu[q] * ih;
+        v = a.hv[q] * ih;
+        const R c = sqrt(P.g * (h > R(0) ? h : R(0)));
+        const R Ax = a.m.Ax[q], Cx = a.m.Cx[q], Ae = a.m.Ae[q], Ce = a.m.Ce[q];
+        J = Ce * Ax - Cx * Ae;
+        const R lx = fabs(Ax * u + Cx * v) + c * sqrt(Ax * Ax + Cx * Cx);
+        const R le = fabs(Ae * u + Ce * v) + c * sqrt(Ae * Ae + Ce * Ce);
+        if (lx + le > R(0)) cflb = P.cfl * (R(2) / R(nf)) * J / (lx + le);
+        gg = (Ax * Ax + Cx * Cx + Ae * Ae + Ce * Ce) / (J * J);
+    }
+    s_J[t] = J;
+    s_u[t] = u;
+    s_v[t] = v;
+    __syncthreads();
+    // Lemma 2 bounds at the face nodes
+    R posb = R(3.0e38);
+    for (int f = t; f < NF; f += T) {
+        const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+        const int64_t fe = e0 + fel;
+        if (fe >= a.m.K) continue;
+        int fi, fj, ns, kk;
+        int64_t en;
+        side_node<N>(s, k, fi, fj);
+        const int lp = fel * np + fi * nf + fj;
+        const int64_t qo = fe * np + fi * nf + fj;
+        const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+        R snx, sny;
+        if (s == 1) { snx = a.m.Ax[qo]; sny = a.m.Cx[qo]; }
+        else if (s == 3) { snx = -a.m.Ax[qo]; sny = -a.m.Cx[qo]; }
+        else if (s == 2) { snx = a.m.Ae[qo]; sny = a.m.Ce[qo]; }
+        else { snx = -a.m.Ae[qo]; sny = -a.m.Ce[qo]; }
+        const R js = sqrt(snx * snx + sny * sny);
+        const R nx = snx / js, ny = sny / js;
+        const R aa = s_J[lp] / js;
+        const R hm = a.h[qo], hp = a.h[qn];
+        const R ip = rcp_wet(hp, P.h_tol);
+        const R utm = nx * s_u[lp] + ny * s_v[lp];
+        const R utp = nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
+        const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
+        const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
+        const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
+        const R w0 = a.tab.w[0];
+        const R den1 = A + R(2) * au;
+        if (den1 > R(0)) { const R bnd = w0 * aa / den1; posb = bnd < posb ? bnd : posb; }
+        const R den2 = ac * B * (utp - utm);
+        if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0 * aa * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
+    }
+    // per-element viscous bound
+    R viscb = R(3.0e38);
+    {
+        R vals[1] = {-gg};
+        ElemReduce<N, R, 1>::template run<true>(vals, s_red, t, el, p);
+        if (a.eps && act && p == 0) {
+            const R eps = a.eps[e];
+            if (eps > R(0)) viscb = P.cfl_visc * R(4.0 * kLsrkRealLimit) / (R(a.br1_radius) * eps * (-vals[0]));
+        }
+    }
+    // workgroup minima
+    s_red[t] = cflb;
+    s_red[T + t] = viscb;
+    s_red[2 * T + t] = posb;
+    __syncthreads();
+    for (int st = T / 2; st > 0; st >>= 1) {
+        if (t < st) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R o = s_red[c * T + t + st];
+                if (o < s_red[c * T + t]) s_red[c * T + t] = o;
+            }
+        }
+        __syncthreads();
+    }
+    if (t < 3) {
+        const R v = s_red[t * T];
+        if (v < R(1.0e38)) slot_min(&a.slots[t * kDtSlots + (blockIdx.x % kDtSlots)], (double)v);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Diagnostics: per-workgroup partial sums of J w w (h, hu, hv, e, q.R),
+// min h, max h, #dry nodes.
+// ------------------------------------------------------------------------
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void diag_kernel(Mesh<R> m, Phys<R> P, Tab<R> tab, const R *h_,
+                                                           const R *hu_, const R *hv_, const R *b_,
+                                                           const R *r0, const R *r1, const R *r2,
+                                                           double *part)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, T = S::T;
+    __shared__ double s[8][T];
+    const int t = threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * T + t;
+    double v[8] = {0, 0, 0, 0, 0, 1e300, -1e300, 0};
+    if (q < m.K * np) {
+        const int p = (int)(q % np), i = p / nf, j = p - i * nf;
+        const double J = (double)m.Ce[q] * m.Ax[q] - (double)m.Cx[q] * m.Ae[q];
+        const double wq = J * tab.w[i] * tab.w[j];
+        const double h = h_[q], hu = hu_[q], hv = hv_[q], b = b_[q];
+        const double ih = h > P.h_tol ? 1.0 / h : 0.0;
+        const double u = hu * ih, vv = hv * ih, g = P.g;
+        v[0] = wq * h;
+        v[1] = wq * hu;
+        v[2] = wq * hv;
+        v[3] = wq * (0.5 * h * (u * u + vv * vv) + 0.5 * g * h * h + g * h * b);
+        v[4] = wq * ((g * (h + b) - 0.5 * (u * u + vv * vv)) * r0[q] + u * r1[q] + vv * r2[q]);
+        v[5] = h;
+        v[6] = h;
+        v[7] = h > P.h_tol ? 0.0 : 1.0;
+    }
+    for (int c = 0; c < 8; ++c) s[c][t] = v[c];
+    __syncthreads();
+    for (int st = T / 2; st > 0; st >>= 1) {
+        if (t < st) {
+            for (int c = 0; c < 5; ++c) s[c][t] += s[c][t + st];
+            s[5][t] = fmin(s[5][t], s[5][t + st]);
+            s[6][t] = fmax(s[6][t], s[6][t + st]);
+            s[7][t] += s[7][t + st];
+        }
+        __syncthreads();
+    }
+    if (t < 8) part[blockIdx.x * 8 + t] = s[t][0];
+}
+
+// ------------------------------------------------------------------------
+// Precision conversion
+// ------------------------------------------------------------------------
+template <typename A, typename B>
+__global__ void convert_kernel(const A *__restrict__ src, B *__restrict__ dst, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = (B)src[q];
+}
+
+}  // namespace esdg

@@ -1,0 +1,57 @@
+// Launch wrappers: one translation unit per polynomial degree instantiates
+// Launch<N, double> and Launch<N, float>; the runtime dispatches on N.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace esdg {
+
+template <typename R> struct Tab;
+template <typename R> struct Phys;
+
+// Device buffers of one context (typed views are cast per precision).
+struct Bufs {
+    int N = 0;
+    int64_t K = 0;
+    double *x = nullptr, *y = nullptr;      // float64 coordinates
+    void *Ax = nullptr, *Cx = nullptr, *Ae = nullptr, *Ce = nullptr;
+    void *bx = nullptr, *by = nullptr, *bface = nullptr, *b = nullptr;
+    int32_t *nbr = nullptr;
+    int8_t *code = nullptr;
+    void *W[4][3] = {};      // state buffers [buffer][h, hu, hv]: ping-pong, W^n, retry backup
+    void *dU[3] = {};        // LSRK register
+    void *Rb[3] = {};        // right-hand side output scratch
+    void *eps = nullptr;     // [K]
+    void *vtr = nullptr;     // [K][4][nf][4]
+    double *dscal = nullptr; // [0..3] dt bounds, [4] time, [5..7] spare
+    unsigned long long *slots = nullptr;  // [3][kDtSlots]
+    int *flags = nullptr;    // [0] neg mean, [1] limited count, [2] bad dt, [3] bad J
+    double *part = nullptr;  // diagnostics partial sums
+    int64_t part_cap = 0;
+};
+
+struct StageCall {
+    int mode;          // kModeRhs, kModeLsrk, kModeSsp
+    bool av;
+    int in, out, base; // state buffers: input, output, W^n (SSP)
+    bool out_rhs;      // write into Rb instead of W[out]
+    double ca, cb;     // stage coefficients
+};
+
+template <int N, typename R>
+struct Launch {
+    static hipError_t geometry(const Bufs &B, const Tab<double> &td, hipStream_t s);
+    static hipError_t bathymetry(const Bufs &B, const double *b, const Tab<double> &td, hipStream_t s);
+    static hipError_t av(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
+    static hipError_t stage(const Bufs &B, const StageCall &c, const Phys<R> &P, const Tab<R> &t,
+                            hipStream_t s);
+    static hipError_t limit(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
+    static hipError_t dt(const Bufs &B, int in, bool av, const Phys<R> &P, const Tab<R> &t,
+                         double br1_radius, hipStream_t s);
+    static hipError_t diag(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, int64_t *nblocks,
+                           hipStream_t s);
+    static int threads();
+    static int elems_per_block();
+};
+
+}  // namespace esdg

@@ -1,0 +1,821 @@
+// Host runtime of the C ABI declared in include/esdg.h: argument checks,
+// device buffers, the per-step launch sequence and error reporting.  Every
+// numerical step runs in the kernels of esdg_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "esdg.h"
+#include "esdg_kernels.hpp"
+#include "esdg_launch.hpp"
+#include "esdg_tables.hpp"
+
+namespace esdg {
+
+// Reduce the dt slots: dt[0] = step, dt[1..3] = CFL, viscous, Lemma 2
+// bounds; fixed > 0 overrides the step.  Adds the step to *tacc when
+// advance.  Resets the slots to +inf.
+__global__ void dt_finalize_kernel(unsigned long long *slots, double *dt, double fixed, int use_pos,
+                                   int advance, double *tacc, int *flags)
+{
+    __shared__ double s[3][kDtSlots];
+    const int t = threadIdx.x;
+    const unsigned long long inf = 0x7FF0000000000000ull;
+    for (int c = 0; c < 3; ++c) {
+        s[c][t] = __longlong_as_double((long long)slots[c * kDtSlots + t]);
+        slots[c * kDtSlots + t] = inf;
+    }
+    __syncthreads();
+    for (int st = kDtSlots / 2; st > 0; st >>= 1) {
+        if (t < st)
+            for (int c = 0; c < 3; ++c) s[c][t] = fmin(s[c][t], s[c][t + st]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        double step = fixed;
+        if (!(fixed > 0.0)) {
+            step = fmin(s[0][0], s[1][0]);
+            if (use_pos) step = fmin(step, s[2][0]);
+            if (!(step > 0.0) || !(step < __builtin_huge_val())) {
+                atomicOr(&flags[2], 1);
+                step = 0.0;
+            }
+        }
+        dt[0] = step;
+        dt[1] = s[0][0];
+        dt[2] = s[1][0];
+        dt[3] = s[2][0];
+        if (advance) tacc[0] += step;
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+__global__ void fill_int_kernel(int *p, int v, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// Retry support: step <- f * step, time corrected by the removed part.
+__global__ void scale_step_kernel(double *dt, double f, double *tacc)
+{
+    if (threadIdx.x == 0) {
+        const double old = dt[0];
+        dt[0] = old * f;
+        tacc[0] -= old * (1.0 - f);
+    }
+}
+
+__global__ void set_scalar_kernel(double *p, double v)
+{
+    if (threadIdx.x == 0) p[0] = v;
+}
+
+// Metric terms in the ABI's layout: x_xi, x_eta, y_xi, y_eta, J (float64).
+template <typename R>
+__global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const R *Ce, double *out,
+                                    int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double ax = Ax[q], cx = Cx[q], ae = Ae[q], ce = Ce[q];
+    out[q] = ce;             // x_xi
+    out[n + q] = -cx;        // x_eta
+    out[2 * n + q] = -ae;    // y_xi
+    out[3 * n + q] = ax;     // y_eta
+    out[4 * n + q] = ce * ax - cx * ae;
+}
+
+}  // namespace esdg
+
+using namespace esdg;
+
+struct esdg_ctx {
+    int device = 0;
+    int prec = 64;
+    hipStream_t stream = nullptr;
+    esdg_params P{};
+    Bufs B;
+    int N = 0;
+    int64_t K = 0;
+    bool have_mesh = false, have_b = false, have_state = false;
+    int cur = 0;
+    HostTables ht{};
+    Tab<double> td{};
+    Tab<float> tf{};
+    double *stage_d = nullptr;   // float64 staging [5][n] (conversions, geometry output)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_stage, ev_av;
+    size_t ev_next = 0;
+    std::string err = "no error";
+};
+
+namespace {
+
+int fail(esdg_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define CK(expr)                                                                               \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, ESDG_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+int64_t nodes(const esdg_ctx *c) { return c->K * (int64_t)(c->N + 1) * (c->N + 1); }
+size_t rsz(const esdg_ctx *c) { return c->prec == 64 ? sizeof(double) : sizeof(float); }
+
+template <typename R>
+Phys<R> phys(const esdg_ctx *c)
+{
+    Phys<R> p;
+    p.g = (R)c->P.g;
+    p.h_tol = (R)c->P.h_tol;
+    p.eps0 = (R)c->P.eps0;
+    p.sigma_min = (R)c->P.sigma_min;
+    p.sigma_max = (R)c->P.sigma_max;
+    p.cfl = (R)c->P.cfl;
+    p.cfl_visc = (R)c->P.cfl_visc;
+    p.ec = c->P.surface_flux == 1;
+    p.limiter_on = c->P.limiter_on != 0;
+    return p;
+}
+
+template <typename R>
+const Tab<R> &tab(const esdg_ctx *c);
+template <>
+const Tab<double> &tab<double>(const esdg_ctx *c) { return c->td; }
+template <>
+const Tab<float> &tab<float>(const esdg_ctx *c) { return c->tf; }
+
+// Call f(Launch<N,R>{}, R{}) for the context's degree and precision.
+template <typename F>
+hipError_t dispatch(const esdg_ctx *c, F &&f)
+{
+#define ESDG_CASE(n)                                                        \
+    case n:                                                                 \
+        return c->prec == 64 ? f(Launch<n, double>{}, double{}) : f(Launch<n, float>{}, float{});
+    switch (c->N) {
+        ESDG_CASE(2)
+        ESDG_CASE(3)
+        ESDG_CASE(4)
+        ESDG_CASE(5)
+        ESDG_CASE(6)
+        ESDG_CASE(7)
+        ESDG_CASE(8)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef ESDG_CASE
+}
+
+void free_bufs(esdg_ctx *c)
+{
+    Bufs &B = c->B;
+    void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.eps,
+                  B.vtr, B.dscal, B.slots, B.flags, B.part, c->stage_d};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    for (auto &w : B.W)
+        for (void *p : w)
+            if (p) (void)hipFree(p);
+    for (void *p : B.dU)
+        if (p) (void)hipFree(p);
+    for (void *p : B.Rb)
+        if (p) (void)hipFree(p);
+    B = Bufs{};
+    c->stage_d = nullptr;
+    c->have_mesh = c->have_b = c->have_state = false;
+}
+
+hipEvent_t next_event(esdg_ctx *c)
+{
+    if (c->ev_next == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_next++];
+}
+
+// Launch with optional event timing.
+template <typename F>
+int timed(esdg_ctx *ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F &&launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->prof) {
+        a = next_event(ctx);
+        b = next_event(ctx);
+        if (!a || !b) return fail(ctx, ESDG_EHIP, "hipEventCreate failed");
+        CK(hipEventRecord(a, ctx->stream));
+    }
+    CK(launch());
+    if (ctx->prof) {
+        CK(hipEventRecord(b, ctx->stream));
+        log.emplace_back(a, b);
+    }
+    return ESDG_OK;
+}
+
+int launch_av(esdg_ctx *ctx, int buf)
+{
+    return timed(ctx, ctx->ev_av, [&] {
+        return dispatch(ctx, [&](auto L, auto r) {
+            using R = decltype(r);
+            return decltype(L)::av(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+        });
+    });
+}
+
+int launch_stage(esdg_ctx *ctx, const StageCall &sc)
+{
+    return timed(ctx, ctx->ev_stage, [&] {
+        return dispatch(ctx, [&](auto L, auto r) {
+            using R = decltype(r);
+            return decltype(L)::stage(ctx->B, sc, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+        });
+    });
+}
+
+int launch_dt(esdg_ctx *ctx, int buf, double fixed, int advance)
+{
+    const bool av = ctx->P.av_on != 0;
+    if (!(fixed > 0.0)) {
+        CK(dispatch(ctx, [&](auto L, auto r) {
+            using R = decltype(r);
+            return decltype(L)::dt(ctx->B, buf, av, phys<R>(ctx), tab<R>(ctx), kBR1Radius[ctx->N],
+                                   ctx->stream);
+        }));
+    }
+    hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
+                       ctx->B.dscal, fixed, ctx->P.limiter_on ? 1 : 0, advance, ctx->B.dscal + 4,
+                       ctx->B.flags);
+    CK(hipGetLastError());
+    return ESDG_OK;
+}
+
+int reset_flags(esdg_ctx *ctx)
+{
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.flags, 0, 3);
+    CK(hipGetLastError());
+    return ESDG_OK;
+}
+
+int read_flags(esdg_ctx *ctx, int flags[4])
+{
+    CK(hipMemcpyAsync(flags, ctx->B.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+// Copy a float64 host/device array into a context array of the compute precision.
+int upload_field(esdg_ctx *ctx, void *dst, const double *src, int64_t n, int mem)
+{
+    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (ctx->prec == 64) {
+        CK(hipMemcpyAsync(dst, src, n * sizeof(double), k, ctx->stream));
+    } else {
+        const double *s = src;
+        if (!mem) {
+            CK(hipMemcpyAsync(ctx->stage_d, src, n * sizeof(double), k, ctx->stream));
+            s = ctx->stage_d;
+        }
+        hipLaunchKernelGGL((convert_kernel<double, float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           ctx->stream, s, (float *)dst, n);
+        CK(hipGetLastError());
+    }
+    if (!mem) CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int download_field(esdg_ctx *ctx, double *dst, const void *src, int64_t n, int mem)
+{
+    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (ctx->prec == 64) {
+        CK(hipMemcpyAsync(dst, src, n * sizeof(double), k, ctx->stream));
+    } else {
+        double *d = mem ? dst : ctx->stage_d;
+        hipLaunchKernelGGL((convert_kernel<float, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           ctx->stream, (const float *)src, d, n);
+        CK(hipGetLastError());
+        if (!mem) CK(hipMemcpyAsync(dst, ctx->stage_d, n * sizeof(double), k, ctx->stream));
+    }
+    if (!mem) CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+template <typename T>
+int alloc(esdg_ctx *ctx, T **p, size_t bytes)
+{
+    hipError_t e = hipMalloc((void **)p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(ctx, ESDG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return ESDG_OK;
+}
+
+#define TRY(expr)               \
+    do {                        \
+        int st_ = (expr);       \
+        if (st_) return st_;    \
+    } while (0)
+
+bool check_ctx(esdg_ctx *ctx, bool need_state)
+{
+    if (!ctx) return false;
+    if (!ctx->have_mesh || !ctx->have_b || (need_state && !ctx->have_state)) {
+        fail(ctx, ESDG_EINVAL, "call order: upload_mesh, set_bathymetry and set_state first");
+        return false;
+    }
+    return hipSetDevice(ctx->device) == hipSuccess;
+}
+
+int run_rhs(esdg_ctx *ctx, int buf)
+{
+    if (ctx->P.av_on) TRY(launch_av(ctx, buf));
+    StageCall sc{kModeRhs, ctx->P.av_on != 0, buf, buf, buf, true, 0.0, 0.0};
+    return launch_stage(ctx, sc);
+}
+
+}  // namespace
+
+extern "C" {
+
+int esdg_abi_version(void) { return 100; }
+
+void esdg_default_params(esdg_params *p, int N)
+{
+    if (!p) return;
+    const double s0 = -4.0 * std::log10((double)(N > 0 ? N : 1));
+    p->g = 9.81;
+    p->h_tol = 1e-4;
+    p->eps0 = 0.0;
+    p->sigma_min = s0 - 1.0;
+    p->sigma_max = s0 + 1.0;
+    p->cfl = 0.5;
+    p->cfl_visc = 0.5;
+    p->surface_flux = 0;
+    p->av_on = 0;
+    p->limiter_on = 0;
+    p->integrator = 0;
+    p->max_dt_retries = 0;
+}
+
+const char *esdg_last_error(const esdg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int esdg_create(esdg_ctx **out, int device, int precision)
+{
+    if (!out) return ESDG_EINVAL;
+    *out = nullptr;
+    if (precision != 64 && precision != 32) return ESDG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ESDG_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return ESDG_EHIP;
+    esdg_ctx *c = new (std::nothrow) esdg_ctx;
+    if (!c) return ESDG_ENOMEM;
+    c->device = device;
+    c->prec = precision;
+    esdg_default_params(&c->P, 3);
+    *out = c;
+    return ESDG_OK;
+}
+
+int esdg_destroy(esdg_ctx *ctx)
+{
+    if (!ctx) return ESDG_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_bufs(ctx);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return ESDG_OK;
+}
+
+int esdg_set_stream(esdg_ctx *ctx, void *s)
+{
+    if (!ctx) return ESDG_EINVAL;
+    ctx->stream = (hipStream_t)s;
+    return ESDG_OK;
+}
+
+int esdg_set_params(esdg_ctx *ctx, const esdg_params *p)
+{
+    if (!ctx || !p) return ESDG_EINVAL;
+    if (!(p->g > 0) || !(p->cfl > 0) || !(p->cfl_visc > 0) || !(p->eps0 >= 0) ||
+        !(p->sigma_max > p->sigma_min) || p->surface_flux < 0 || p->surface_flux > 1 || p->integrator < 0 ||
+        p->integrator > 1 || p->max_dt_retries < 0 || !std::isfinite(p->h_tol))
+        return fail(ctx, ESDG_EINVAL, "invalid parameter value");
+    ctx->P = *p;
+    return ESDG_OK;
+}
+
+int esdg_get_params(const esdg_ctx *ctx, esdg_params *p)
+{
+    if (!ctx || !p) return ESDG_EINVAL;
+    *p = ctx->P;
+    return ESDG_OK;
+}
+
+int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const double *y,
+                     const int32_t *nbr_elem, const int8_t *nbr_side, const int8_t *flip, int mem)
+{
+    if (!ctx) return ESDG_EINVAL;
+    if (N < 2 || N > kMaxN) return fail(ctx, ESDG_EINVAL, "N=%d outside [2, %d]", N, kMaxN);
+    if (K < 1 || K > (int64_t)INT32_MAX) return fail(ctx, ESDG_EINVAL, "K=%lld out of range", (long long)K);
+    if (!x || !y || !nbr_elem || !nbr_side || !flip) return fail(ctx, ESDG_EINVAL, "null pointer");
+    CK(hipSetDevice(ctx->device));
+    // face map to the host for validation
+    std::vector<int32_t> ne(4 * K);
+    std::vector<int8_t> ns(4 * K), fl(4 * K);
+    if (mem) {
+        CK(hipMemcpy(ne.data(), nbr_elem, 4 * K * sizeof(int32_t), hipMemcpyDeviceToHost));
+        CK(hipMemcpy(ns.data(), nbr_side, 4 * K, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(fl.data(), flip, 4 * K, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(ne.data(), nbr_elem, 4 * K * sizeof(int32_t));
+        std::memcpy(ns.data(), nbr_side, 4 * K);
+        std::memcpy(fl.data(), flip, 4 * K);
+    }
+    std::vector<int8_t> code(4 * K);
+    for (int64_t e = 0; e < K; ++e)
+        for (int s = 0; s < 4; ++s) {
+            const int64_t f = e * 4 + s;
+            const int32_t en = ne[f];
+            const int sn = ns[f], fv = fl[f];
+            if (en < 0 || en >= K || sn < 0 || sn > 3 || (fv != 0 && fv != 1))
+                return fail(ctx, ESDG_EMESH, "face map entry (%lld,%d) out of range", (long long)e, s);
+            const int64_t g = (int64_t)en * 4 + sn;
+            if (ne[g] != e || ns[g] != s || fl[g] != fv)
+                return fail(ctx, ESDG_EMESH, "face map not symmetric at element %lld side %d", (long long)e, s);
+            code[f] = (int8_t)(sn | (fv << 2));
+        }
+    free_bufs(ctx);
+    ctx->N = N;
+    ctx->K = K;
+    build_tables(N, ctx->ht);
+    std::memset(&ctx->td, 0, sizeof(ctx->td));
+    std::memset(&ctx->tf, 0, sizeof(ctx->tf));
+    for (int i = 0; i <= N; ++i) {
+        ctx->td.w[i] = (double)ctx->ht.w[i];
+        ctx->tf.w[i] = (float)ctx->ht.w[i];
+        for (int j = 0; j <= N; ++j) {
+            ctx->td.D[i * kMaxNF + j] = (double)ctx->ht.D[i][j];
+            ctx->tf.D[i * kMaxNF + j] = (float)ctx->ht.D[i][j];
+            ctx->td.Vinv[i * kMaxNF + j] = (double)ctx->ht.Vinv[i][j];
+            ctx->tf.Vinv[i * kMaxNF + j] = (float)ctx->ht.Vinv[i][j];
+        }
+    }
+    Bufs &B = ctx->B;
+    B.N = N;
+    B.K = K;
+    const int64_t n = nodes(ctx);
+    const int nf = N + 1;
+    const size_t r = rsz(ctx);
+    TRY(alloc(ctx, &B.x, n * sizeof(double)));
+    TRY(alloc(ctx, &B.y, n * sizeof(double)));
+    void **rn[] = {&B.Ax, &B.Cx, &B.Ae, &B.Ce, &B.bx, &B.by, &B.b, &B.dU[0], &B.dU[1], &B.dU[2],
+                   &B.Rb[0], &B.Rb[1], &B.Rb[2]};
+    for (void **p : rn) TRY(alloc(ctx, p, n * r));
+    for (auto &w : B.W)
+        for (void *&p : w) TRY(alloc(ctx, &p, n * r));
+    TRY(alloc(ctx, &B.bface, K * 4 * nf * r));
+    TRY(alloc(ctx, &B.nbr, K * 4 * sizeof(int32_t)));
+    TRY(alloc(ctx, &B.code, K * 4));
+    TRY(alloc(ctx, &B.eps, K * r));
+    TRY(alloc(ctx, &B.vtr, K * 4 * nf * 4 * r));
+    TRY(alloc(ctx, &B.dscal, 8 * sizeof(double)));
+    TRY(alloc(ctx, &B.slots, 3 * kDtSlots * sizeof(unsigned long long)));
+    TRY(alloc(ctx, &B.flags, 4 * sizeof(int)));
+    int64_t T = 0;
+    (void)dispatch(ctx, [&](auto L, auto) {
+        T = decltype(L)::threads();
+        return hipSuccess;
+    });
+    B.part_cap = (n + T - 1) / T;
+    TRY(alloc(ctx, &B.part, B.part_cap * 8 * sizeof(double)));
+    TRY(alloc(ctx, &ctx->stage_d, 5 * n * sizeof(double)));
+    // zero-filled registers and traces
+    for (void *p : B.dU) CK(hipMemsetAsync(p, 0, n * r, ctx->stream));
+    CK(hipMemsetAsync(B.vtr, 0, K * 4 * nf * 4 * r, ctx->stream));
+    CK(hipMemsetAsync(B.eps, 0, K * r, ctx->stream));
+    CK(hipMemsetAsync(B.dscal, 0, 8 * sizeof(double), ctx->stream));
+    CK(hipMemsetAsync(B.flags, 0, 4 * sizeof(int), ctx->stream));
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(3 * kDtSlots), 0, ctx->stream, B.slots,
+                       0x7FF0000000000000ull, 3 * kDtSlots);
+    CK(hipGetLastError());
+    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    CK(hipMemcpyAsync(B.x, x, n * sizeof(double), k, ctx->stream));
+    CK(hipMemcpyAsync(B.y, y, n * sizeof(double), k, ctx->stream));
+    CK(hipMemcpyAsync(B.nbr, ne.data(), 4 * K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(B.code, code.data(), 4 * K, hipMemcpyHostToDevice, ctx->stream));
+    CK(dispatch(ctx, [&](auto L, auto) { return decltype(L)::geometry(ctx->B, ctx->td, ctx->stream); }));
+    int flags[4];
+    TRY(read_flags(ctx, flags));
+    if (flags[3]) {
+        free_bufs(ctx);
+        return fail(ctx, ESDG_EMESH, "Jacobian not positive at some node");
+    }
+    ctx->have_mesh = true;
+    ctx->cur = 0;
+    return ESDG_OK;
+}
+
+int esdg_set_bathymetry(esdg_ctx *ctx, const double *b, int mem)
+{
+    if (!ctx || !b) return ESDG_EINVAL;
+    if (!ctx->have_mesh) return fail(ctx, ESDG_EINVAL, "upload_mesh first");
+    CK(hipSetDevice(ctx->device));
+    const int64_t n = nodes(ctx);
+    const double *db = b;
+    if (!mem) {
+        CK(hipMemcpyAsync(ctx->stage_d, b, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        db = ctx->stage_d;
+    }
+    CK(dispatch(ctx, [&](auto L, auto) { return decltype(L)::bathymetry(ctx->B, db, ctx->td, ctx->stream); }));
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->have_b = true;
+    return ESDG_OK;
+}
+
+int esdg_set_state(esdg_ctx *ctx, const double *h, const double *hu, const double *hv, int mem)
+{
+    if (!ctx || !h || !hu || !hv) return ESDG_EINVAL;
+    if (!ctx->have_mesh) return fail(ctx, ESDG_EINVAL, "upload_mesh first");
+    CK(hipSetDevice(ctx->device));
+    const int64_t n = nodes(ctx);
+    ctx->cur = 0;
+    TRY(upload_field(ctx, ctx->B.W[0][0], h, n, mem));
+    TRY(upload_field(ctx, ctx->B.W[0][1], hu, n, mem));
+    TRY(upload_field(ctx, ctx->B.W[0][2], hv, n, mem));
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal + 4, 0.0);
+    CK(hipGetLastError());
+    ctx->have_state = true;
+    return ESDG_OK;
+}
+
+int esdg_get_state(esdg_ctx *ctx, double *h, double *hu, double *hv, int mem)
+{
+    if (!ctx || !h || !hu || !hv) return ESDG_EINVAL;
+    if (!ctx->have_state) return fail(ctx, ESDG_EINVAL, "no state");
+    CK(hipSetDevice(ctx->device));
+    const int64_t n = nodes(ctx);
+    TRY(download_field(ctx, h, ctx->B.W[ctx->cur][0], n, mem));
+    TRY(download_field(ctx, hu, ctx->B.W[ctx->cur][1], n, mem));
+    TRY(download_field(ctx, hv, ctx->B.W[ctx->cur][2], n, mem));
+    return ESDG_OK;
+}
+
+int esdg_rhs(esdg_ctx *ctx, double *rh, double *rhu, double *rhv, int mem)
+{
+    if (!rh || !rhu || !rhv) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_ctx(ctx, true)) return ctx ? ESDG_EINVAL : ESDG_EINVAL;
+    TRY(run_rhs(ctx, ctx->cur));
+    const int64_t n = nodes(ctx);
+    TRY(download_field(ctx, rh, ctx->B.Rb[0], n, mem));
+    TRY(download_field(ctx, rhu, ctx->B.Rb[1], n, mem));
+    TRY(download_field(ctx, rhv, ctx->B.Rb[2], n, mem));
+    return ESDG_OK;
+}
+
+int esdg_limit(esdg_ctx *ctx, int64_t *n_limited)
+{
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    TRY(reset_flags(ctx));
+    CK(dispatch(ctx, [&](auto L, auto r) {
+        using R = decltype(r);
+        return decltype(L)::limit(ctx->B, ctx->cur, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+    }));
+    int flags[4];
+    TRY(read_flags(ctx, flags));
+    if (n_limited) *n_limited = flags[1];
+    if (flags[0]) return fail(ctx, ESDG_ENEGMEAN, "negative element mean in the limiter");
+    return ESDG_OK;
+}
+
+int esdg_compute_dt(esdg_ctx *ctx, double out[4])
+{
+    if (!out) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    TRY(reset_flags(ctx));
+    if (ctx->P.av_on) TRY(launch_av(ctx, ctx->cur));
+    TRY(launch_dt(ctx, ctx->cur, 0.0, 0));
+    CK(hipMemcpyAsync(out, ctx->B.dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
+{
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    if (nsteps < 0) return fail(ctx, ESDG_EINVAL, "nsteps < 0");
+    const bool av = ctx->P.av_on != 0;
+    const bool adaptive = !(dt > 0.0);
+    const bool ssp = ctx->P.integrator == 1;
+    const int retries = ctx->P.max_dt_retries;
+    TRY(reset_flags(ctx));
+    int status = ESDG_OK;
+    for (int it = 0; it < nsteps; ++it) {
+        const int base = ctx->cur;
+        const int backup = 3;
+        if (retries > 0) {
+            const int64_t n = nodes(ctx);
+            for (int c = 0; c < 3; ++c)
+                CK(hipMemcpyAsync(ctx->B.W[backup][c], ctx->B.W[base][c], n * rsz(ctx),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+            TRY(reset_flags(ctx));
+        }
+        // step size (AV at W^n first: the viscous bound needs the viscosity)
+        bool av_fresh = false;
+        if (adaptive && av) {
+            TRY(launch_av(ctx, base));
+            av_fresh = true;
+        }
+        TRY(launch_dt(ctx, base, adaptive ? 0.0 : dt, 1));
+        for (int attempt = 0;; ++attempt) {
+            int in = base;
+            if (!ssp) {
+                for (int k = 0; k < 5; ++k) {
+                    const int out = (in == 0) ? 1 : 0;
+                    if (av && !(k == 0 && av_fresh)) TRY(launch_av(ctx, in));
+                    StageCall sc{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k]};
+                    TRY(launch_stage(ctx, sc));
+                    in = out;
+                }
+                ctx->cur = in;
+            } else {
+                const int o1 = (base + 1) % 3, o2 = (base + 2) % 3;
+                const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
+                const int outs[3] = {o1, o2, base};
+                for (int k = 0; k < 3; ++k) {
+                    if (av && !(k == 0 && av_fresh)) TRY(launch_av(ctx, in));
+                    StageCall sc{kModeSsp, av, in, outs[k], base, false, al[k], be[k]};
+                    TRY(launch_stage(ctx, sc));
+                    in = outs[k];
+                }
+                ctx->cur = base;
+            }
+            if (retries <= 0) break;
+            int flags[4];
+            TRY(read_flags(ctx, flags));
+            if (!flags[0] || attempt >= retries) {
+                if (flags[0]) status = ESDG_ENEGMEAN;
+                break;
+            }
+            // negative mean: restore W^n and retry with half the step
+            const int64_t n = nodes(ctx);
+            for (int c = 0; c < 3; ++c)
+                CK(hipMemcpyAsync(ctx->B.W[base][c], ctx->B.W[backup][c], n * rsz(ctx),
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+            ctx->cur = base;
+            hipLaunchKernelGGL(scale_step_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal, 0.5,
+                               ctx->B.dscal + 4);
+            CK(hipGetLastError());
+            TRY(reset_flags(ctx));
+            av_fresh = false;
+        }
+    }
+    int flags[4];
+    TRY(read_flags(ctx, flags));
+    if (t_out) CK(hipMemcpy(t_out, ctx->B.dscal + 4, sizeof(double), hipMemcpyDeviceToHost));
+    if (flags[2]) return fail(ctx, ESDG_EDTPOS, "no admissible time step");
+    if (status == ESDG_OK && flags[0] && retries <= 0) status = ESDG_ENEGMEAN;
+    if (status == ESDG_ENEGMEAN) return fail(ctx, ESDG_ENEGMEAN, "negative element mean in the limiter");
+    return ESDG_OK;
+}
+
+int esdg_get_time(esdg_ctx *ctx, double *t)
+{
+    if (!ctx || !t || !ctx->have_mesh) return ESDG_EINVAL;
+    CK(hipSetDevice(ctx->device));
+    CK(hipMemcpyAsync(t, ctx->B.dscal + 4, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int esdg_set_time(esdg_ctx *ctx, double t)
+{
+    if (!ctx || !ctx->have_mesh) return ESDG_EINVAL;
+    CK(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal + 4, t);
+    CK(hipGetLastError());
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int esdg_diagnostics(esdg_ctx *ctx, double out[8])
+{
+    if (!out) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    TRY(run_rhs(ctx, ctx->cur));
+    int64_t nb = 0;
+    CK(dispatch(ctx, [&](auto L, auto r) {
+        using R = decltype(r);
+        return decltype(L)::diag(ctx->B, ctx->cur, phys<R>(ctx), tab<R>(ctx), &nb, ctx->stream);
+    }));
+    std::vector<double> part(nb * 8);
+    CK(hipMemcpyAsync(part.data(), ctx->B.part, nb * 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    double acc[8] = {0, 0, 0, 0, 0, INFINITY, -INFINITY, 0};
+    for (int64_t b = 0; b < nb; ++b) {
+        for (int c = 0; c < 5; ++c) acc[c] += part[b * 8 + c];
+        acc[5] = std::fmin(acc[5], part[b * 8 + 5]);
+        acc[6] = std::fmax(acc[6], part[b * 8 + 6]);
+        acc[7] += part[b * 8 + 7];
+    }
+    std::memcpy(out, acc, sizeof acc);
+    return ESDG_OK;
+}
+
+int esdg_get_eps(esdg_ctx *ctx, double *eps, int mem)
+{
+    if (!eps) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    if (ctx->P.av_on) {
+        TRY(launch_av(ctx, ctx->cur));
+    } else {
+        CK(hipMemsetAsync(ctx->B.eps, 0, ctx->K * rsz(ctx), ctx->stream));
+    }
+    return download_field(ctx, eps, ctx->B.eps, ctx->K, mem);
+}
+
+int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, double *yeta, double *J,
+                      int mem)
+{
+    if (!ctx || !ctx->have_mesh || !xxi || !xeta || !yxi || !yeta || !J) return ESDG_EINVAL;
+    CK(hipSetDevice(ctx->device));
+    const int64_t n = nodes(ctx);
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (ctx->prec == 64)
+        hipLaunchKernelGGL((geometry_out_kernel<double>), dim3(g), dim3(256), 0, ctx->stream,
+                           (const double *)ctx->B.Ax, (const double *)ctx->B.Cx, (const double *)ctx->B.Ae,
+                           (const double *)ctx->B.Ce, ctx->stage_d, n);
+    else
+        hipLaunchKernelGGL((geometry_out_kernel<float>), dim3(g), dim3(256), 0, ctx->stream,
+                           (const float *)ctx->B.Ax, (const float *)ctx->B.Cx, (const float *)ctx->B.Ae,
+                           (const float *)ctx->B.Ce, ctx->stage_d, n);
+    CK(hipGetLastError());
+    double *outs[5] = {xxi, xeta, yxi, yeta, J};
+    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int c = 0; c < 5; ++c)
+        CK(hipMemcpyAsync(outs[c], ctx->stage_d + c * n, n * sizeof(double), k, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int esdg_profile(esdg_ctx *ctx, int enable)
+{
+    if (!ctx) return ESDG_EINVAL;
+    ctx->prof = enable != 0;
+    return ESDG_OK;
+}
+
+int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_n, double *av_ms, int64_t *av_n)
+{
+    if (!ctx) return ESDG_EINVAL;
+    CK(hipSetDevice(ctx->device));
+    CK(hipStreamSynchronize(ctx->stream));
+    double s = 0, a = 0;
+    for (auto &pr : ctx->ev_stage) {
+        float ms = 0;
+        CK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        s += ms;
+    }
+    for (auto &pr : ctx->ev_av) {
+        float ms = 0;
+        CK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        a += ms;
+    }
+    if (stage_ms) *stage_ms = s;
+    if (stage_n) *stage_n = (int64_t)ctx->ev_stage.size();
+    if (av_ms) *av_ms = a;
+    if (av_n) *av_n = (int64_t)ctx->ev_av.size();
+    ctx->ev_stage.clear();
+    ctx->ev_av.clear();
+    ctx->ev_next = 0;
+    return ESDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+"""ctypes binding of the C ABI in ``include/esdg.h`` (argument marshalling only).
+
+Every computation runs in the HIP library ``libesdg.so`` next to this file;
+there is no CPU fallback: if the library is missing, loading it raises.
+Arrays may be numpy float64 arrays (host memory) or contiguous float64 torch
+CUDA tensors (device memory, passed by pointer; the copy is ordered on the
+solver's stream).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesdg.so")
+
+OK, EINVAL, ENOMEM, EHIP, EMESH, ENEGMEAN, EDTPOS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EMESH: "EMESH", ENEGMEAN: "ENEGMEAN",
+          EDTPOS: "EDTPOS", ENONFINITE: "ENONFINITE"}
+
+
+class EsdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("g", C.c_double), ("h_tol", C.c_double), ("eps0", C.c_double),
+                ("sigma_min", C.c_double), ("sigma_max", C.c_double), ("cfl", C.c_double),
+                ("cfl_visc", C.c_double), ("surface_flux", C.c_int), ("av_on", C.c_int),
+                ("limiter_on", C.c_int), ("integrator", C.c_int), ("max_dt_retries", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libesdg.so (built by ``paper_1804_02221_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1804_02221_amd/build.py "
+                              "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        sig = {
+            "esdg_default_params": ([P, I], None),
+            "esdg_create": ([P, I, I], I),
+            "esdg_destroy": ([P], I),
+            "esdg_set_stream": ([P, P], I),
+            "esdg_set_params": ([P, P], I),
+            "esdg_get_params": ([P, P], I),
+            "esdg_upload_mesh": ([P, I, I64, P, P, P, P, P, I], I),
+            "esdg_set_bathymetry": ([P, P, I], I),
+            "esdg_set_state": ([P, P, P, P, I], I),
+            "esdg_get_state": ([P, P, P, P, I], I),
+            "esdg_rhs": ([P, P, P, P, I], I),
+            "esdg_limit": ([P, P], I),
+            "esdg_compute_dt": ([P, P], I),
+            "esdg_step": ([P, I, D, P], I),
+            "esdg_get_time": ([P, P], I),
+            "esdg_set_time": ([P, D], I),
+            "esdg_diagnostics": ([P, P], I),
+            "esdg_get_eps": ([P, P, I], I),
+            "esdg_get_geometry": ([P, P, P, P, P, P, I], I),
+            "esdg_profile": ([P, I], I),
+            "esdg_profile_read": ([P, P, P, P, P], I),
+            "esdg_last_error": ([P], C.c_char_p),
+            "esdg_abi_version": ([], I),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names of the ABI entry points the binding expects."""
+    lib()
+    return [n for n in dir(_lib) if n.startswith("esdg_")]
+
+
+def default_params(N: int = 3, **kw) -> Params:
+    p = Params()
+    lib().esdg_default_params(C.byref(p), int(N))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class _Arg:
+    """Pointer + memory kind of a float64 array argument."""
+
+    def __init__(self, a, n=None, dtype=np.float64):
+        if _is_torch(a):
+            import torch
+            want = {np.float64: torch.float64, np.int32: torch.int32, np.int8: torch.int8}[dtype]
+            if a.dtype != want or not a.is_contiguous() or not a.is_cuda:
+                raise TypeError(f"expected a contiguous CUDA tensor of {want}")
+            self.keep = a
+            self.ptr = C.c_void_p(a.data_ptr())
+            self.mem = 1
+            size = a.numel()
+        else:
+            arr = np.ascontiguousarray(a, dtype=dtype)
+            self.keep = arr
+            self.ptr = arr.ctypes.data_as(C.c_void_p)
+            self.mem = 0
+            size = arr.size
+        if n is not None and size != n:
+            raise ValueError(f"array has {size} entries, expected {n}")
+
+
+class Solver:
+    """One solver context (one mesh, one degree) on one GPU."""
+
+    def __init__(self, device: int = 0, precision: int = 64, stream=None):
+        self._ctx = C.c_void_p()
+        st = lib().esdg_create(C.byref(self._ctx), int(device), int(precision))
+        if st != OK:
+            raise EsdgError(st, "esdg_create failed")
+        self.device = device
+        self.precision = precision
+        self.N = None
+        self.K = None
+        if stream is not None:
+            self.set_stream(stream)
+
+    # -- plumbing -------------------------------------------------------
+    def _check(self, st):
+        if st != OK:
+            raise EsdgError(st, lib().esdg_last_error(self._ctx).decode())
+        return st
+
+    def close(self):
+        if self._ctx:
+            lib().esdg_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def n_nodes(self):
+        return 0 if self.N is None else self.K * (self.N + 1) ** 2
+
+    def set_stream(self, stream):
+        """stream: an int handle or a torch.cuda.Stream."""
+        h = getattr(stream, "cuda_stream", stream)
+        self._check(lib().esdg_set_stream(self._ctx, C.c_void_p(int(h) if h else 0)))
+
+    def set_params(self, P: Params | None = None, **kw):
+        if P is None:
+            P = default_params(self.N or 3)
+        for k, v in kw.items():
+            setattr(P, k, v)
+        self._check(lib().esdg_set_params(self._ctx, C.byref(P)))
+        return P
+
+    def get_params(self) -> Params:
+        P = Params()
+        self._check(lib().esdg_get_params(self._ctx, C.byref(P)))
+        return P
+
+    # -- setup ----------------------------------------------------------
+    def upload_mesh(self, N, K=None, x=None, y=None, nbr_elem=None, nbr_side=None, flip=None):
+        """upload_mesh(mesh) with a mesh object (N, x, y, nbr_elem, nbr_side,
+        flip attributes) or upload_mesh(N, K, x, y, nbr_elem, nbr_side, flip)."""
+        if not isinstance(N, int):
+            m = N
+            N, x, y, nbr_elem, nbr_side, flip = m.N, m.x, m.y, m.nbr_elem, m.nbr_side, m.flip
+            K = x.shape[0]
+        n = K * (N + 1) ** 2
+        ax, ay = _Arg(x, n), _Arg(y, n)
+        ne = _Arg(nbr_elem, 4 * K, np.int32)
+        ns = _Arg(nbr_side, 4 * K, np.int8)
+        fl = _Arg(flip, 4 * K, np.int8)
+        mems = {ax.mem, ay.mem, ne.mem, ns.mem, fl.mem}
+        if len(mems) != 1:
+            raise ValueError("mix of host and device arrays")
+        self._check(lib().esdg_upload_mesh(self._ctx, int(N), int(K), ax.ptr, ay.ptr, ne.ptr, ns.ptr,
+                                           fl.ptr, ax.mem))
+        self.N, self.K = int(N), int(K)
+
+    def set_bathymetry(self, b):
+        a = _Arg(b, self.n_nodes)
+        self._check(lib().esdg_set_bathymetry(self._ctx, a.ptr, a.mem))
+
+    def set_state(self, h, hu, hv):
+        a, b, c = _Arg(h, self.n_nodes), _Arg(hu, self.n_nodes), _Arg(hv, self.n_nodes)
+        if len({a.mem, b.mem, c.mem}) != 1:
+            raise ValueError("mix of host and device arrays")
+        self._check(lib().esdg_set_state(self._ctx, a.ptr, b.ptr, c.ptr, a.mem))
+
+    # -- outputs ----------------------------------------------------------
+    def _outs(self, count, size, device):
+        if device:
+            import torch
+            return [torch.empty(size, dtype=torch.float64, device=f"cuda:{self.device}") for _ in range(count)]
+        return [np.empty(size) for _ in range(count)]
+
+    def _shape(self, arrs):
+        if self.N is None:
+            return arrs
+        return [a.reshape(self.K, (self.N + 1) ** 2) for a in arrs]
+
+    def get_state(self, device: bool = False):
+        outs = self._outs(3, self.n_nodes, device)
+        ps = [_Arg(o) for o in outs]
+        self._check(lib().esdg_get_state(self._ctx, ps[0].ptr, ps[1].ptr, ps[2].ptr, ps[0].mem))
+        return self._shape(outs)
+
+    def rhs(self, device: bool = False):
+        outs = self._outs(3, self.n_nodes, device)
+        ps = [_Arg(o) for o in outs]
+        self._check(lib().esdg_rhs(self._ctx, ps[0].ptr, ps[1].ptr, ps[2].ptr, ps[0].mem))
+        return self._shape(outs)
+
+    def limit(self):
+        """Returns (n_limited, status); status ENEGMEAN is not raised."""
+        n = C.c_int64(0)
+        st = lib().esdg_limit(self._ctx, C.byref(n))
+        if st not in (OK, ENEGMEAN):
+            self._check(st)
+        return int(n.value), st
+
+    def compute_dt(self):
+        out = np.zeros(4)
+        self._check(lib().esdg_compute_dt(self._ctx, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def step(self, nsteps: int, dt: float = 0.0, raise_negmean: bool = True):
+        t = C.c_double(0.0)
+        st = lib().esdg_step(self._ctx, int(nsteps), float(dt), C.byref(t))
+        if st == ENEGMEAN and not raise_negmean:
+            return t.value, st
+        self._check(st)
+        return t.value, st
+
+    def get_time(self):
+        t = C.c_double(0.0)
+        self._check(lib().esdg_get_time(self._ctx, C.byref(t)))
+        return t.value
+
+    def set_time(self, t: float):
+        self._check(lib().esdg_set_time(self._ctx, float(t)))
+
+    def diagnostics(self):
+        out = np.zeros(8)
+        self._check(lib().esdg_diagnostics(self._ctx, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def get_eps(self, device: bool = False):
+        (o,) = self._outs(1, self.K, device)
+        a = _Arg(o)
+        self._check(lib().esdg_get_eps(self._ctx, a.ptr, a.mem))
+        return o
+
+    def get_geometry(self):
+        outs = self._outs(5, self.n_nodes, False)
+        ps = [_Arg(o) for o in outs]
+        self._check(lib().esdg_get_geometry(self._ctx, *[p.ptr for p in ps], 0))
+        return dict(zip(("xxi", "xeta", "yxi", "yeta", "J"), self._shape(outs)))
+
+    def profile(self, enable: bool = True):
+        self._check(lib().esdg_profile(self._ctx, int(bool(enable))))
+
+    def profile_read(self):
+        sm, sn, am, an = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
+        self._check(lib().esdg_profile_read(self._ctx, C.byref(sm), C.byref(sn), C.byref(am), C.byref(an)))
+        return dict(stage_ms=sm.value, stage_launches=sn.value, av_ms=am.value, av_launches=an.value)
+
+
+def solver_for(workload, device: int = 0, precision: int = 64, **params) -> Solver:
+    """Solver with a workload's mesh, bathymetry and state uploaded."""
+    s = Solver(device, precision)
+    s.upload_mesh(workload.mesh)
+    P = default_params(workload.mesh.N)
+    for k, v in {**workload.params, **params}.items():
+        setattr(P, k, v)
+    s.set_params(P)
+    s.set_bathymetry(workload.b)
+    s.set_state(workload.h, workload.hu, workload.hv)
+    return s
