@@ -51,14 +51,6 @@ def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int) -> 
     return (per_node * n + per_elem * K) * real_bytes
 
 
-def av_bytes(N: int, K: int, real_bytes: int) -> float:
-    """Algorithmic bytes of the viscosity kernel: W (3/node), the four metric
-    directions on the face nodes (16(N+1)/element); writes the viscosity
-    (1/element) and the viscous face fluxes (16(N+1)/element)."""
-    nf = N + 1
-    return (3 * K * nf * nf + 16 * nf * K + K + 16 * nf * K) * real_bytes
-
-
 def cpu_baseline(N: int, n_patch: int):
     import oracle
     from paper_1804_02221_amd.inputs import smooth_sweep
@@ -140,14 +132,33 @@ def main():
                    stage_mean_ms=stage_mean_ms, stage_launches=stage_launch,
                    stage_bytes_per_launch=per_step / 5,
                    stage_GBs=achieved,
-                   av_mean_ms=prof["av_ms"] / max(prof["av_launches"], 1),
-                   av_GBs=(av_bytes(N, K, rb) * prof["av_launches"]) / max(prof["av_ms"] * 1e-3, 1e-12) / 1e9
-                   if av else None)
+                   av_ms_per_stage=prof["av_ms"] / (5 * args.steps),
+                   av_launches=prof["av_launches"])
         s.close()
         del w
         return res
 
+    def memcopy_probe(nbytes):
+        # empirical MemCopy roofline: device copy of (bytes read + written)/2
+        n = int(nbytes // 2 // 8)
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 10
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del src, dst
+        return dict(bytes=2 * n * 8, mean_ms=ms, GBs=2 * n * 8 / (ms * 1e-3) / 1e9)
+
     main_res = run(args.N)
+    log("memcopy probe")
+    mc = memcopy_probe(main_res["stage_bytes_per_launch"])
     sweep = []
     for tok in [t for t in args.sweep.split(",") if t.strip()]:
         r = run(int(tok))
@@ -186,7 +197,10 @@ def main():
             "mean_launch_ms": main_res["stage_mean_ms"],
         },
         "cpu_baseline": cpu,
-        "av_kernel": {"mean_launch_ms": main_res["av_mean_ms"], "GBs": main_res["av_GBs"]},
+        "viscosity_kernels": {"ms_per_stage": main_res["av_ms_per_stage"],
+                              "launches": main_res["av_launches"]},
+        "memcopy_roofline": {"GBs": mc["GBs"], "bytes": mc["bytes"],
+                             "stage_frac": main_res["stage_GBs"] / mc["GBs"]},
     }
     if sweep:
         out["sweep"] = sweep

@@ -72,26 +72,67 @@ hipError_t Launch<N, R>::bathymetry(const Bufs &B, const double *b, const Tab<do
 }
 
 template <int N, typename R>
-hipError_t Launch<N, R>::av(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
+hipError_t Launch<N, R>::indicator(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
 {
-    AvArgs<N, R> a;
+    IndicatorArgs<N, R> a;
+    a.P = P;
+    a.tab = t;
+    a.K = B.K;
+    a.h = (const R *)B.W[buf][0];
+    a.eps = (R *)B.eps[buf];
+    a.list = B.list[buf];
+    a.count = B.count + buf;
+    a.ntiles = ntiles_of<N>(B.K);
+    hipLaunchKernelGGL((indicator_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N, typename R>
+static ListArgs<N, R> list_args(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t)
+{
+    ListArgs<N, R> a;
     a.m = mesh_view<R>(B);
     a.P = P;
     a.tab = t;
     a.h = (const R *)B.W[in][0];
     a.hu = (const R *)B.W[in][1];
     a.hv = (const R *)B.W[in][2];
-    a.eps = (R *)B.eps;
+    a.eps = (const R *)B.eps[in];
+    a.list = B.list[in];
+    a.count = B.count + in;
     a.vtr = (R *)B.vtr;
-    a.ntiles = ntiles_of<N>(B.K);
-    hipLaunchKernelGGL((av_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, a);
+    a.lv2 = (R *)B.lv[0];
+    a.lv3 = (R *)B.lv[1];
+    a.count_reset = nullptr;
+    return a;
+}
+
+// Fixed grid for the list passes: a few workgroups per CU, grid-stride over
+// the list (its length is only known on the device).
+constexpr unsigned kListBlocks = 1024;
+
+template <int N, typename R>
+hipError_t Launch<N, R>::av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
+{
+    hipLaunchKernelGGL((av_faces_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s,
+                       list_args<N, R>(B, in, P, t));
     return hipGetLastError();
 }
 
-template <int N, typename R, int MODE, bool AV>
+template <int N, typename R>
+hipError_t Launch<N, R>::av_div(const Bufs &B, int in, int reset, const Phys<R> &P, const Tab<R> &t,
+                                hipStream_t s)
+{
+    ListArgs<N, R> a = list_args<N, R>(B, in, P, t);
+    a.count_reset = reset >= 0 ? B.count + reset : nullptr;
+    hipLaunchKernelGGL((av_div_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N, typename R, int MODE>
 static void launch_stage(const StageArgs<R> &a, int64_t K, hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<N, R, MODE, AV>), tile_grid<N>(K), dim3(Shape<N>::T), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<N, R, MODE>), tile_grid<N>(K), dim3(Shape<N>::T), 0, s, a);
 }
 
 template <int N, typename R>
@@ -115,23 +156,21 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.dh = (R *)B.dU[0];
     a.dhu = (R *)B.dU[1];
     a.dhv = (R *)B.dU[2];
-    a.eps = (const R *)B.eps;
+    a.eps = c.av ? (const R *)B.eps[c.in] : nullptr;
     a.vtr = (const R *)B.vtr;
+    a.lv2 = (const R *)B.lv[0];
+    a.lv3 = (const R *)B.lv[1];
+    a.eps_out = c.out_rhs ? nullptr : (R *)B.eps[c.out];
+    a.list_out = c.out_rhs ? nullptr : B.list[c.out];
+    a.count_out = c.out_rhs ? nullptr : B.count + c.out;
     a.dt = B.dscal;
     a.ca = (R)c.ca;
     a.cb = (R)c.cb;
     a.flags = B.flags;
     a.ntiles = ntiles_of<N>(B.K);
-    if (c.mode == kModeRhs) {
-        if (c.av) launch_stage<N, R, kModeRhs, true>(a, B.K, s);
-        else launch_stage<N, R, kModeRhs, false>(a, B.K, s);
-    } else if (c.mode == kModeLsrk) {
-        if (c.av) launch_stage<N, R, kModeLsrk, true>(a, B.K, s);
-        else launch_stage<N, R, kModeLsrk, false>(a, B.K, s);
-    } else {
-        if (c.av) launch_stage<N, R, kModeSsp, true>(a, B.K, s);
-        else launch_stage<N, R, kModeSsp, false>(a, B.K, s);
-    }
+    if (c.mode == kModeRhs) launch_stage<N, R, kModeRhs>(a, B.K, s);
+    else if (c.mode == kModeLsrk) launch_stage<N, R, kModeLsrk>(a, B.K, s);
+    else launch_stage<N, R, kModeSsp>(a, B.K, s);
     return hipGetLastError();
 }
 
@@ -154,7 +193,7 @@ hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, const Phys<R> &P, co
     a.h = (const R *)B.W[in][0];
     a.hu = (const R *)B.W[in][1];
     a.hv = (const R *)B.W[in][2];
-    a.eps = av ? (const R *)B.eps : nullptr;
+    a.eps = av ? (const R *)B.eps[in] : nullptr;
     a.slots = B.slots;
     a.br1_radius = br1_radius;
     a.ntiles = ntiles_of<N>(B.K);

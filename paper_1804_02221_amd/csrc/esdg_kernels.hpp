@@ -64,6 +64,7 @@ struct Tab {
     R D[kMaxNF * kMaxNF];     // derivative matrix, row-major
     R Vinv[kMaxNF * kMaxNF];  // Vandermonde inverse
     R w[kMaxNF];              // LGL weights
+    R iw0;                    // 1 / w_0 (end weight)
 };
 
 template <typename R>
@@ -80,6 +81,8 @@ struct Mesh {
 template <typename R>
 struct Phys {
     R g, h_tol, eps0, sigma_min, sigma_max, cfl, cfl_visc;
+    R i2g;                 // 1 / (2 g)
+    R ratio_min, ratio_max; // 10^sigma_min, 10^sigma_max
     int ec, limiter_on;
 };
 
@@ -107,13 +110,12 @@ __device__ __forceinline__ R rcp_wet(R h, R h_tol)
 // Rotated numerical interface flux along the unit normal (nx, ny), '-' =
 // own trace, '+' = neighbour (appendix B): EC part plus, for the entropy
 // stable flux, -1/2 R |Lambda| R^T [[q~]] expanded in closed form.
+// Velocities are the primitive ones (zero at dry nodes).
 template <typename R>
-__device__ __forceinline__ void interface_flux(R hm, R hum, R hvm, R bm, R hp, R hup, R hvp, R bp,
-                                               R nx, R ny, const Phys<R> &P, R &F0, R &F1, R &F2)
+__device__ __forceinline__ void interface_flux(R hm, R um, R vm, R bm, R hp, R up, R vp, R bp, R nx, R ny,
+                                               const Phys<R> &P, R &F0, R &F1, R &F2)
 {
     const R g = P.g;
-    const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
-    const R um = hum * im, vm = hvm * im, up = hup * ip, vp = hvp * ip;
     const R utm = nx * um + ny * vm, vtm = nx * vm - ny * um;
     const R utp = nx * up + ny * vp, vtp = nx * vp - ny * up;
     const R cm = sqrt(g * (hm > R(0) ? hm : R(0)));
@@ -127,8 +129,7 @@ __device__ __forceinline__ void interface_flux(R hm, R hum, R hvm, R bm, R hp, R
         const R dq1 = g * ((hp + bp) - (hm + bm)) -
                       R(0.5) * ((utp * utp + vtp * vtp) - (utm * utm + vtm * vtm));
         const R dq2 = utp - utm, dq3 = vtp - vtm;
-        const R i2g = R(0.5) / g;
-        const R lp = fabs(au + ac) * i2g, l2 = fabs(ah * au), lm = fabs(au - ac) * i2g;
+        const R lp = fabs(au + ac) * P.i2g, l2 = fabs(ah * au), lm = fabs(au - ac) * P.i2g;
         const R r1 = lp * (dq1 + (au + ac) * dq2 + av * dq3);
         const R r2 = l2 * dq3;
         const R r3 = lm * (dq1 + (au - ac) * dq2 + av * dq3);
@@ -276,25 +277,108 @@ struct ElemReduce {
     }
 };
 
+// Element totals: NQ values per thread summed over the nodes of each element
+// (the last reduced by min when MINLAST); only thread p == 0 of each element
+// receives the totals.  Two barriers; red: NQ*T reals of LDS.  The caller
+// synchronises before reusing red.
+template <int N, typename R, int NQ, bool MINLAST>
+__device__ __forceinline__ void elem_totals(R (&v)[NQ], R *red, int t, int el, int p, bool lane)
+{
+    constexpr int nf = N + 1, np = nf * nf, T = Shape<N>::T;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) red[c * T + t] = v[c];
+    __syncthreads();
+    if (lane && p < nf) {
+        // column p of element el; its total goes to the column's first slot,
+        // which only this thread reads
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            R s = red[c * T + el * np + p];
+#pragma unroll
+            for (int r = 1; r < nf; ++r) {
+                const R val = red[c * T + el * np + r * nf + p];
+                if (MINLAST && c == NQ - 1) s = val < s ? val : s;
+                else s += val;
+            }
+            red[c * T + el * np + p] = s;
+        }
+    }
+    __syncthreads();
+    if (lane && p == 0) {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            R s = red[c * T + el * np];
+#pragma unroll
+            for (int r = 1; r < nf; ++r) {
+                const R val = red[c * T + el * np + r];
+                if (MINLAST && c == NQ - 1) s = val < s ? val : s;
+                else s += val;
+            }
+            v[c] = s;
+        }
+    }
+}
+
 // ------------------------------------------------------------------------
-// Artificial viscosity: element viscosity (appendix A) and the physical
-// viscous fluxes h eps (U1, V1), h eps (U2, V2) on the element's faces
-// (Theorem 1, BR1 gradients with U* = {u}).  Only face values leave the
-// kernel; the stage kernel recomputes interior gradients itself.
+// Artificial viscosity (appendix A, Theorem 1)
 // ------------------------------------------------------------------------
+// Viscosity from the indicator's element totals: modal energy of all modes,
+// of the top shell, of the modes up to N-1 and of shell N-1, and max h.
+template <typename R>
+__device__ __forceinline__ R viscosity_from_totals(R all, R top, R allM, R topM, R hmax, const Phys<R> &P)
+{
+    if (!(hmax > P.h_tol)) return R(0);
+    const R r1 = all > R(0) ? top / all : R(0);
+    const R r2 = allM > R(0) ? topM / allM : R(0);
+    const R rm = r1 > r2 ? r1 : r2;
+    // sigma = log10(rm) against the thresholds, compared as rm against
+    // 10^sigma (the ramp is continuous at both ends); log10 and sin only on
+    // the ramp
+    if (!(rm > P.ratio_min)) return R(0);
+    if (rm >= P.ratio_max) return P.eps0;
+    const R sg = log10(rm);
+    const R smin = P.sigma_min, smax = P.sigma_max;
+    if (sg >= smax) return P.eps0;
+    if (!(sg > smin)) return R(0);
+    return R(0.5) * P.eps0 *
+           (R(1) + sin(R(3.14159265358979323846) * (sg - R(0.5) * (smax + smin)) / (smax - smin)));
+}
+
+// Element viscosity of the elements whose nodal water heights are staged in
+// sh[el*np + p]: modal coefficients Q^ = V^{-1} h V^{-T}, the energy
+// fractions of the top two mode shells, sigma = log10 of the larger, and the
+// sine ramp between sigma_min and sigma_max; zero for dry elements.  The
+// result is valid in thread p == 0 of each element.  red: 6*T reals of LDS
+// (the last T hold the intermediate V^{-1} h).  Three barriers.
 template <int N, typename R>
-struct AvArgs {
-    Mesh<R> m;
-    Phys<R> P;
-    Tab<R> tab;
-    const R *h, *hu, *hv;   // stage input state
-    R *eps;                 // [K]
-    R *vtr;                 // [K][4][nf][4]: Fv2, Fv3, Gv2, Gv3 at face nodes
-    int64_t ntiles;
-};
+__device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phys<R> &P, int t, int el,
+                               int p, bool lane, R h)
+{
+    constexpr int nf = N + 1, np = nf * nf, T = Shape<N>::T;
+    const int i = p / nf, j = p - i * nf;
+    R Tq = 0;
+    if (lane) {
+#pragma unroll
+        for (int r = 0; r < nf; ++r) Tq += tab.Vinv[i * kMaxNF + r] * sh[el * np + r * nf + j];
+    }
+    red[5 * T + t] = Tq;
+    __syncthreads();
+    R Qh = 0;
+    if (lane) {
+#pragma unroll
+        for (int c = 0; c < nf; ++c) Qh += red[5 * T + el * np + i * nf + c] * tab.Vinv[j * kMaxNF + c];
+    }
+    const R q2 = Qh * Qh;
+    const int mx = i > j ? i : j;
+    R vals[5] = {q2, mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0),
+                 lane ? -h : R(3.0e38)};
+    elem_totals<N, R, 5, true>(vals, red, t, el, p, lane);
+    return viscosity_from_totals<R>(vals[0], vals[1], vals[2], vals[3], -vals[4], P);
+}
 
 // Viscous physical fluxes at node (i,j) of the element whose u, v are in
-// LDS (su, sv offset to the element), with U*, V* per face slot in us, vs.
+// LDS (su, sv offset to the element), with U*, V* per face slot in us, vs
+// (BR1 gradients of eq. BR1 with the lifted reference derivatives).
 template <int N, typename R>
 __device__ __forceinline__ void viscous_flux_at(int i, int j, const R *su, const R *sv, const R *us,
                                                 const R *vs, R Ax, R Cx, R Ae, R Ce, R he,
@@ -311,7 +395,7 @@ __device__ __forceinline__ void viscous_flux_at(int i, int j, const R *su, const
         deu += dj * su[i * nf + m];
         dev += dj * sv[i * nf + m];
     }
-    const R iw = R(1) / tab.w[0];
+    const R iw = tab.iw0;
     // BR1 lift (U* - u)/w on the faces the node lies on
     if (i == N) { dxu += (us[1 * nf + j] - u0) * iw; dxv += (vs[1 * nf + j] - v0) * iw; }
     if (i == 0) { dxu -= (us[3 * nf + j] - u0) * iw; dxv -= (vs[3 * nf + j] - v0) * iw; }
@@ -326,24 +410,75 @@ __device__ __forceinline__ void viscous_flux_at(int i, int j, const R *su, const
     Gv3 = s * (Cx * dxv + Ce * dev);
 }
 
+// Indicator sweep over all elements (initial data, or after the state was
+// replaced): element viscosity, and the list of elements with eps > 0.
 template <int N, typename R>
-__global__ __launch_bounds__(Shape<N>::T) void av_kernel(AvArgs<N, R> a)
+struct IndicatorArgs {
+    Phys<R> P;
+    Tab<R> tab;
+    int64_t K;
+    const R *h;
+    R *eps;             // [K]
+    int32_t *list;      // [K] elements with eps > 0 (order unspecified)
+    int *count;         // list length (zeroed beforehand)
+    int64_t ntiles;
+};
+
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void indicator_kernel(IndicatorArgs<N, R> a)
 {
     using S = Shape<N>;
-    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
-    __shared__ R s_h[T], s_u[T], s_v[T], s_red[4 * T];
-    __shared__ R s_us[NF], s_vs[NF], s_eps[E];
+    constexpr int np = S::np, E = S::E, T = S::T;
+    __shared__ R s_h[T], s_red[6 * T];
     const int64_t tile = xcd_tile(a.ntiles);
     if (tile < 0) return;
     const int t = threadIdx.x;
-    // lanes past the last element's nodes shadow node 0 of the last slot
-    // (all LDS indices stay in range; they never store)
     const bool lane = t < E * np;
-    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0, i = p / nf, j = p - i * nf;
-    const int64_t e0 = tile * E, e = e0 + el;
-    const bool act = lane && (e < a.m.K);
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0;
+    const int64_t e = tile * E + el;
+    const bool act = lane && (e < a.K);
+    const R h = act ? a.h[e * np + p] : R(0);
+    s_h[t] = h;
+    __syncthreads();
+    const R eps = element_viscosity<N, R>(s_h, s_red, a.tab, a.P, t, el, p, lane, h);
+    if (act && p == 0) {
+        a.eps[e] = eps;
+        if (eps > R(0)) a.list[atomicAdd(a.count, 1)] = (int32_t)e;
+    }
+}
+
+// Work over the viscous-element list: groups of E listed elements per
+// iteration, grid-stride; an empty list exits at once.
+template <int N, typename R>
+struct ListArgs {
+    Mesh<R> m;
+    Phys<R> P;
+    Tab<R> tab;
+    const R *h, *hu, *hv;     // stage input state
+    const R *eps;             // [K] viscosity of this state
+    const int32_t *list;      // elements with eps > 0
+    const int *count;
+    R *vtr;                   // [K][4][nf][4] face viscous fluxes (pass 1 writes, pass 2 reads)
+    R *lv2, *lv3;             // [K][np] viscous terms (pass 2)
+    int *count_reset;         // pass 2: list counter of the next state, zeroed here
+};
+
+// Stage the listed elements' velocities and the BR1 interface states
+// U* = {u}, V* = {v} in LDS (shared by both passes).
+template <int N, typename R>
+__device__ __forceinline__ void load_viscous_element(const ListArgs<N, R> &a, int64_t g, int cnt, int t, int el,
+                                                     int p, bool lane, int64_t *s_e, R *s_h, R *s_u, R *s_v,
+                                                     R *s_us, R *s_vs, int64_t &e, R &h)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
+    if (lane && p == 0) s_e[el] = (g * E + el < cnt) ? (int64_t)a.list[g * E + el] : int64_t(-1);
+    __syncthreads();
+    e = s_e[el];
+    const bool act = lane && e >= 0;
     const int64_t q = e * np + p;
-    R h = 0, u = 0, v = 0;
+    h = 0;
+    R u = 0, v = 0;
     if (act) {
         h = a.h[q];
         const R ih = rcp_wet(h, a.P.h_tol);
@@ -353,92 +488,142 @@ __global__ __launch_bounds__(Shape<N>::T) void av_kernel(AvArgs<N, R> a)
     s_h[t] = h;
     s_u[t] = u;
     s_v[t] = v;
-    // BR1 interface states U* = {u}, V* = {v}
+    __syncthreads();
     for (int f = t; f < NF; f += T) {
         const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
-        const int64_t fe = e0 + fel;
+        const int64_t fe = s_e[fel];
         R us = 0, vs = 0;
-        if (fe < a.m.K) {
+        if (fe >= 0) {
             int fi, fj, ns, kk;
             int64_t en;
             side_node<N>(s, k, fi, fj);
-            const int64_t qo = fe * np + fi * nf + fj;
+            const int lp = fel * np + fi * nf + fj;
             const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
-            const R ho = a.h[qo], hn = a.h[qn];
-            const R io = rcp_wet(ho, a.P.h_tol), in = rcp_wet(hn, a.P.h_tol);
-            us = R(0.5) * (a.hu[qo] * io + a.hu[qn] * in);
-            vs = R(0.5) * (a.hv[qo] * io + a.hv[qn] * in);
+            const R in = rcp_wet(a.h[qn], a.P.h_tol);
+            us = R(0.5) * (s_u[lp] + a.hu[qn] * in);
+            vs = R(0.5) * (s_v[lp] + a.hv[qn] * in);
         }
         s_us[f] = us;
         s_vs[f] = vs;
     }
     __syncthreads();
-    // modal indicator: T = Vinv h (rows), Qh = T Vinv^T
-    R Tq = 0;
-    if (t < E * np) {
-#pragma unroll
-        for (int r = 0; r < nf; ++r) Tq += a.tab.Vinv[i * kMaxNF + r] * s_h[el * np + r * nf + j];
+}
+
+// Pass 1: the physical viscous fluxes h eps (U1, V1), h eps (U2, V2) on the
+// faces of the listed elements (their neighbours' divergence needs them).
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void av_faces_kernel(ListArgs<N, R> a)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
+    __shared__ R s_h[T], s_u[T], s_v[T], s_us[NF], s_vs[NF];
+    __shared__ int64_t s_e[E];
+    const int cnt = *a.count;
+    const int t = threadIdx.x;
+    const bool lane = t < E * np;
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0;
+    for (int64_t g = blockIdx.x; g * E < cnt; g += gridDim.x) {
+        int64_t e;
+        R h;
+        load_viscous_element<N, R>(a, g, cnt, t, el, p, lane, s_e, s_h, s_u, s_v, s_us, s_vs, e, h);
+        for (int f = t; f < NF; f += T) {
+            const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+            const int64_t fe = s_e[fel];
+            if (fe < 0) continue;
+            int fi, fj;
+            side_node<N>(s, k, fi, fj);
+            const int lp = fel * np + fi * nf + fj;
+            const int64_t qo = fe * np + fi * nf + fj;
+            R Fv2, Fv3, Gv2, Gv3;
+            viscous_flux_at<N, R>(fi, fj, s_u + fel * np, s_v + fel * np, s_us + fel * 4 * nf,
+                                  s_vs + fel * 4 * nf, a.m.Ax[qo], a.m.Cx[qo], a.m.Ae[qo], a.m.Ce[qo],
+                                  s_h[lp] * a.eps[fe], a.tab, Fv2, Fv3, Gv2, Gv3);
+            R *o = a.vtr + ((fe * 4 + s) * nf + k) * 4;
+            o[0] = Fv2;
+            o[1] = Fv3;
+            o[2] = Gv2;
+            o[3] = Gv3;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    s_red[t] = Tq;   // reuse as T storage
-    __syncthreads();
-    R Qh = 0;
-    if (t < E * np) {
-#pragma unroll
-        for (int c = 0; c < nf; ++c) Qh += s_red[el * np + i * nf + c] * a.tab.Vinv[j * kMaxNF + c];
-    }
-    __syncthreads();
-    {
-        const R q2 = Qh * Qh;
-        const int mx = i > j ? i : j;
-        R vals[4] = {q2, mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0)};
-        ElemReduce<N, R, 4>::template run<false>(vals, s_red, t, el, p);
-        R hv[1] = {h};
-        // max h over the element through the min of -h
-        R mh[1] = {-h};
-        ElemReduce<N, R, 1>::template run<true>(mh, s_red, t, el, p);
-        (void)hv;
-        if (act && p == 0) {
-            R eps = 0;
-            const R hmax = -mh[0];
-            if (hmax > a.P.h_tol) {
-                const R r1 = vals[0] > R(0) ? vals[1] / vals[0] : R(0);
-                const R r2 = vals[2] > R(0) ? vals[3] / vals[2] : R(0);
-                const R rm = r1 > r2 ? r1 : r2;
-                if (rm > R(0)) {
-                    const R sg = log10(rm);
-                    const R smin = a.P.sigma_min, smax = a.P.sigma_max;
-                    if (sg >= smax) eps = a.P.eps0;
-                    else if (sg > smin)
-                        eps = R(0.5) * a.P.eps0 *
-                              (R(1) + sin(R(3.14159265358979323846) * (sg - R(0.5) * (smax + smin)) /
-                                          (smax - smin)));
+}
+
+// Pass 2: the BR1 viscous divergence (Theorem 1, eq. ViscTermsDisc) L^v on
+// the momentum rows of the listed elements, interface fluxes averaged with
+// the neighbours' pass-1 fluxes (zero for neighbours without viscosity).
+// Elements without viscosity get their (face-only) viscous terms inside the
+// stage kernel.
+template <int N, typename R>
+__global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
+{
+    using S = Shape<N>;
+    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
+    __shared__ R s_h[T], s_u[T], s_v[T], s_us[NF], s_vs[NF], s_Fv[4][T], s_vn[4][NF];
+    __shared__ int64_t s_e[E];
+    if (a.count_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.count_reset = 0;
+    const int cnt = *a.count;
+    const int t = threadIdx.x;
+    const bool lane = t < E * np;
+    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0, i = p / nf, j = p - i * nf;
+    for (int64_t g = blockIdx.x; g * E < cnt; g += gridDim.x) {
+        int64_t e;
+        R h;
+        load_viscous_element<N, R>(a, g, cnt, t, el, p, lane, s_e, s_h, s_u, s_v, s_us, s_vs, e, h);
+        const bool act = lane && e >= 0;
+        const int64_t q = e * np + p;
+        // neighbours' face fluxes
+        for (int f = t; f < NF; f += T) {
+            const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+            const int64_t fe = s_e[fel];
+            R n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+            if (fe >= 0) {
+                int ns, kk;
+                int64_t en;
+                (void)nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+                if (a.eps[en] > R(0)) {
+                    const R *vn = a.vtr + ((en * 4 + ns) * nf + kk) * 4;
+                    n0 = vn[0]; n1 = vn[1]; n2 = vn[2]; n3 = vn[3];
                 }
             }
-            a.eps[e] = eps;
-            s_eps[el] = eps;
+            s_vn[0][f] = n0; s_vn[1][f] = n1; s_vn[2][f] = n2; s_vn[3][f] = n3;
         }
-    }
-    __syncthreads();
-    // viscous fluxes at the face nodes
-    for (int f = t; f < NF; f += T) {
-        const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
-        const int64_t fe = e0 + fel;
-        if (fe >= a.m.K) continue;
-        int fi, fj;
-        side_node<N>(s, k, fi, fj);
-        const int lp = fel * np + fi * nf + fj;
-        const int64_t qo = fe * np + fi * nf + fj;
-        const R he = s_h[lp] * s_eps[fel];
-        R Fv2, Fv3, Gv2, Gv3;
-        viscous_flux_at<N, R>(fi, fj, s_u + fel * np, s_v + fel * np, s_us + fel * 4 * nf,
-                              s_vs + fel * 4 * nf, a.m.Ax[qo], a.m.Cx[qo], a.m.Ae[qo], a.m.Ce[qo], he,
-                              a.tab, Fv2, Fv3, Gv2, Gv3);
-        R *o = a.vtr + ((fe * 4 + s) * nf + k) * 4;
-        o[0] = Fv2;
-        o[1] = Fv3;
-        o[2] = Gv2;
-        o[3] = Gv3;
+        R Ax = 0, Cx = 0, Ae = 0, Ce = 0, Fv2 = 0, Fv3 = 0, Gv2 = 0, Gv3 = 0;
+        if (act) {
+            Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
+            viscous_flux_at<N, R>(i, j, s_u + el * np, s_v + el * np, s_us + el * 4 * nf, s_vs + el * 4 * nf,
+                                  Ax, Cx, Ae, Ce, h * a.eps[e], a.tab, Fv2, Fv3, Gv2, Gv3);
+        }
+        // contravariant fluxes: F~v = J grad(xi) . (Fv, Gv), G~v = J grad(eta) . (Fv, Gv)
+        s_Fv[0][t] = Ax * Fv2 + Cx * Gv2;
+        s_Fv[1][t] = Ax * Fv3 + Cx * Gv3;
+        s_Fv[2][t] = Ae * Fv2 + Ce * Gv2;
+        s_Fv[3][t] = Ae * Fv3 + Ce * Gv3;
+        __syncthreads();
+        if (act) {
+            R Lv2 = 0, Lv3 = 0;
+            const int base = el * np;
+#pragma unroll
+            for (int mm = 0; mm < nf; ++mm) {
+                const R di = a.tab.D[i * kMaxNF + mm], dj = a.tab.D[j * kMaxNF + mm];
+                Lv2 += di * s_Fv[0][base + mm * nf + j] + dj * s_Fv[2][base + i * nf + mm];
+                Lv3 += di * s_Fv[1][base + mm * nf + j] + dj * s_Fv[3][base + i * nf + mm];
+            }
+            // faces: (1/(2 w_0)) n_s . (Fv_nbr - Fv_own), n_s outward scaled normal
+            const R hw = R(0.5) * a.tab.iw0;
+            const int fb = el * 4 * nf;
+            auto face = [&](int s, int k, R snx, R sny) {
+                const int f = fb + s * nf + k;
+                Lv2 += hw * (snx * (s_vn[0][f] - Fv2) + sny * (s_vn[2][f] - Gv2));
+                Lv3 += hw * (snx * (s_vn[1][f] - Fv3) + sny * (s_vn[3][f] - Gv3));
+            };
+            if (j == 0) face(0, i, -Ae, -Ce);
+            if (i == N) face(1, j, Ax, Cx);
+            if (j == N) face(2, i, Ae, Ce);
+            if (i == 0) face(3, j, -Ax, -Cx);
+            a.lv2[q] = Lv2;
+            a.lv3[q] = Lv3;
+        }
+        __syncthreads();
     }
 }
 
@@ -456,29 +641,33 @@ struct StageArgs {
     const R *h0, *hu0, *hv0;     // SSP: W^n
     R *oh, *ohu, *ohv;           // output: R (rhs mode) or the new state
     R *dh, *dhu, *dhv;           // LSRK register dU (in place)
-    const R *eps;                // [K] (AV)
-    const R *vtr;                // [K][4][nf][4] (AV)
+    // artificial viscosity (nullptr eps: off)
+    const R *eps;                // [K] viscosity of the input state
+    const R *vtr;                // [K][4][nf][4] face viscous fluxes of viscous elements
+    const R *lv2, *lv3;          // [K][np] viscous terms of viscous elements
+    R *eps_out;                  // [K] viscosity of the output state (update modes)
+    int32_t *list_out;           // elements of the output state with eps > 0
+    int *count_out;
     const double *dt;            // device scalar: current step
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
     int *flags;                  // [0]: negative mean seen, [1]: limited elements
     int64_t ntiles;
 };
 
-template <int N, typename R, int MODE, bool AV>
+template <int N, typename R, int MODE>
 __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
 {
     using S = Shape<N>;
     constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
     static_assert((T & (T - 1)) == 0, "workgroup size must be a power of two");
-    // one contiguous staging region: reused as reduction scratch by the limiter
+    // one contiguous staging region: reused as reduction scratch at the end
     __shared__ R s_st[9 * T];
     R *const s_h = s_st, *const s_hu = s_st + T, *const s_hv = s_st + 2 * T;
     R *const s_u = s_st + 3 * T, *const s_v = s_st + 4 * T;
     R *const s_Ax = s_st + 5 * T, *const s_Cx = s_st + 6 * T;
     R *const s_Ae = s_st + 7 * T, *const s_Ce = s_st + 8 * T;
     __shared__ R s_fl[3][NF];
-    __shared__ R s_us[AV ? NF : 1], s_vs[AV ? NF : 1], s_vn[AV ? 4 : 1][AV ? NF : 1];
-    __shared__ R s_Fv[AV ? 4 : 1][AV ? T : 1];
+    __shared__ R s_lim[4 * E];
 
     const int64_t tile = xcd_tile(a.ntiles);
     if (tile < 0) return;
@@ -491,6 +680,7 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
     const bool act = lane && (e < a.m.K);
     const int64_t q = e * np + p;
     const Phys<R> &P = a.P;
+    const bool av = a.eps != nullptr;
 
     R h = 0, hu = 0, hv = 0, Ax = 0, Cx = 0, Ae = 0, Ce = 0;
     if (act) {
@@ -503,8 +693,9 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
     s_Ax[t] = Ax; s_Cx[t] = Cx; s_Ae[t] = Ae; s_Ce[t] = Ce;
     __syncthreads();
 
-    // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node ----
-    const R iw0 = R(1) / a.tab.w[0];
+    // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node; for
+    // an element without viscosity next to one with viscosity, also its only
+    // viscous term: (1/(2 w_0)) n_s . Fv_nbr (its own viscous fluxes are 0) ----
     for (int f = t; f < NF; f += T) {
         const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
         const int64_t fe = e0 + fel;
@@ -526,21 +717,18 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             const R hn = a.h[qn], hun = a.hu[qn], hvn = a.hv[qn];
             const R bo = a.m.bface[(fe * 4 + s) * nf + k];
             const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
+            const R in = rcp_wet(hn, P.h_tol);
             R F0, F1, F2;
-            interface_flux<R>(s_h[lp], s_hu[lp], s_hv[lp], bo, hn, hun, hvn, bn, snx * ijs, sny * ijs, P,
-                              F0, F1, F2);
-            const R sc = js * iw0;
+            interface_flux<R>(s_h[lp], s_u[lp], s_v[lp], bo, hn, hun * in, hvn * in, bn, snx * ijs,
+                              sny * ijs, P, F0, F1, F2);
+            const R sc = js * a.tab.iw0;
             c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
-            if constexpr (AV) {
-                const R in = rcp_wet(hn, P.h_tol);
-                s_us[f] = R(0.5) * (s_u[lp] + hun * in);
-                s_vs[f] = R(0.5) * (s_v[lp] + hvn * in);
+            if (av && !(a.eps[fe] > R(0)) && a.eps[en] > R(0)) {
                 const R *vn = a.vtr + ((en * 4 + ns) * nf + kk) * 4;
-                s_vn[0][f] = vn[0]; s_vn[1][f] = vn[1]; s_vn[2][f] = vn[2]; s_vn[3][f] = vn[3];
+                const R hw = R(0.5) * a.tab.iw0;
+                c1 -= hw * (snx * vn[0] + sny * vn[2]);
+                c2 -= hw * (snx * vn[1] + sny * vn[3]);
             }
-        } else if constexpr (AV) {
-            s_us[f] = 0; s_vs[f] = 0;
-            s_vn[0][f] = 0; s_vn[1][f] = 0; s_vn[2][f] = 0; s_vn[3][f] = 0;
         }
         s_fl[0][f] = c0; s_fl[1][f] = c1; s_fl[2][f] = c2;
     }
@@ -579,7 +767,7 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
         }
     }
     R L1 = R(0.5) * (a1 + b1), L2 = R(0.25) * (a2 + b2), L3 = R(0.25) * (a3 + b3);
-    __syncthreads();   // face slots complete
+    __syncthreads();   // face slots complete; staging region free from here on
     {
         const int fb = el * 4 * nf;
         if (j == 0) { L1 += s_fl[0][fb + 0 * nf + i]; L2 += s_fl[1][fb + 0 * nf + i]; L3 += s_fl[2][fb + 0 * nf + i]; }
@@ -589,44 +777,12 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
     }
     const R J = Ce * Ax - Cx * Ae;
 
-    // ---- viscous divergence (Theorem 1) ----
-    R Lv2 = 0, Lv3 = 0;
-    if constexpr (AV) {
-        const R eps = act ? a.eps[e] : R(0);
-        R Fv2 = 0, Fv3 = 0, Gv2 = 0, Gv3 = 0;
-        if (act)
-            viscous_flux_at<N, R>(i, j, s_u + el * np, s_v + el * np, s_us + el * 4 * nf,
-                                  s_vs + el * 4 * nf, Ax, Cx, Ae, Ce, h * eps, a.tab, Fv2, Fv3, Gv2, Gv3);
-        // contravariant fluxes: F~v = J grad(xi) . (Fv, Gv), G~v = J grad(eta) . (Fv, Gv)
-        s_Fv[0][t] = Ax * Fv2 + Cx * Gv2;
-        s_Fv[1][t] = Ax * Fv3 + Cx * Gv3;
-        s_Fv[2][t] = Ae * Fv2 + Ce * Gv2;
-        s_Fv[3][t] = Ae * Fv3 + Ce * Gv3;
-        __syncthreads();
-        const int base = el * np;
-#pragma unroll
-        for (int mm = 0; mm < nf; ++mm) {
-            const R di = a.tab.D[i * kMaxNF + mm], dj = a.tab.D[j * kMaxNF + mm];
-            Lv2 += di * s_Fv[0][base + mm * nf + j] + dj * s_Fv[2][base + i * nf + mm];
-            Lv3 += di * s_Fv[1][base + mm * nf + j] + dj * s_Fv[3][base + i * nf + mm];
-        }
-        // faces: (1/(2 w_0)) n_s . (Fv_nbr - Fv_own), n_s outward scaled normal
-        const R hw = R(0.5) * iw0;
-        const int fb = el * 4 * nf;
-        auto face = [&](int s, int k, R snx, R sny) {
-            const int f = fb + s * nf + k;
-            Lv2 += hw * (snx * (s_vn[0][f] - Fv2) + sny * (s_vn[2][f] - Gv2));
-            Lv3 += hw * (snx * (s_vn[1][f] - Fv3) + sny * (s_vn[3][f] - Gv3));
-        };
-        if (j == 0) face(0, i, -Ae, -Ce);
-        if (i == N) face(1, j, Ax, Cx);
-        if (j == N) face(2, i, Ae, Ce);
-        if (i == 0) face(3, j, -Ax, -Cx);
-    }
-
     // ---- R = (1/J)(-L + S + L^v), S = -(g/2) h (b_x, b_y) ----
-    R bxv = 0, byv = 0;
-    if (act) { bxv = a.m.bx[q]; byv = a.m.by[q]; }
+    R bxv = 0, byv = 0, Lv2 = 0, Lv3 = 0;
+    if (act) {
+        bxv = a.m.bx[q]; byv = a.m.by[q];
+        if (av && a.eps[e] > R(0)) { Lv2 = a.lv2[q]; Lv3 = a.lv3[q]; }
+    }
     const R iJ = act ? R(1) / J : R(0);
     const R hg = R(0.5) * P.g * h;
     const R R1 = -L1 * iJ;
@@ -658,21 +814,28 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             // positivity limiter (eq. PosPres) toward the J-weighted means
             const R wq = act ? J * a.tab.w[i] * a.tab.w[j] : R(0);
             R vals[5] = {wq, wq * nh, wq * nhu, wq * nhv, act ? nh : R(3.0e38)};
-            // reduce into the (now free) staging region
-            ElemReduce<N, R, 5>::template run<true>(vals, s_st, t, el, p);
-            const R area = vals[0];
-            const R mh = vals[1] / area, mhu = vals[2] / area, mhv = vals[3] / area;
-            const R mn = vals[4];
-            if (act && mn < R(0)) {
-                R th;
-                if (mh < R(0)) {
-                    th = R(0);
-                    if (p == 0) atomicOr(&a.flags[0], 1);
-                } else {
-                    th = mh / (mh - mn);
-                    th = th < R(1) ? th : R(1);
+            elem_totals<N, R, 5, true>(vals, s_st, t, el, p, lane);
+            if (lane && p == 0) {
+                const R area = vals[0];
+                const R mh = vals[1] / area, mhu = vals[2] / area, mhv = vals[3] / area, mn = vals[4];
+                R th = R(1);
+                if (act && mn < R(0)) {
+                    if (mh < R(0)) {
+                        th = R(0);
+                        atomicOr(&a.flags[0], 1);
+                    } else {
+                        th = mh / (mh - mn);
+                        th = th < R(1) ? th : R(1);
+                    }
+                    atomicAdd(&a.flags[1], 1);
                 }
-                if (p == 0) atomicAdd(&a.flags[1], 1);
+                s_lim[4 * el + 0] = th; s_lim[4 * el + 1] = mh;
+                s_lim[4 * el + 2] = mhu; s_lim[4 * el + 3] = mhv;
+            }
+            __syncthreads();
+            const R th = s_lim[4 * el];
+            if (act && th != R(1)) {
+                const R mh = s_lim[4 * el + 1], mhu = s_lim[4 * el + 2], mhv = s_lim[4 * el + 3];
                 nh = th * (nh - mh) + mh;
                 nhu = th * (nhu - mhu) + mhu;
                 nhv = th * (nhv - mhv) + mhv;
@@ -682,6 +845,16 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
         if (act) {
             a.oh[q] = nh; a.ohu[q] = nhu; a.ohv[q] = nhv;
             if constexpr (MODE == kModeLsrk) { a.dh[q] = d0; a.dhu[q] = d1; a.dhv[q] = d2; }
+        }
+        if (av) {
+            // viscosity of the new state for the next stage (appendix A)
+            s_st[8 * T + t] = nh;
+            __syncthreads();
+            const R en = element_viscosity<N, R>(s_st + 8 * T, s_st, a.tab, P, t, el, p, lane, nh);
+            if (act && p == 0) {
+                a.eps_out[e] = en;
+                if (en > R(0)) a.list_out[atomicAdd(a.count_out, 1)] = (int32_t)e;
+            }
         }
     }
 }

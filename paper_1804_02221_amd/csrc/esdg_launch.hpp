@@ -21,8 +21,11 @@ struct Bufs {
     void *W[4][3] = {};      // state buffers [buffer][h, hu, hv]: ping-pong, W^n, retry backup
     void *dU[3] = {};        // LSRK register
     void *Rb[3] = {};        // right-hand side output scratch
-    void *eps = nullptr;     // [K]
-    void *vtr = nullptr;     // [K][4][nf][4]
+    void *eps[4] = {};       // [K] element viscosity of each state buffer
+    int32_t *list[4] = {};   // [K] elements of each state buffer with eps > 0
+    int *count = nullptr;    // [4] list lengths
+    void *vtr = nullptr;     // [K][4][nf][4] viscous face fluxes (elements with eps > 0)
+    void *lv[2] = {};        // [K][np] viscous terms L^v (momentum rows)
     double *dscal = nullptr; // [0..3] dt bounds, [4] time, [5..7] spare
     unsigned long long *slots = nullptr;  // [3][kDtSlots]
     int *flags = nullptr;    // [0] neg mean, [1] limited count, [2] bad dt, [3] bad J
@@ -32,7 +35,7 @@ struct Bufs {
 
 struct StageCall {
     int mode;          // kModeRhs, kModeLsrk, kModeSsp
-    bool av;
+    bool av;           // add the viscous terms of visc()
     int in, out, base; // state buffers: input, output, W^n (SSP)
     bool out_rhs;      // write into Rb instead of W[out]
     double ca, cb;     // stage coefficients
@@ -42,7 +45,10 @@ template <int N, typename R>
 struct Launch {
     static hipError_t geometry(const Bufs &B, const Tab<double> &td, hipStream_t s);
     static hipError_t bathymetry(const Bufs &B, const double *b, const Tab<double> &td, hipStream_t s);
-    static hipError_t av(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
+    static hipError_t indicator(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
+    static hipError_t av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
+    static hipError_t av_div(const Bufs &B, int in, int reset, const Phys<R> &P, const Tab<R> &t,
+                             hipStream_t s);
     static hipError_t stage(const Bufs &B, const StageCall &c, const Phys<R> &P, const Tab<R> &t,
                             hipStream_t s);
     static hipError_t limit(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);

@@ -110,6 +110,7 @@ struct esdg_ctx {
     int64_t K = 0;
     bool have_mesh = false, have_b = false, have_state = false;
     int cur = 0;
+    bool eps_valid[4] = {false, false, false, false};   // viscosity/list of state buffer b are current
     HostTables ht{};
     Tab<double> td{};
     Tab<float> tf{};
@@ -144,6 +145,12 @@ int fail(esdg_ctx *c, int code, const char *fmt, ...)
                         __FILE__, __LINE__);                                                   \
     } while (0)
 
+#define TRY(expr)               \
+    do {                        \
+        int st_ = (expr);       \
+        if (st_) return st_;    \
+    } while (0)
+
 int64_t nodes(const esdg_ctx *c) { return c->K * (int64_t)(c->N + 1) * (c->N + 1); }
 size_t rsz(const esdg_ctx *c) { return c->prec == 64 ? sizeof(double) : sizeof(float); }
 
@@ -158,6 +165,9 @@ Phys<R> phys(const esdg_ctx *c)
     p.sigma_max = (R)c->P.sigma_max;
     p.cfl = (R)c->P.cfl;
     p.cfl_visc = (R)c->P.cfl_visc;
+    p.i2g = (R)(0.5 / c->P.g);
+    p.ratio_min = (R)std::pow(10.0, c->P.sigma_min);
+    p.ratio_max = (R)std::pow(10.0, c->P.sigma_max);
     p.ec = c->P.surface_flux == 1;
     p.limiter_on = c->P.limiter_on != 0;
     return p;
@@ -194,8 +204,9 @@ hipError_t dispatch(const esdg_ctx *c, F &&f)
 void free_bufs(esdg_ctx *c)
 {
     Bufs &B = c->B;
-    void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.eps,
-                  B.vtr, B.dscal, B.slots, B.flags, B.part, c->stage_d};
+    void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
+                  B.vtr, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
+                  B.eps[0], B.eps[1], B.eps[2], B.eps[3], B.list[0], B.list[1], B.list[2], B.list[3]};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (auto &w : B.W)
@@ -239,12 +250,43 @@ int timed(esdg_ctx *ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F 
     return ESDG_OK;
 }
 
-int launch_av(esdg_ctx *ctx, int buf)
+void invalidate_eps(esdg_ctx *ctx)
 {
+    for (bool &v : ctx->eps_valid) v = false;
+}
+
+// Element viscosity and viscous-element list of state buffer buf, when stale
+// (the stage kernel keeps them current for the states it writes).
+int ensure_eps(esdg_ctx *ctx, int buf)
+{
+    if (ctx->eps_valid[buf]) return ESDG_OK;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.count + buf, 0, 1);
+    CK(hipGetLastError());
+    TRY(timed(ctx, ctx->ev_av, [&] {
+        return dispatch(ctx, [&](auto L, auto r) {
+            using R = decltype(r);
+            return decltype(L)::indicator(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+        });
+    }));
+    ctx->eps_valid[buf] = true;
+    return ESDG_OK;
+}
+
+// Viscous terms of the listed elements of state buffer buf (both passes);
+// reset >= 0 zeroes that buffer's list counter for the stage about to run.
+int launch_viscous(esdg_ctx *ctx, int buf, int reset)
+{
+    TRY(ensure_eps(ctx, buf));
+    TRY(timed(ctx, ctx->ev_av, [&] {
+        return dispatch(ctx, [&](auto L, auto r) {
+            using R = decltype(r);
+            return decltype(L)::av_faces(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+        });
+    }));
     return timed(ctx, ctx->ev_av, [&] {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
-            return decltype(L)::av(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+            return decltype(L)::av_div(ctx->B, buf, reset, phys<R>(ctx), tab<R>(ctx), ctx->stream);
         });
     });
 }
@@ -337,12 +379,6 @@ int alloc(esdg_ctx *ctx, T **p, size_t bytes)
     return ESDG_OK;
 }
 
-#define TRY(expr)               \
-    do {                        \
-        int st_ = (expr);       \
-        if (st_) return st_;    \
-    } while (0)
-
 bool check_ctx(esdg_ctx *ctx, bool need_state)
 {
     if (!ctx) return false;
@@ -355,7 +391,7 @@ bool check_ctx(esdg_ctx *ctx, bool need_state)
 
 int run_rhs(esdg_ctx *ctx, int buf)
 {
-    if (ctx->P.av_on) TRY(launch_av(ctx, buf));
+    if (ctx->P.av_on) TRY(launch_viscous(ctx, buf, -1));
     StageCall sc{kModeRhs, ctx->P.av_on != 0, buf, buf, buf, true, 0.0, 0.0};
     return launch_stage(ctx, sc);
 }
@@ -478,6 +514,8 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     build_tables(N, ctx->ht);
     std::memset(&ctx->td, 0, sizeof(ctx->td));
     std::memset(&ctx->tf, 0, sizeof(ctx->tf));
+    ctx->td.iw0 = (double)(1.0L / ctx->ht.w[0]);
+    ctx->tf.iw0 = (float)(1.0L / ctx->ht.w[0]);
     for (int i = 0; i <= N; ++i) {
         ctx->td.w[i] = (double)ctx->ht.w[i];
         ctx->tf.w[i] = (float)ctx->ht.w[i];
@@ -504,7 +542,11 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     TRY(alloc(ctx, &B.bface, K * 4 * nf * r));
     TRY(alloc(ctx, &B.nbr, K * 4 * sizeof(int32_t)));
     TRY(alloc(ctx, &B.code, K * 4));
-    TRY(alloc(ctx, &B.eps, K * r));
+    for (void *&p : B.eps) TRY(alloc(ctx, &p, K * r));
+    for (int32_t *&p : B.list) TRY(alloc(ctx, &p, K * sizeof(int32_t)));
+    TRY(alloc(ctx, &B.count, 4 * sizeof(int)));
+    TRY(alloc(ctx, &B.lv[0], n * r));
+    TRY(alloc(ctx, &B.lv[1], n * r));
     TRY(alloc(ctx, &B.vtr, K * 4 * nf * 4 * r));
     TRY(alloc(ctx, &B.dscal, 8 * sizeof(double)));
     TRY(alloc(ctx, &B.slots, 3 * kDtSlots * sizeof(unsigned long long)));
@@ -520,7 +562,9 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     // zero-filled registers and traces
     for (void *p : B.dU) CK(hipMemsetAsync(p, 0, n * r, ctx->stream));
     CK(hipMemsetAsync(B.vtr, 0, K * 4 * nf * 4 * r, ctx->stream));
-    CK(hipMemsetAsync(B.eps, 0, K * r, ctx->stream));
+    for (void *p : B.eps) CK(hipMemsetAsync(p, 0, K * r, ctx->stream));
+    CK(hipMemsetAsync(B.count, 0, 4 * sizeof(int), ctx->stream));
+    invalidate_eps(ctx);
     CK(hipMemsetAsync(B.dscal, 0, 8 * sizeof(double), ctx->stream));
     CK(hipMemsetAsync(B.flags, 0, 4 * sizeof(int), ctx->stream));
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(3 * kDtSlots), 0, ctx->stream, B.slots,
@@ -572,6 +616,7 @@ int esdg_set_state(esdg_ctx *ctx, const double *h, const double *hu, const doubl
     TRY(upload_field(ctx, ctx->B.W[0][2], hv, n, mem));
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal + 4, 0.0);
     CK(hipGetLastError());
+    invalidate_eps(ctx);
     ctx->have_state = true;
     return ESDG_OK;
 }
@@ -608,6 +653,7 @@ int esdg_limit(esdg_ctx *ctx, int64_t *n_limited)
         using R = decltype(r);
         return decltype(L)::limit(ctx->B, ctx->cur, phys<R>(ctx), tab<R>(ctx), ctx->stream);
     }));
+    ctx->eps_valid[ctx->cur] = false;
     int flags[4];
     TRY(read_flags(ctx, flags));
     if (n_limited) *n_limited = flags[1];
@@ -620,7 +666,7 @@ int esdg_compute_dt(esdg_ctx *ctx, double out[4])
     if (!out) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
     if (!check_ctx(ctx, true)) return ESDG_EINVAL;
     TRY(reset_flags(ctx));
-    if (ctx->P.av_on) TRY(launch_av(ctx, ctx->cur));
+    if (ctx->P.av_on) TRY(ensure_eps(ctx, ctx->cur));
     TRY(launch_dt(ctx, ctx->cur, 0.0, 0));
     CK(hipMemcpyAsync(out, ctx->B.dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
@@ -647,21 +693,18 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                                   hipMemcpyDeviceToDevice, ctx->stream));
             TRY(reset_flags(ctx));
         }
-        // step size (AV at W^n first: the viscous bound needs the viscosity)
-        bool av_fresh = false;
-        if (adaptive && av) {
-            TRY(launch_av(ctx, base));
-            av_fresh = true;
-        }
+        // the viscous bound of the step needs the viscosity of W^n
+        if (av) TRY(ensure_eps(ctx, base));
         TRY(launch_dt(ctx, base, adaptive ? 0.0 : dt, 1));
         for (int attempt = 0;; ++attempt) {
             int in = base;
             if (!ssp) {
                 for (int k = 0; k < 5; ++k) {
                     const int out = (in == 0) ? 1 : 0;
-                    if (av && !(k == 0 && av_fresh)) TRY(launch_av(ctx, in));
+                    if (av) TRY(launch_viscous(ctx, in, out));
                     StageCall sc{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k]};
                     TRY(launch_stage(ctx, sc));
+                    ctx->eps_valid[out] = av;   // written by the stage epilogue
                     in = out;
                 }
                 ctx->cur = in;
@@ -670,9 +713,10 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
                 const int outs[3] = {o1, o2, base};
                 for (int k = 0; k < 3; ++k) {
-                    if (av && !(k == 0 && av_fresh)) TRY(launch_av(ctx, in));
+                    if (av) TRY(launch_viscous(ctx, in, outs[k]));
                     StageCall sc{kModeSsp, av, in, outs[k], base, false, al[k], be[k]};
                     TRY(launch_stage(ctx, sc));
+                    ctx->eps_valid[outs[k]] = av;
                     in = outs[k];
                 }
                 ctx->cur = base;
@@ -690,11 +734,11 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 CK(hipMemcpyAsync(ctx->B.W[base][c], ctx->B.W[backup][c], n * rsz(ctx),
                                   hipMemcpyDeviceToDevice, ctx->stream));
             ctx->cur = base;
+            invalidate_eps(ctx);
             hipLaunchKernelGGL(scale_step_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal, 0.5,
                                ctx->B.dscal + 4);
             CK(hipGetLastError());
             TRY(reset_flags(ctx));
-            av_fresh = false;
         }
     }
     int flags[4];
@@ -754,11 +798,12 @@ int esdg_get_eps(esdg_ctx *ctx, double *eps, int mem)
     if (!eps) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
     if (!check_ctx(ctx, true)) return ESDG_EINVAL;
     if (ctx->P.av_on) {
-        TRY(launch_av(ctx, ctx->cur));
+        TRY(ensure_eps(ctx, ctx->cur));
     } else {
-        CK(hipMemsetAsync(ctx->B.eps, 0, ctx->K * rsz(ctx), ctx->stream));
+        CK(hipMemsetAsync(ctx->B.eps[ctx->cur], 0, ctx->K * rsz(ctx), ctx->stream));
+        ctx->eps_valid[ctx->cur] = false;
     }
-    return download_field(ctx, eps, ctx->B.eps, ctx->K, mem);
+    return download_field(ctx, eps, ctx->B.eps[ctx->cur], ctx->K, mem);
 }
 
 int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, double *yeta, double *J,
