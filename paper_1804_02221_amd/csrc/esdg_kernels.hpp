@@ -25,13 +25,19 @@ namespace esdg {
 // ------------------------------------------------------------------------
 // Shapes
 // ------------------------------------------------------------------------
+// Workgroup shape per degree.  Where whole elements fill a 64-wide wave
+// with (almost) no idle lanes (N = 2, 3, 7) a workgroup is one wave: its
+// barriers are cheap and waves run independently.  Otherwise four waves
+// hold E = floor(256/(N+1)^2) elements packed across the waves.
 template <int N>
 struct Shape {
     static constexpr int nf = N + 1;
     static constexpr int np = nf * nf;
-    static constexpr int E = (256 / np) > 0 ? (256 / np) : 1;    // elements per workgroup
-    static constexpr int T = ((E * np + 63) / 64) * 64;           // threads per workgroup
-    static constexpr int NFACE = E * 4 * nf;                      // face-node slots per workgroup
+    static constexpr bool one_wave = (np <= 64) && (64 - (64 / np) * np) * 16 <= 64;
+    static constexpr int T = one_wave ? 64 : 256;                  // threads per workgroup
+    static constexpr int E = (T / np) > 0 ? (T / np) : 1;          // elements per workgroup
+    static constexpr int NFACE = E * 4 * nf;                       // face-node slots per workgroup
+    static_assert(E * np <= T, "elements must fit the workgroup");
 };
 
 constexpr int kXcds = 8;
@@ -714,13 +720,22 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             else { snx = -s_Ae[lp]; sny = -s_Ce[lp]; }
             const R js = sqrt(snx * snx + sny * sny);
             const R ijs = R(1) / js;
-            const R hn = a.h[qn], hun = a.hu[qn], hvn = a.hv[qn];
+            // neighbour trace: from LDS when the neighbour is in this workgroup
+            const int64_t ql = qn - e0 * np;
+            R hn, un, vn;
+            if (ql >= 0 && ql < E * np) {
+                hn = s_h[ql]; un = s_u[ql]; vn = s_v[ql];
+            } else {
+                hn = a.h[qn];
+                const R in = rcp_wet(hn, P.h_tol);
+                un = a.hu[qn] * in;
+                vn = a.hv[qn] * in;
+            }
             const R bo = a.m.bface[(fe * 4 + s) * nf + k];
             const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
-            const R in = rcp_wet(hn, P.h_tol);
             R F0, F1, F2;
-            interface_flux<R>(s_h[lp], s_u[lp], s_v[lp], bo, hn, hun * in, hvn * in, bn, snx * ijs,
-                              sny * ijs, P, F0, F1, F2);
+            interface_flux<R>(s_h[lp], s_u[lp], s_v[lp], bo, hn, un, vn, bn, snx * ijs, sny * ijs, P, F0,
+                              F1, F2);
             const R sc = js * a.tab.iw0;
             c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
             if (av && !(a.eps[fe] > R(0)) && a.eps[en] > R(0)) {

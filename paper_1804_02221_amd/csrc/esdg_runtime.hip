@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -81,19 +82,44 @@ __global__ void set_scalar_kernel(double *p, double v)
     if (threadIdx.x == 0) p[0] = v;
 }
 
-// Metric terms in the ABI's layout: x_xi, x_eta, y_xi, y_eta, J (float64).
-template <typename R>
-__global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const R *Ce, double *out,
-                                    int64_t n)
+// Element permutation between the caller's order and the internal
+// locality order: internal element e holds the caller's element perm[e].
+template <typename A, typename B>
+__global__ void gather_kernel(const A *__restrict__ src, B *__restrict__ dst, const int32_t *__restrict__ perm,
+                              int64_t K, int np)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * np) return;
+    const int64_t e = q / np;
+    dst[q] = (B)src[(int64_t)perm[e] * np + (q - e * np)];
+}
+
+template <typename A, typename B>
+__global__ void scatter_kernel(const A *__restrict__ src, B *__restrict__ dst, const int32_t *__restrict__ perm,
+                               int64_t K, int np)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * np) return;
+    const int64_t e = q / np;
+    dst[(int64_t)perm[e] * np + (q - e * np)] = (B)src[q];
+}
+
+// Metric terms in the ABI's layout and order: x_xi, x_eta, y_xi, y_eta, J (float64).
+template <typename R>
+__global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const R *Ce, double *out,
+                                    const int32_t *perm, int64_t K, int np)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = K * np;
     if (q >= n) return;
+    const int64_t e = q / np;
+    const int64_t o = (int64_t)perm[e] * np + (q - e * np);
     const double ax = Ax[q], cx = Cx[q], ae = Ae[q], ce = Ce[q];
-    out[q] = ce;             // x_xi
-    out[n + q] = -cx;        // x_eta
-    out[2 * n + q] = -ae;    // y_xi
-    out[3 * n + q] = ax;     // y_eta
-    out[4 * n + q] = ce * ax - cx * ae;
+    out[o] = ce;             // x_xi
+    out[n + o] = -cx;        // x_eta
+    out[2 * n + o] = -ae;    // y_xi
+    out[3 * n + o] = ax;     // y_eta
+    out[4 * n + o] = ce * ax - cx * ae;
 }
 
 }  // namespace esdg
@@ -115,6 +141,7 @@ struct esdg_ctx {
     Tab<double> td{};
     Tab<float> tf{};
     double *stage_d = nullptr;   // float64 staging [5][n] (conversions, geometry output)
+    int32_t *perm = nullptr;     // [K] caller's element of each internal element
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_stage, ev_av;
@@ -217,6 +244,8 @@ void free_bufs(esdg_ctx *c)
     for (void *p : B.Rb)
         if (p) (void)hipFree(p);
     B = Bufs{};
+    if (c->perm) (void)hipFree(c->perm);
+    c->perm = nullptr;
     c->stage_d = nullptr;
     c->have_mesh = c->have_b = c->have_state = false;
 }
@@ -332,40 +361,69 @@ int read_flags(esdg_ctx *ctx, int flags[4])
     return ESDG_OK;
 }
 
-// Copy a float64 host/device array into a context array of the compute precision.
-int upload_field(esdg_ctx *ctx, void *dst, const double *src, int64_t n, int mem)
+// Copy a float64 host/device array in the caller's element order into a
+// context array (compute precision, internal order); per = values per element.
+int upload_field(esdg_ctx *ctx, void *dst, const double *src, int64_t per, int mem)
 {
-    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if (ctx->prec == 64) {
-        CK(hipMemcpyAsync(dst, src, n * sizeof(double), k, ctx->stream));
-    } else {
-        const double *s = src;
-        if (!mem) {
-            CK(hipMemcpyAsync(ctx->stage_d, src, n * sizeof(double), k, ctx->stream));
-            s = ctx->stage_d;
-        }
-        hipLaunchKernelGGL((convert_kernel<double, float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           ctx->stream, s, (float *)dst, n);
-        CK(hipGetLastError());
+    const int64_t n = ctx->K * per;
+    const double *s = src;
+    if (!mem) {
+        CK(hipMemcpyAsync(ctx->stage_d, src, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        s = ctx->stage_d;
     }
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (ctx->prec == 64)
+        hipLaunchKernelGGL((gather_kernel<double, double>), dim3(g), dim3(256), 0, ctx->stream, s,
+                           (double *)dst, ctx->perm, ctx->K, (int)per);
+    else
+        hipLaunchKernelGGL((gather_kernel<double, float>), dim3(g), dim3(256), 0, ctx->stream, s,
+                           (float *)dst, ctx->perm, ctx->K, (int)per);
+    CK(hipGetLastError());
     if (!mem) CK(hipStreamSynchronize(ctx->stream));
     return ESDG_OK;
 }
 
-int download_field(esdg_ctx *ctx, double *dst, const void *src, int64_t n, int mem)
+// Copy a context array out into a float64 host/device array in the caller's order.
+int download_field(esdg_ctx *ctx, double *dst, const void *src, int64_t per, int mem)
 {
-    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (ctx->prec == 64) {
-        CK(hipMemcpyAsync(dst, src, n * sizeof(double), k, ctx->stream));
-    } else {
-        double *d = mem ? dst : ctx->stage_d;
-        hipLaunchKernelGGL((convert_kernel<float, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           ctx->stream, (const float *)src, d, n);
-        CK(hipGetLastError());
-        if (!mem) CK(hipMemcpyAsync(dst, ctx->stage_d, n * sizeof(double), k, ctx->stream));
+    const int64_t n = ctx->K * per;
+    double *d = mem ? dst : ctx->stage_d;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (ctx->prec == 64)
+        hipLaunchKernelGGL((scatter_kernel<double, double>), dim3(g), dim3(256), 0, ctx->stream,
+                           (const double *)src, d, ctx->perm, ctx->K, (int)per);
+    else
+        hipLaunchKernelGGL((scatter_kernel<float, double>), dim3(g), dim3(256), 0, ctx->stream,
+                           (const float *)src, d, ctx->perm, ctx->K, (int)per);
+    CK(hipGetLastError());
+    if (!mem) {
+        CK(hipMemcpyAsync(dst, ctx->stage_d, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
     }
-    if (!mem) CK(hipStreamSynchronize(ctx->stream));
     return ESDG_OK;
+}
+
+// Locality order of the elements: recursive coordinate bisection of the
+// element centroids (split the longer extent at the median).  Consecutive
+// elements, hence the elements of one workgroup and of neighbouring
+// workgroups, are close in space, so neighbour traces are mostly read from
+// LDS or the XCD's L2.
+void rcb_order(int32_t *idx, int64_t n, const std::vector<double> &cx, const std::vector<double> &cy)
+{
+    if (n <= 2) return;
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (int64_t k = 0; k < n; ++k) {
+        x0 = std::fmin(x0, cx[idx[k]]); x1 = std::fmax(x1, cx[idx[k]]);
+        y0 = std::fmin(y0, cy[idx[k]]); y1 = std::fmax(y1, cy[idx[k]]);
+    }
+    const bool byx = (x1 - x0) >= (y1 - y0);
+    const int64_t mid = n / 2;
+    std::nth_element(idx, idx + mid, idx + n, [&](int32_t a, int32_t b) {
+        const double va = byx ? cx[a] : cy[a], vb = byx ? cx[b] : cy[b];
+        return va < vb || (va == vb && a < b);
+    });
+    rcb_order(idx, mid, cx, cy);
+    rcb_order(idx + mid, n - mid, cx, cy);
 }
 
 template <typename T>
@@ -508,6 +566,36 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
                 return fail(ctx, ESDG_EMESH, "face map not symmetric at element %lld side %d", (long long)e, s);
             code[f] = (int8_t)(sn | (fv << 2));
         }
+    // locality order of the elements (internal), from the element centroids
+    const int64_t npn = (int64_t)(N + 1) * (N + 1);
+    std::vector<double> hx, hy;
+    const double *xs = x, *ys = y;
+    if (mem) {
+        hx.resize(K * npn);
+        hy.resize(K * npn);
+        CK(hipMemcpy(hx.data(), x, K * npn * sizeof(double), hipMemcpyDeviceToHost));
+        CK(hipMemcpy(hy.data(), y, K * npn * sizeof(double), hipMemcpyDeviceToHost));
+        xs = hx.data();
+        ys = hy.data();
+    }
+    std::vector<double> cxv(K), cyv(K);
+    for (int64_t e = 0; e < K; ++e) {
+        double sx = 0, sy = 0;
+        for (int64_t p = 0; p < npn; ++p) { sx += xs[e * npn + p]; sy += ys[e * npn + p]; }
+        cxv[e] = sx / npn;
+        cyv[e] = sy / npn;
+    }
+    std::vector<int32_t> perm(K), inv(K);
+    for (int64_t e = 0; e < K; ++e) perm[e] = (int32_t)e;
+    rcb_order(perm.data(), K, cxv, cyv);
+    for (int64_t e = 0; e < K; ++e) inv[perm[e]] = (int32_t)e;
+    std::vector<int32_t> ne2(4 * K);
+    std::vector<int8_t> code2(4 * K);
+    for (int64_t e = 0; e < K; ++e)
+        for (int s = 0; s < 4; ++s) {
+            ne2[e * 4 + s] = inv[ne[(int64_t)perm[e] * 4 + s]];
+            code2[e * 4 + s] = code[(int64_t)perm[e] * 4 + s];
+        }
     free_bufs(ctx);
     ctx->N = N;
     ctx->K = K;
@@ -570,11 +658,25 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(3 * kDtSlots), 0, ctx->stream, B.slots,
                        0x7FF0000000000000ull, 3 * kDtSlots);
     CK(hipGetLastError());
-    const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    CK(hipMemcpyAsync(B.x, x, n * sizeof(double), k, ctx->stream));
-    CK(hipMemcpyAsync(B.y, y, n * sizeof(double), k, ctx->stream));
-    CK(hipMemcpyAsync(B.nbr, ne.data(), 4 * K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    CK(hipMemcpyAsync(B.code, code.data(), 4 * K, hipMemcpyHostToDevice, ctx->stream));
+    TRY(alloc(ctx, &ctx->perm, K * sizeof(int32_t)));
+    CK(hipMemcpyAsync(ctx->perm, perm.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(B.nbr, ne2.data(), 4 * K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(B.code, code2.data(), 4 * K, hipMemcpyHostToDevice, ctx->stream));
+    {
+        const double *sx = x, *sy = y;
+        if (!mem) {
+            CK(hipMemcpyAsync(ctx->stage_d, x, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+            CK(hipMemcpyAsync(ctx->stage_d + n, y, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+            sx = ctx->stage_d;
+            sy = ctx->stage_d + n;
+        }
+        const unsigned g = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL((gather_kernel<double, double>), dim3(g), dim3(256), 0, ctx->stream, sx, B.x,
+                           ctx->perm, K, (int)npn);
+        hipLaunchKernelGGL((gather_kernel<double, double>), dim3(g), dim3(256), 0, ctx->stream, sy, B.y,
+                           ctx->perm, K, (int)npn);
+        CK(hipGetLastError());
+    }
     CK(dispatch(ctx, [&](auto L, auto) { return decltype(L)::geometry(ctx->B, ctx->td, ctx->stream); }));
     int flags[4];
     TRY(read_flags(ctx, flags));
@@ -593,11 +695,15 @@ int esdg_set_bathymetry(esdg_ctx *ctx, const double *b, int mem)
     if (!ctx->have_mesh) return fail(ctx, ESDG_EINVAL, "upload_mesh first");
     CK(hipSetDevice(ctx->device));
     const int64_t n = nodes(ctx);
-    const double *db = b;
+    const double *src = b;
     if (!mem) {
         CK(hipMemcpyAsync(ctx->stage_d, b, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        db = ctx->stage_d;
+        src = ctx->stage_d;
     }
+    double *db = ctx->stage_d + n;   // internal order
+    hipLaunchKernelGGL((gather_kernel<double, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       ctx->stream, src, db, ctx->perm, ctx->K, (ctx->N + 1) * (ctx->N + 1));
+    CK(hipGetLastError());
     CK(dispatch(ctx, [&](auto L, auto) { return decltype(L)::bathymetry(ctx->B, db, ctx->td, ctx->stream); }));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->have_b = true;
@@ -611,9 +717,10 @@ int esdg_set_state(esdg_ctx *ctx, const double *h, const double *hu, const doubl
     CK(hipSetDevice(ctx->device));
     const int64_t n = nodes(ctx);
     ctx->cur = 0;
-    TRY(upload_field(ctx, ctx->B.W[0][0], h, n, mem));
-    TRY(upload_field(ctx, ctx->B.W[0][1], hu, n, mem));
-    TRY(upload_field(ctx, ctx->B.W[0][2], hv, n, mem));
+    const int64_t per = n / ctx->K;
+    TRY(upload_field(ctx, ctx->B.W[0][0], h, per, mem));
+    TRY(upload_field(ctx, ctx->B.W[0][1], hu, per, mem));
+    TRY(upload_field(ctx, ctx->B.W[0][2], hv, per, mem));
     hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal + 4, 0.0);
     CK(hipGetLastError());
     invalidate_eps(ctx);
@@ -627,9 +734,10 @@ int esdg_get_state(esdg_ctx *ctx, double *h, double *hu, double *hv, int mem)
     if (!ctx->have_state) return fail(ctx, ESDG_EINVAL, "no state");
     CK(hipSetDevice(ctx->device));
     const int64_t n = nodes(ctx);
-    TRY(download_field(ctx, h, ctx->B.W[ctx->cur][0], n, mem));
-    TRY(download_field(ctx, hu, ctx->B.W[ctx->cur][1], n, mem));
-    TRY(download_field(ctx, hv, ctx->B.W[ctx->cur][2], n, mem));
+    const int64_t per = n / ctx->K;
+    TRY(download_field(ctx, h, ctx->B.W[ctx->cur][0], per, mem));
+    TRY(download_field(ctx, hu, ctx->B.W[ctx->cur][1], per, mem));
+    TRY(download_field(ctx, hv, ctx->B.W[ctx->cur][2], per, mem));
     return ESDG_OK;
 }
 
@@ -639,9 +747,10 @@ int esdg_rhs(esdg_ctx *ctx, double *rh, double *rhu, double *rhv, int mem)
     if (!check_ctx(ctx, true)) return ctx ? ESDG_EINVAL : ESDG_EINVAL;
     TRY(run_rhs(ctx, ctx->cur));
     const int64_t n = nodes(ctx);
-    TRY(download_field(ctx, rh, ctx->B.Rb[0], n, mem));
-    TRY(download_field(ctx, rhu, ctx->B.Rb[1], n, mem));
-    TRY(download_field(ctx, rhv, ctx->B.Rb[2], n, mem));
+    const int64_t per = n / ctx->K;
+    TRY(download_field(ctx, rh, ctx->B.Rb[0], per, mem));
+    TRY(download_field(ctx, rhu, ctx->B.Rb[1], per, mem));
+    TRY(download_field(ctx, rhv, ctx->B.Rb[2], per, mem));
     return ESDG_OK;
 }
 
@@ -803,7 +912,7 @@ int esdg_get_eps(esdg_ctx *ctx, double *eps, int mem)
         CK(hipMemsetAsync(ctx->B.eps[ctx->cur], 0, ctx->K * rsz(ctx), ctx->stream));
         ctx->eps_valid[ctx->cur] = false;
     }
-    return download_field(ctx, eps, ctx->B.eps[ctx->cur], ctx->K, mem);
+    return download_field(ctx, eps, ctx->B.eps[ctx->cur], 1, mem);
 }
 
 int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, double *yeta, double *J,
@@ -813,14 +922,15 @@ int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, dou
     CK(hipSetDevice(ctx->device));
     const int64_t n = nodes(ctx);
     const unsigned g = (unsigned)((n + 255) / 256);
+    const int npn = (ctx->N + 1) * (ctx->N + 1);
     if (ctx->prec == 64)
         hipLaunchKernelGGL((geometry_out_kernel<double>), dim3(g), dim3(256), 0, ctx->stream,
                            (const double *)ctx->B.Ax, (const double *)ctx->B.Cx, (const double *)ctx->B.Ae,
-                           (const double *)ctx->B.Ce, ctx->stage_d, n);
+                           (const double *)ctx->B.Ce, ctx->stage_d, ctx->perm, ctx->K, npn);
     else
         hipLaunchKernelGGL((geometry_out_kernel<float>), dim3(g), dim3(256), 0, ctx->stream,
                            (const float *)ctx->B.Ax, (const float *)ctx->B.Cx, (const float *)ctx->B.Ae,
-                           (const float *)ctx->B.Ce, ctx->stage_d, n);
+                           (const float *)ctx->B.Ce, ctx->stage_d, ctx->perm, ctx->K, npn);
     CK(hipGetLastError());
     double *outs[5] = {xxi, xeta, yxi, yeta, J};
     const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
