@@ -1,5 +1,7 @@
 // Instantiation of the kernels for one polynomial degree ESDG_N (set by the
 // build, one object file per degree so the degrees compile in parallel).
+#include <hip/hip_ext.h>
+
 #include "esdg_kernels.hpp"
 #include "esdg_launch.hpp"
 
@@ -53,6 +55,15 @@ hipError_t Launch<N, R>::geometry(const Bufs &B, const Tab<double> &td, hipStrea
     const int bs = 256;
     hipLaunchKernelGGL((geometry_kernel<N, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, B.K,
                        B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.flags + 3, td);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((gmax_kernel<N, R>), dim3((unsigned)((B.K + bs - 1) / bs)), dim3(bs), 0, s,
+                       mesh_view<R>(B), (R *)B.gmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nfn = B.K * 4 * (N + 1);
+    hipLaunchKernelGGL((face_geometry_kernel<N, R>), dim3((unsigned)((nfn + bs - 1) / bs)), dim3(bs), 0, s,
+                       mesh_view<R>(B), (R)td.w[0], (R *)B.fgeo);
     return hipGetLastError();
 }
 
@@ -72,7 +83,8 @@ hipError_t Launch<N, R>::bathymetry(const Bufs &B, const double *b, const Tab<do
 }
 
 template <int N, typename R>
-hipError_t Launch<N, R>::indicator(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
+hipError_t Launch<N, R>::indicator(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s,
+                                   Ev ev)
 {
     IndicatorArgs<N, R> a;
     a.P = P;
@@ -83,7 +95,7 @@ hipError_t Launch<N, R>::indicator(const Bufs &B, int buf, const Phys<R> &P, con
     a.list = B.list[buf];
     a.count = B.count + buf;
     a.ntiles = ntiles_of<N>(B.K);
-    hipLaunchKernelGGL((indicator_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, a);
+    hipExtLaunchKernelGGL((indicator_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0, a);
     return hipGetLastError();
 }
 
@@ -112,32 +124,33 @@ static ListArgs<N, R> list_args(const Bufs &B, int in, const Phys<R> &P, const T
 constexpr unsigned kListBlocks = 1024;
 
 template <int N, typename R>
-hipError_t Launch<N, R>::av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s)
+hipError_t Launch<N, R>::av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s,
+                                  Ev ev)
 {
-    hipLaunchKernelGGL((av_faces_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s,
-                       list_args<N, R>(B, in, P, t));
+    hipExtLaunchKernelGGL((av_faces_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0,
+                          list_args<N, R>(B, in, P, t));
     return hipGetLastError();
 }
 
 template <int N, typename R>
 hipError_t Launch<N, R>::av_div(const Bufs &B, int in, int reset, const Phys<R> &P, const Tab<R> &t,
-                                hipStream_t s)
+                                hipStream_t s, Ev ev)
 {
     ListArgs<N, R> a = list_args<N, R>(B, in, P, t);
     a.count_reset = reset >= 0 ? B.count + reset : nullptr;
-    hipLaunchKernelGGL((av_div_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s, a);
+    hipExtLaunchKernelGGL((av_div_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0, a);
     return hipGetLastError();
 }
 
 template <int N, typename R, int MODE>
-static void launch_stage(const StageArgs<R> &a, int64_t K, hipStream_t s)
+static void launch_stage(const StageArgs<R> &a, int64_t K, hipStream_t s, Ev ev)
 {
-    hipLaunchKernelGGL((stage_kernel<N, R, MODE>), tile_grid<N>(K), dim3(Shape<N>::T), 0, s, a);
+    hipExtLaunchKernelGGL((stage_kernel<N, R, MODE>), tile_grid<N>(K), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0, a);
 }
 
 template <int N, typename R>
 hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> &P, const Tab<R> &t,
-                               hipStream_t s)
+                               hipStream_t s, Ev ev)
 {
     StageArgs<R> a;
     a.m = mesh_view<R>(B);
@@ -163,14 +176,17 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.eps_out = c.out_rhs ? nullptr : (R *)B.eps[c.out];
     a.list_out = c.out_rhs ? nullptr : B.list[c.out];
     a.count_out = c.out_rhs ? nullptr : B.count + c.out;
+    a.dtc_out = c.dt_next && !c.out_rhs ? (R *)B.dtc : nullptr;
+    a.dtv_out = c.dt_next && !c.out_rhs && c.av ? (R *)B.dtv : nullptr;
+    a.gmax = (const R *)B.gmax;
     a.dt = B.dscal;
     a.ca = (R)c.ca;
     a.cb = (R)c.cb;
     a.flags = B.flags;
     a.ntiles = ntiles_of<N>(B.K);
-    if (c.mode == kModeRhs) launch_stage<N, R, kModeRhs>(a, B.K, s);
-    else if (c.mode == kModeLsrk) launch_stage<N, R, kModeLsrk>(a, B.K, s);
-    else launch_stage<N, R, kModeSsp>(a, B.K, s);
+    if (c.mode == kModeRhs) launch_stage<N, R, kModeRhs>(a, B.K, s, ev);
+    else if (c.mode == kModeLsrk) launch_stage<N, R, kModeLsrk>(a, B.K, s, ev);
+    else launch_stage<N, R, kModeSsp>(a, B.K, s, ev);
     return hipGetLastError();
 }
 
@@ -183,21 +199,25 @@ hipError_t Launch<N, R>::limit(const Bufs &B, int buf, const Phys<R> &P, const T
 }
 
 template <int N, typename R>
-hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, const Phys<R> &P, const Tab<R> &t,
-                            double br1_radius, hipStream_t s)
+hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s)
 {
-    DtArgs<N, R> a;
+    DtArgs<R> a;
     a.m = mesh_view<R>(B);
     a.P = P;
-    a.tab = t;
     a.h = (const R *)B.W[in][0];
     a.hu = (const R *)B.W[in][1];
     a.hv = (const R *)B.W[in][2];
-    a.eps = av ? (const R *)B.eps[in] : nullptr;
+    a.eps = av && !fused ? (const R *)B.eps[in] : nullptr;
+    a.dtc = fused ? (const R *)B.dtc : nullptr;
+    a.dtv = fused && av ? (const R *)B.dtv : nullptr;
+    a.gmax = (const R *)B.gmax;
+    a.fgeo = (const R *)B.fgeo;
     a.slots = B.slots;
-    a.br1_radius = br1_radius;
-    a.ntiles = ntiles_of<N>(B.K);
-    hipLaunchKernelGGL((dt_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, a);
+    constexpr int64_t np = (N + 1) * (N + 1);
+    const int64_t items = fused ? B.K * 4 * (N + 1) : B.K * np;
+    const int64_t want = ((items + kDtThreads * kXcds - 1) / (kDtThreads * kXcds)) * kXcds;
+    const unsigned grid = (unsigned)(want < (int64_t)kDtMaxBlocks ? want : (int64_t)kDtMaxBlocks);
+    hipLaunchKernelGGL((dt_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, a);
     return hipGetLastError();
 }
 

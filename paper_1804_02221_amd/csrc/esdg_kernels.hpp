@@ -89,6 +89,7 @@ struct Phys {
     R g, h_tol, eps0, sigma_min, sigma_max, cfl, cfl_visc;
     R i2g;                 // 1 / (2 g)
     R ratio_min, ratio_max; // 10^sigma_min, 10^sigma_max
+    R visc_c, br1;          // viscous bound: visc_c / (br1 eps max|grad|^2)
     int ec, limiter_on;
 };
 
@@ -638,6 +639,26 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
 // ------------------------------------------------------------------------
 enum StageMode { kModeRhs = 0, kModeLsrk = 1, kModeSsp = 2 };
 
+// CFL bound of one node: cfl (2/(N+1)) J / (|(A_xi . u)| + c |A_xi| + |(A_eta . u)| + c |A_eta|),
+// with the contravariant directions A_xi = (Ax, Cx), A_eta = (Ae, Ce).
+template <int N, typename R>
+__device__ __forceinline__ R cfl_bound(R h, R hu, R hv, R Ax, R Cx, R Ae, R Ce, R J, const Phys<R> &P)
+{
+    const R ih = rcp_wet(h, P.h_tol);
+    const R u = hu * ih, v = hv * ih;
+    const R cs = sqrt(P.g * (h > R(0) ? h : R(0)));
+    const R lx = fabs(Ax * u + Cx * v) + cs * sqrt(Ax * Ax + Cx * Cx);
+    const R le = fabs(Ae * u + Ce * v) + cs * sqrt(Ae * Ae + Ce * Ce);
+    return lx + le > R(0) ? P.cfl * (R(2) / R(N + 1)) * J / (lx + le) : R(3.0e38);
+}
+
+// Viscous bound of an element with viscosity eps > 0.
+template <typename R>
+__device__ __forceinline__ R visc_bound(R eps, R gmax, const Phys<R> &P)
+{
+    return P.visc_c / (P.br1 * eps * gmax);
+}
+
 template <typename R>
 struct StageArgs {
     Mesh<R> m;
@@ -654,6 +675,8 @@ struct StageArgs {
     R *eps_out;                  // [K] viscosity of the output state (update modes)
     int32_t *list_out;           // elements of the output state with eps > 0
     int *count_out;
+    R *dtc_out, *dtv_out;        // last stage of a step: per-element CFL / viscous bounds of the output
+    const R *gmax;               // [K] max |grad xi|^2 + |grad eta|^2 (viscous bound)
     const double *dt;            // device scalar: current step
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
     int *flags;                  // [0]: negative mean seen, [1]: limited elements
@@ -861,14 +884,25 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             a.oh[q] = nh; a.ohu[q] = nhu; a.ohv[q] = nhv;
             if constexpr (MODE == kModeLsrk) { a.dh[q] = d0; a.dhu[q] = d1; a.dhv[q] = d2; }
         }
+        R en = R(0);
         if (av) {
             // viscosity of the new state for the next stage (appendix A)
             s_st[8 * T + t] = nh;
             __syncthreads();
-            const R en = element_viscosity<N, R>(s_st + 8 * T, s_st, a.tab, P, t, el, p, lane, nh);
+            en = element_viscosity<N, R>(s_st + 8 * T, s_st, a.tab, P, t, el, p, lane, nh);
             if (act && p == 0) {
                 a.eps_out[e] = en;
                 if (en > R(0)) a.list_out[atomicAdd(a.count_out, 1)] = (int32_t)e;
+            }
+        }
+        if (a.dtc_out) {
+            // CFL and viscous bounds of the new state for the next step
+            R vals[1] = {act ? cfl_bound<N, R>(nh, nhu, nhv, Ax, Cx, Ae, Ce, J, P) : R(3.0e38)};
+            __syncthreads();   // scratch free
+            elem_totals<N, R, 1, true>(vals, s_st, t, el, p, lane);
+            if (act && p == 0) {
+                a.dtc_out[e] = vals[0];
+                if (a.dtv_out) a.dtv_out[e] = en > R(0) ? visc_bound<R>(en, a.gmax[e], P) : R(3.0e38);
             }
         }
     }
@@ -925,17 +959,29 @@ __global__ __launch_bounds__(Shape<N>::T) void limit_kernel(Mesh<R> m, Phys<R> P
 // Time step bounds: CFL, viscous (AV), Lemma 2.  Minima go to 64 slots per
 // bound by atomicMin on the bit patterns of non-negative doubles (which order
 // like unsigned integers); dt_finalize_kernel reduces and resets them.
+//
+// The last stage of every step leaves the per-element CFL and viscous bounds
+// of its output state in dtc/dtv (stage epilogue); the time-step pass then
+// only reduces those and evaluates Lemma 2 at the face nodes.  For a state
+// no stage produced (initial data, after a limiter call or a retry) the pass
+// evaluates every bound itself.  All loops are flat over nodes, face nodes
+// and elements, with a fixed grid: each XCD takes one contiguous range of
+// each index space so that neighbour traces hit its L2.  Each workgroup
+// issues one atomic per bound.
 // ------------------------------------------------------------------------
-template <int N, typename R>
+constexpr int kDtThreads = 256;
+constexpr unsigned kDtMaxBlocks = 2048;
+
+template <typename R>
 struct DtArgs {
     Mesh<R> m;
     Phys<R> P;
-    Tab<R> tab;
     const R *h, *hu, *hv;
-    const R *eps;              // nullptr without AV
+    const R *eps;              // full pass with AV: element viscosity of the state
+    const R *dtc, *dtv;        // per-element CFL / viscous bounds from the stage epilogue (nullptr: full pass)
+    const R *gmax;             // [K] max over the element's nodes of |grad xi|^2 + |grad eta|^2
+    const R *fgeo;             // [K][4][nf][3] outward unit normal and w_0 J / J^surf per face node
     unsigned long long *slots; // [3][kDtSlots]
-    double br1_radius;         // spectral radius of 1D BR1 at unit width/viscosity
-    int64_t ntiles;
 };
 
 __device__ __forceinline__ void slot_min(unsigned long long *slot, double v)
@@ -943,99 +989,152 @@ __device__ __forceinline__ void slot_min(unsigned long long *slot, double v)
     if (v >= 0.0 && v < __builtin_huge_val()) atomicMin(slot, (unsigned long long)__double_as_longlong(v));
 }
 
-template <int N, typename R>
-__global__ __launch_bounds__(Shape<N>::T) void dt_kernel(DtArgs<N, R> a)
+template <typename R>
+__device__ __forceinline__ R wave_min(R v)
 {
-    using S = Shape<N>;
-    constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
-    __shared__ R s_red[3 * T];
-    __shared__ R s_J[T], s_u[T], s_v[T];
-    const int64_t tile = xcd_tile(a.ntiles);
-    if (tile < 0) return;
-    const int t = threadIdx.x;
-    const bool lane = t < E * np;
-    const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0;
-    const int64_t e0 = tile * E, e = e0 + el;
-    const bool act = lane && (e < a.m.K);
-    const int64_t q = e * np + p;
-    const Phys<R> &P = a.P;
-    R cflb = R(3.0e38), gg = 0, J = 0, u = 0, v = 0;
-    if (act) {
-        const R h = a.h[q], ih = rcp_wet(h, P.h_tol);
-        u = a.hu[q] * ih;
-        v = a.hv[q] * ih;
-        const R c = sqrt(P.g * (h > R(0) ? h : R(0)));
-        const R Ax = a.m.Ax[q], Cx = a.m.Cx[q], Ae = a.m.Ae[q], Ce = a.m.Ce[q];
-        J = Ce * Ax - Cx * Ae;
-        const R lx = fabs(Ax * u + Cx * v) + c * sqrt(Ax * Ax + Cx * Cx);
-        const R le = fabs(Ae * u + Ce * v) + c * sqrt(Ae * Ae + Ce * Ce);
-        if (lx + le > R(0)) cflb = P.cfl * (R(2) / R(nf)) * J / (lx + le);
-        gg = (Ax * Ax + Cx * Cx + Ae * Ae + Ce * Ce) / (J * J);
-    }
-    s_J[t] = J;
-    s_u[t] = u;
-    s_v[t] = v;
-    __syncthreads();
-    // Lemma 2 bounds at the face nodes
-    R posb = R(3.0e38);
-    for (int f = t; f < NF; f += T) {
-        const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
-        const int64_t fe = e0 + fel;
-        if (fe >= a.m.K) continue;
-        int fi, fj, ns, kk;
-        int64_t en;
-        side_node<N>(s, k, fi, fj);
-        const int lp = fel * np + fi * nf + fj;
-        const int64_t qo = fe * np + fi * nf + fj;
-        const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
-        R snx, sny;
-        if (s == 1) { snx = a.m.Ax[qo]; sny = a.m.Cx[qo]; }
-        else if (s == 3) { snx = -a.m.Ax[qo]; sny = -a.m.Cx[qo]; }
-        else if (s == 2) { snx = a.m.Ae[qo]; sny = a.m.Ce[qo]; }
-        else { snx = -a.m.Ae[qo]; sny = -a.m.Ce[qo]; }
-        const R js = sqrt(snx * snx + sny * sny);
-        const R nx = snx / js, ny = sny / js;
-        const R aa = s_J[lp] / js;
-        const R hm = a.h[qo], hp = a.h[qn];
-        const R ip = rcp_wet(hp, P.h_tol);
-        const R utm = nx * s_u[lp] + ny * s_v[lp];
-        const R utp = nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
-        const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
-        const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
-        const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
-        const R w0 = a.tab.w[0];
-        const R den1 = A + R(2) * au;
-        if (den1 > R(0)) { const R bnd = w0 * aa / den1; posb = bnd < posb ? bnd : posb; }
-        const R den2 = ac * B * (utp - utm);
-        if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0 * aa * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
-    }
-    // per-element viscous bound
-    R viscb = R(3.0e38);
-    {
-        R vals[1] = {-gg};
-        ElemReduce<N, R, 1>::template run<true>(vals, s_red, t, el, p);
-        if (a.eps && act && p == 0) {
-            const R eps = a.eps[e];
-            if (eps > R(0)) viscb = P.cfl_visc * R(4.0 * kLsrkRealLimit) / (R(a.br1_radius) * eps * (-vals[0]));
-        }
-    }
-    // workgroup minima
-    s_red[t] = cflb;
-    s_red[T + t] = viscb;
-    s_red[2 * T + t] = posb;
-    __syncthreads();
-    for (int st = T / 2; st > 0; st >>= 1) {
-        if (t < st) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const R o = s_red[c * T + t + st];
-                if (o < s_red[c * T + t]) s_red[c * T + t] = o;
+    for (int off = 32; off > 0; off >>= 1) {
+        const R o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Per-element max of |grad xi|^2 + |grad eta|^2 (mesh constant; used by the
+// viscous bound).  One thread per element.
+template <int N, typename R>
+__global__ void gmax_kernel(Mesh<R> m, R *gmax)
+{
+    constexpr int np = (N + 1) * (N + 1);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m.K) return;
+    R gm = R(0);
+    for (int p = 0; p < np; ++p) {
+        const int64_t q = e * np + p;
+        const R Ax = m.Ax[q], Cx = m.Cx[q], Ae = m.Ae[q], Ce = m.Ce[q];
+        const R J = Ce * Ax - Cx * Ae;
+        const R gg = (Ax * Ax + Cx * Cx + Ae * Ae + Ce * Ce) / (J * J);
+        gm = gg > gm ? gg : gm;
+    }
+    gmax[e] = gm;
+}
+
+// Face geometry for Lemma 2 (mesh constant): per face node the outward unit
+// normal and w_0 J / J^surf.  One thread per face node.
+template <int N, typename R>
+__global__ void face_geometry_kernel(Mesh<R> m, R w0, R *fgeo)
+{
+    constexpr int nf = N + 1, np = nf * nf;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= m.K * 4 * nf) return;
+    const int64_t e = f / (4 * nf);
+    const int r = (int)(f - e * 4 * nf), s = r / nf, k = r - s * nf;
+    int i, j;
+    side_node<N>(s, k, i, j);
+    const int64_t q = e * np + i * nf + j;
+    const R Ax = m.Ax[q], Cx = m.Cx[q], Ae = m.Ae[q], Ce = m.Ce[q];
+    R snx, sny;
+    if (s == 1) { snx = Ax; sny = Cx; }
+    else if (s == 3) { snx = -Ax; sny = -Cx; }
+    else if (s == 2) { snx = Ae; sny = Ce; }
+    else { snx = -Ae; sny = -Ce; }
+    const R js = sqrt(snx * snx + sny * sny);
+    const R J = Ce * Ax - Cx * Ae;
+    fgeo[f * 3 + 0] = snx / js;
+    fgeo[f * 3 + 1] = sny / js;
+    fgeo[f * 3 + 2] = w0 * (J / js);
+}
+
+// Index range [b, e) and stride of this workgroup over n items: XCD x of 8
+// takes the x-th contiguous eighth.
+struct XcdRange {
+    int64_t b, e, stride;
+    __device__ XcdRange(int64_t n, int T)
+    {
+        const int64_t per = (n + kXcds - 1) / kXcds;
+        const int64_t lo = (int64_t)(blockIdx.x % kXcds) * per;
+        const int64_t hi = lo + per < n ? lo + per : n;
+        b = lo + (int64_t)(blockIdx.x / kXcds) * T + threadIdx.x;
+        e = hi;
+        stride = (int64_t)(gridDim.x / kXcds) * T;
+    }
+};
+
+template <int N, typename R>
+__global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
+{
+    constexpr int nf = N + 1, np = nf * nf, T = kDtThreads;
+    __shared__ R s_w[3][T / 64];
+    const Phys<R> &P = a.P;
+    const int64_t K = a.m.K;
+    R cflb = R(3.0e38), viscb = R(3.0e38), posb = R(3.0e38);
+    if (a.dtc) {
+        // per-element bounds left by the stage epilogue
+        for (XcdRange r(K, T); r.b < r.e; r.b += r.stride) {
+            const R c = a.dtc[r.b];
+            cflb = c < cflb ? c : cflb;
+            if (a.dtv) {
+                const R v = a.dtv[r.b];
+                viscb = v < viscb ? v : viscb;
             }
         }
-        __syncthreads();
+    } else {
+        for (XcdRange r(K * np, T); r.b < r.e; r.b += r.stride) {
+            const int64_t q = r.b;
+            const R Ax = a.m.Ax[q], Cx = a.m.Cx[q], Ae = a.m.Ae[q], Ce = a.m.Ce[q];
+            const R c = cfl_bound<N, R>(a.h[q], a.hu[q], a.hv[q], Ax, Cx, Ae, Ce, Ce * Ax - Cx * Ae, P);
+            cflb = c < cflb ? c : cflb;
+        }
+        if (a.eps) {
+            for (XcdRange r(K, T); r.b < r.e; r.b += r.stride) {
+                const R eps = a.eps[r.b];
+                if (eps > R(0)) {
+                    const R v = visc_bound<R>(eps, a.gmax[r.b], P);
+                    viscb = v < viscb ? v : viscb;
+                }
+            }
+        }
     }
+    if (P.limiter_on) {
+        // Lemma 2 at every face node: own trace '-', neighbour '+'
+        for (XcdRange r(K * 4 * nf, T); r.b < r.e; r.b += r.stride) {
+            const int64_t f = r.b;
+            const int64_t fe = f / (4 * nf);
+            const int rr = (int)(f - fe * 4 * nf), s = rr / nf, k = rr - s * nf;
+            int fi, fj, ns, kk;
+            int64_t en;
+            side_node<N>(s, k, fi, fj);
+            const int64_t qo = fe * np + fi * nf + fj;
+            const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+            const R nx = a.fgeo[f * 3 + 0], ny = a.fgeo[f * 3 + 1], w0a = a.fgeo[f * 3 + 2];
+            const R hm = a.h[qo], hp = a.h[qn];
+            const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
+            const R utm = nx * (a.hu[qo] * im) + ny * (a.hv[qo] * im);
+            const R utp = nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
+            const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
+            const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
+            const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
+            const R den1 = A + R(2) * au;
+            if (den1 > R(0)) { const R bnd = w0a / den1; posb = bnd < posb ? bnd : posb; }
+            const R den2 = ac * B * (utp - utm);
+            if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0a * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
+        }
+    }
+    // workgroup minima: within each wave by lane exchange, then across waves
+    cflb = wave_min(cflb);
+    viscb = wave_min(viscb);
+    posb = wave_min(posb);
+    const int t = threadIdx.x, wv = t >> 6;
+    if ((t & 63) == 0) {
+        s_w[0][wv] = cflb;
+        s_w[1][wv] = viscb;
+        s_w[2][wv] = posb;
+    }
+    __syncthreads();
     if (t < 3) {
-        const R v = s_red[t * T];
+        R v = s_w[t][0];
+#pragma unroll
+        for (int w = 1; w < T / 64; ++w) v = s_w[t][w] < v ? s_w[t][w] : v;
         if (v < R(1.0e38)) slot_min(&a.slots[t * kDtSlots + (blockIdx.x % kDtSlots)], (double)v);
     }
 }

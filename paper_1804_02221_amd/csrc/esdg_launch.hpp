@@ -18,12 +18,15 @@ struct Bufs {
     void *bx = nullptr, *by = nullptr, *bface = nullptr, *b = nullptr;
     int32_t *nbr = nullptr;
     int8_t *code = nullptr;
-    void *W[4][3] = {};      // state buffers [buffer][h, hu, hv]: ping-pong, W^n, retry backup
+    void *W[3][3] = {};      // state buffers [buffer][h, hu, hv]: W^n and the two stage outputs
     void *dU[3] = {};        // LSRK register
     void *Rb[3] = {};        // right-hand side output scratch
-    void *eps[4] = {};       // [K] element viscosity of each state buffer
-    int32_t *list[4] = {};   // [K] elements of each state buffer with eps > 0
-    int *count = nullptr;    // [4] list lengths
+    void *gmax = nullptr;    // [K] max |grad xi|^2 + |grad eta|^2 per element (mesh constant)
+    void *fgeo = nullptr;    // [K][4][nf][3] face unit normals and w_0 J / J^surf (mesh constant)
+    void *dtc = nullptr, *dtv = nullptr;  // [K] per-element CFL / viscous bounds of one state
+    void *eps[3] = {};       // [K] element viscosity of each state buffer
+    int32_t *list[3] = {};   // [K] elements of each state buffer with eps > 0
+    int *count = nullptr;    // [3] list lengths
     void *vtr = nullptr;     // [K][4][nf][4] viscous face fluxes (elements with eps > 0)
     void *lv[2] = {};        // [K][np] viscous terms L^v (momentum rows)
     double *dscal = nullptr; // [0..3] dt bounds, [4] time, [5..7] spare
@@ -33,27 +36,33 @@ struct Bufs {
     int64_t part_cap = 0;
 };
 
+// Optional events recorded by the launch itself around one kernel (timing).
+struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
 struct StageCall {
     int mode;          // kModeRhs, kModeLsrk, kModeSsp
     bool av;           // add the viscous terms of visc()
     int in, out, base; // state buffers: input, output, W^n (SSP)
     bool out_rhs;      // write into Rb instead of W[out]
     double ca, cb;     // stage coefficients
+    bool dt_next;      // last stage of a step: leave the output's dt bounds in dtc/dtv
 };
 
 template <int N, typename R>
 struct Launch {
     static hipError_t geometry(const Bufs &B, const Tab<double> &td, hipStream_t s);
     static hipError_t bathymetry(const Bufs &B, const double *b, const Tab<double> &td, hipStream_t s);
-    static hipError_t indicator(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
-    static hipError_t av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
+    static hipError_t indicator(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s,
+                                Ev ev);
+    static hipError_t av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s, Ev ev);
     static hipError_t av_div(const Bufs &B, int in, int reset, const Phys<R> &P, const Tab<R> &t,
-                             hipStream_t s);
+                             hipStream_t s, Ev ev);
     static hipError_t stage(const Bufs &B, const StageCall &c, const Phys<R> &P, const Tab<R> &t,
-                            hipStream_t s);
+                            hipStream_t s, Ev ev);
     static hipError_t limit(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
-    static hipError_t dt(const Bufs &B, int in, bool av, const Phys<R> &P, const Tab<R> &t,
-                         double br1_radius, hipStream_t s);
+    static hipError_t dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s);
     static hipError_t diag(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, int64_t *nblocks,
                            hipStream_t s);
     static int threads();

@@ -136,7 +136,8 @@ struct esdg_ctx {
     int64_t K = 0;
     bool have_mesh = false, have_b = false, have_state = false;
     int cur = 0;
-    bool eps_valid[4] = {false, false, false, false};   // viscosity/list of state buffer b are current
+    bool eps_valid[3] = {false, false, false};   // viscosity/list of state buffer b are current
+    int dtb_buf = -1;   // state buffer whose per-element dt bounds are in dtc/dtv (-1: none)
     HostTables ht{};
     Tab<double> td{};
     Tab<float> tf{};
@@ -195,6 +196,8 @@ Phys<R> phys(const esdg_ctx *c)
     p.i2g = (R)(0.5 / c->P.g);
     p.ratio_min = (R)std::pow(10.0, c->P.sigma_min);
     p.ratio_max = (R)std::pow(10.0, c->P.sigma_max);
+    p.visc_c = (R)(c->P.cfl_visc * 4.0 * kLsrkRealLimit);
+    p.br1 = (c->N >= 2 && c->N <= 8) ? (R)kBR1Radius[c->N] : R(1);
     p.ec = c->P.surface_flux == 1;
     p.limiter_on = c->P.limiter_on != 0;
     return p;
@@ -232,8 +235,8 @@ void free_bufs(esdg_ctx *c)
 {
     Bufs &B = c->B;
     void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
-                  B.vtr, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
-                  B.eps[0], B.eps[1], B.eps[2], B.eps[3], B.list[0], B.list[1], B.list[2], B.list[3]};
+                  B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
+                  B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2]};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (auto &w : B.W)
@@ -260,28 +263,27 @@ hipEvent_t next_event(esdg_ctx *c)
     return c->ev_pool[c->ev_next++];
 }
 
-// Launch with optional event timing.
+// Launch with optional timing: the events are recorded by the kernel
+// dispatch itself (no marker packets between kernels).
 template <typename F>
 int timed(esdg_ctx *ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F &&launch)
 {
-    hipEvent_t a = nullptr, b = nullptr;
+    Ev ev;
     if (ctx->prof) {
-        a = next_event(ctx);
-        b = next_event(ctx);
-        if (!a || !b) return fail(ctx, ESDG_EHIP, "hipEventCreate failed");
-        CK(hipEventRecord(a, ctx->stream));
+        ev.a = next_event(ctx);
+        ev.b = next_event(ctx);
+        if (!ev.a || !ev.b) return fail(ctx, ESDG_EHIP, "hipEventCreate failed");
     }
-    CK(launch());
-    if (ctx->prof) {
-        CK(hipEventRecord(b, ctx->stream));
-        log.emplace_back(a, b);
-    }
+    CK(launch(ev));
+    if (ctx->prof) log.emplace_back(ev.a, ev.b);
     return ESDG_OK;
 }
 
+// Derived per-state data (viscosity, viscous list, dt bounds) is stale.
 void invalidate_eps(esdg_ctx *ctx)
 {
     for (bool &v : ctx->eps_valid) v = false;
+    ctx->dtb_buf = -1;
 }
 
 // Element viscosity and viscous-element list of state buffer buf, when stale
@@ -291,10 +293,10 @@ int ensure_eps(esdg_ctx *ctx, int buf)
     if (ctx->eps_valid[buf]) return ESDG_OK;
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.count + buf, 0, 1);
     CK(hipGetLastError());
-    TRY(timed(ctx, ctx->ev_av, [&] {
+    TRY(timed(ctx, ctx->ev_av, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
-            return decltype(L)::indicator(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+            return decltype(L)::indicator(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
         });
     }));
     ctx->eps_valid[buf] = true;
@@ -306,38 +308,41 @@ int ensure_eps(esdg_ctx *ctx, int buf)
 int launch_viscous(esdg_ctx *ctx, int buf, int reset)
 {
     TRY(ensure_eps(ctx, buf));
-    TRY(timed(ctx, ctx->ev_av, [&] {
+    TRY(timed(ctx, ctx->ev_av, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
-            return decltype(L)::av_faces(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+            return decltype(L)::av_faces(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
         });
     }));
-    return timed(ctx, ctx->ev_av, [&] {
+    return timed(ctx, ctx->ev_av, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
-            return decltype(L)::av_div(ctx->B, buf, reset, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+            return decltype(L)::av_div(ctx->B, buf, reset, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
         });
     });
 }
 
 int launch_stage(esdg_ctx *ctx, const StageCall &sc)
 {
-    return timed(ctx, ctx->ev_stage, [&] {
+    return timed(ctx, ctx->ev_stage, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
-            return decltype(L)::stage(ctx->B, sc, phys<R>(ctx), tab<R>(ctx), ctx->stream);
+            return decltype(L)::stage(ctx->B, sc, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
         });
     });
 }
 
+// Time step of state buffer buf (fixed > 0: that step); the bounds the last
+// stage left for buf are used when current.
 int launch_dt(esdg_ctx *ctx, int buf, double fixed, int advance)
 {
     const bool av = ctx->P.av_on != 0;
     if (!(fixed > 0.0)) {
+        const bool fused = ctx->dtb_buf == buf;
+        if (av && !fused) TRY(ensure_eps(ctx, buf));
         CK(dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
-            return decltype(L)::dt(ctx->B, buf, av, phys<R>(ctx), tab<R>(ctx), kBR1Radius[ctx->N],
-                                   ctx->stream);
+            return decltype(L)::dt(ctx->B, buf, av, fused, phys<R>(ctx), ctx->stream);
         }));
     }
     hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
@@ -450,7 +455,7 @@ bool check_ctx(esdg_ctx *ctx, bool need_state)
 int run_rhs(esdg_ctx *ctx, int buf)
 {
     if (ctx->P.av_on) TRY(launch_viscous(ctx, buf, -1));
-    StageCall sc{kModeRhs, ctx->P.av_on != 0, buf, buf, buf, true, 0.0, 0.0};
+    StageCall sc{kModeRhs, ctx->P.av_on != 0, buf, buf, buf, true, 0.0, 0.0, false};
     return launch_stage(ctx, sc);
 }
 
@@ -523,6 +528,7 @@ int esdg_set_params(esdg_ctx *ctx, const esdg_params *p)
         p->integrator > 1 || p->max_dt_retries < 0 || !std::isfinite(p->h_tol))
         return fail(ctx, ESDG_EINVAL, "invalid parameter value");
     ctx->P = *p;
+    invalidate_eps(ctx);
     return ESDG_OK;
 }
 
@@ -631,6 +637,10 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     TRY(alloc(ctx, &B.nbr, K * 4 * sizeof(int32_t)));
     TRY(alloc(ctx, &B.code, K * 4));
     for (void *&p : B.eps) TRY(alloc(ctx, &p, K * r));
+    TRY(alloc(ctx, &B.gmax, K * r));
+    TRY(alloc(ctx, &B.dtc, K * r));
+    TRY(alloc(ctx, &B.dtv, K * r));
+    TRY(alloc(ctx, &B.fgeo, K * 4 * nf * 3 * r));
     for (int32_t *&p : B.list) TRY(alloc(ctx, &p, K * sizeof(int32_t)));
     TRY(alloc(ctx, &B.count, 4 * sizeof(int)));
     TRY(alloc(ctx, &B.lv[0], n * r));
@@ -763,6 +773,7 @@ int esdg_limit(esdg_ctx *ctx, int64_t *n_limited)
         return decltype(L)::limit(ctx->B, ctx->cur, phys<R>(ctx), tab<R>(ctx), ctx->stream);
     }));
     ctx->eps_valid[ctx->cur] = false;
+    if (ctx->dtb_buf == ctx->cur) ctx->dtb_buf = -1;
     int flags[4];
     TRY(read_flags(ctx, flags));
     if (n_limited) *n_limited = flags[1];
@@ -775,7 +786,6 @@ int esdg_compute_dt(esdg_ctx *ctx, double out[4])
     if (!out) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
     if (!check_ctx(ctx, true)) return ESDG_EINVAL;
     TRY(reset_flags(ctx));
-    if (ctx->P.av_on) TRY(ensure_eps(ctx, ctx->cur));
     TRY(launch_dt(ctx, ctx->cur, 0.0, 0));
     CK(hipMemcpyAsync(out, ctx->B.dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
@@ -790,46 +800,32 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
     const bool adaptive = !(dt > 0.0);
     const bool ssp = ctx->P.integrator == 1;
     const int retries = ctx->P.max_dt_retries;
+    const int nst = ssp ? 3 : 5;
+    const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
     TRY(reset_flags(ctx));
     int status = ESDG_OK;
     for (int it = 0; it < nsteps; ++it) {
+        // W^n stays untouched in its buffer for the whole step: the stages
+        // alternate between the other two (the last one ends in o1), so a
+        // retry restarts from it without a copy
         const int base = ctx->cur;
-        const int backup = 3;
-        if (retries > 0) {
-            const int64_t n = nodes(ctx);
-            for (int c = 0; c < 3; ++c)
-                CK(hipMemcpyAsync(ctx->B.W[backup][c], ctx->B.W[base][c], n * rsz(ctx),
-                                  hipMemcpyDeviceToDevice, ctx->stream));
-            TRY(reset_flags(ctx));
-        }
-        // the viscous bound of the step needs the viscosity of W^n
-        if (av) TRY(ensure_eps(ctx, base));
+        const int o1 = (base + 1) % 3, o2 = (base + 2) % 3;
+        if (retries > 0) TRY(reset_flags(ctx));
         TRY(launch_dt(ctx, base, adaptive ? 0.0 : dt, 1));
         for (int attempt = 0;; ++attempt) {
             int in = base;
-            if (!ssp) {
-                for (int k = 0; k < 5; ++k) {
-                    const int out = (in == 0) ? 1 : 0;
-                    if (av) TRY(launch_viscous(ctx, in, out));
-                    StageCall sc{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k]};
-                    TRY(launch_stage(ctx, sc));
-                    ctx->eps_valid[out] = av;   // written by the stage epilogue
-                    in = out;
-                }
-                ctx->cur = in;
-            } else {
-                const int o1 = (base + 1) % 3, o2 = (base + 2) % 3;
-                const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
-                const int outs[3] = {o1, o2, base};
-                for (int k = 0; k < 3; ++k) {
-                    if (av) TRY(launch_viscous(ctx, in, outs[k]));
-                    StageCall sc{kModeSsp, av, in, outs[k], base, false, al[k], be[k]};
-                    TRY(launch_stage(ctx, sc));
-                    ctx->eps_valid[outs[k]] = av;
-                    in = outs[k];
-                }
-                ctx->cur = base;
+            for (int k = 0; k < nst; ++k) {
+                const int out = (k % 2 == 0) ? o1 : o2;
+                if (av) TRY(launch_viscous(ctx, in, out));
+                const bool last = k == nst - 1;
+                StageCall sc = ssp ? StageCall{kModeSsp, av, in, out, base, false, al[k], be[k], last}
+                                   : StageCall{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k], last};
+                TRY(launch_stage(ctx, sc));
+                ctx->eps_valid[out] = av;   // written by the stage epilogue
+                in = out;
             }
+            ctx->cur = o1;
+            ctx->dtb_buf = o1;   // the last stage left its dt bounds
             if (retries <= 0) break;
             int flags[4];
             TRY(read_flags(ctx, flags));
@@ -837,13 +833,8 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 if (flags[0]) status = ESDG_ENEGMEAN;
                 break;
             }
-            // negative mean: restore W^n and retry with half the step
-            const int64_t n = nodes(ctx);
-            for (int c = 0; c < 3; ++c)
-                CK(hipMemcpyAsync(ctx->B.W[base][c], ctx->B.W[backup][c], n * rsz(ctx),
-                                  hipMemcpyDeviceToDevice, ctx->stream));
+            // negative mean: restart from W^n with half the step
             ctx->cur = base;
-            invalidate_eps(ctx);
             hipLaunchKernelGGL(scale_step_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal, 0.5,
                                ctx->B.dscal + 4);
             CK(hipGetLastError());

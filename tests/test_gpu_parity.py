@@ -140,6 +140,27 @@ def test_dt_limiter_eps_diagnostics(esdg, orc):
     s.close()
 
 
+@pytest.mark.parametrize("N,integrator", [(3, 0), (4, 1), (7, 0)])
+def test_dt_bounds_left_by_the_last_stage(esdg, orc, N, integrator):
+    """After a step the time-step pass reduces the per-element CFL and
+    viscous bounds the last stage left; they must equal the bounds of the
+    full pass on the same state and the oracle's after the same step."""
+    w = dam_break(6, N, seed=4, rotate_seed=3)
+    s, P = make_solver(esdg, w, av_on=1, limiter_on=1, eps0=0.05, integrator=integrator)
+    Po = oparams(orc, P)
+    s.step(1, 0.0)
+    fused = s.compute_dt()
+    h, hu, hv = s.get_state()
+    s.set_state(h, hu, hv)             # invalidates the stage's bounds: full pass
+    full = s.compute_dt()
+    assert np.allclose(fused, full, rtol=1e-14, atol=0), (fused, full)
+    ho, huo, hvo, _, _ = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
+    dto = orc.dt(Po, w.mesh, w.b, ho, huo, hvo)
+    assert np.allclose(fused, dto, rtol=1e-11, atol=0), (fused, dto)
+    assert np.isfinite(fused[2]) and fused[2] < 1e30, "viscous bound expected on the dam break"
+    s.close()
+
+
 @pytest.mark.parametrize("integrator,adaptive", [(0, False), (0, True), (1, True)])
 def test_step_parity_dam_break(esdg, orc, integrator, adaptive):
     w = dam_break(8, 5, seed=2, rotate_seed=2)
