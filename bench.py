@@ -77,7 +77,11 @@ def main():
     ap.add_argument("--no-av", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-patch", type=int, default=256)
-    ap.add_argument("--sweep", default="", help="comma list of extra N values to time (same mesh)")
+    ap.add_argument("--sweep", default="3,4,5,6,8",
+                    help="comma list of further N values to time on the same mesh ('' for none)")
+    ap.add_argument("--sweep-steps", type=int, default=10)
+    ap.add_argument("--fp32-check", type=int, default=1,
+                    help="also time the main N in FP32 (reported beside, not as value)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -94,10 +98,10 @@ def main():
     dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream()
 
-    def run(N):
-        log(f"generating {args.n}x{args.n} workload at N={N}")
+    def run(N, precision=args.precision, steps=args.steps, warmup=args.warmup):
+        log(f"generating {args.n}x{args.n} workload at N={N} (FP{precision})")
         w = smooth_sweep(args.n, N, seed=3)
-        s = esdg.Solver(dev, args.precision, stream=stream)
+        s = esdg.Solver(dev, precision, stream=stream)
         s.upload_mesh(w.mesh)
         P = esdg.default_params(N, av_on=0 if args.no_av else 1, limiter_on=1, eps0=0.025)
         s.set_params(P)
@@ -105,34 +109,35 @@ def main():
         s.set_state(w.h, w.hu, w.hv)
         K = w.mesh.K
         nodes = K * (N + 1) ** 2
-        log(f"uploaded K={K} nodes={nodes}; warmup {args.warmup} steps")
-        s.step(args.warmup, 0.0)
+        log(f"uploaded K={K} nodes={nodes}; warmup {warmup} steps")
+        s.step(warmup, 0.0)
         torch.cuda.synchronize()
         s.profile(True)
         s.profile_read()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        t_sim, _ = s.step(args.steps, 0.0)
+        t_sim, _ = s.step(steps, 0.0)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = s.profile_read()
         s.profile(False)
         d = s.diagnostics()
-        log(f"N={N}: {args.steps} steps in {el:.3f} s, t={t_sim:.4g}, min h={d[5]:.3g}")
-        rb = 8 if args.precision == 64 else 4
+        log(f"N={N}: {steps} steps in {el:.3f} s, t={t_sim:.4g}, min h={d[5]:.3g}")
+        rb = 8 if precision == 64 else 4
         av = not args.no_av
         per_step = sum(stage_bytes(N, K, av, rb, k) for k in range(5))
-        stage_total = per_step * args.steps
+        stage_total = per_step * steps
         stage_launch = prof["stage_launches"]
         stage_mean_ms = prof["stage_ms"] / max(stage_launch, 1)
         achieved = stage_total / (prof["stage_ms"] * 1e-3) / 1e9
-        res = dict(N=N, K=K, nodes=nodes, elapsed=el, t_sim=t_sim,
-                   value=nodes * 5 * args.steps / el,
-                   ms_per_step=el * 1e3 / args.steps,
+        res = dict(N=N, precision=precision, K=K, nodes=nodes, elapsed=el, t_sim=t_sim,
+                   value=nodes * 5 * steps / el,
+                   ms_per_step=el * 1e3 / steps,
                    stage_mean_ms=stage_mean_ms, stage_launches=stage_launch,
                    stage_bytes_per_launch=per_step / 5,
                    stage_GBs=achieved,
-                   av_ms_per_stage=prof["av_ms"] / (5 * args.steps),
+                   roofline_frac=achieved / HBM_PEAK_GBS,
+                   av_ms_per_stage=prof["av_ms"] / (5 * steps),
                    av_launches=prof["av_launches"])
         s.close()
         del w
@@ -160,9 +165,13 @@ def main():
     log("memcopy probe")
     mc = memcopy_probe(main_res["stage_bytes_per_launch"])
     sweep = []
+    keys = ("N", "precision", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs", "roofline_frac")
     for tok in [t for t in args.sweep.split(",") if t.strip()]:
-        r = run(int(tok))
-        sweep.append({k: r[k] for k in ("N", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs")})
+        r = run(int(tok), steps=args.sweep_steps, warmup=2)
+        sweep.append({k: r[k] for k in keys})
+    if args.fp32_check and args.precision == 64:
+        r = run(args.N, precision=32, steps=args.sweep_steps, warmup=2)
+        sweep.append({k: r[k] for k in keys})
 
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
