@@ -89,6 +89,7 @@ hipError_t Launch<N, R>::indicator(const Bufs &B, int buf, const Phys<R> &P, con
     IndicatorArgs<N, R> a;
     a.P = P;
     a.tab = t;
+    a.tg = (const Tab<R> *)B.tabg;
     a.K = B.K;
     a.h = (const R *)B.W[buf][0];
     a.eps = (R *)B.eps[buf];
@@ -106,6 +107,7 @@ static ListArgs<N, R> list_args(const Bufs &B, int in, const Phys<R> &P, const T
     a.m = mesh_view<R>(B);
     a.P = P;
     a.tab = t;
+    a.tg = (const Tab<R> *)B.tabg;
     a.h = (const R *)B.W[in][0];
     a.hu = (const R *)B.W[in][1];
     a.hv = (const R *)B.W[in][2];
@@ -156,6 +158,7 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.m = mesh_view<R>(B);
     a.P = P;
     a.tab = t;
+    a.tg = (const Tab<R> *)B.tabg;
     a.h = (const R *)B.W[c.in][0];
     a.hu = (const R *)B.W[c.in][1];
     a.hv = (const R *)B.W[c.in][2];

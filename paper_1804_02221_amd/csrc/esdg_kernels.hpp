@@ -68,6 +68,7 @@ __device__ __forceinline__ void side_node(int s, int k, int &i, int &j)
 template <typename R>
 struct Tab {
     R D[kMaxNF * kMaxNF];     // derivative matrix, row-major
+    R Dz[kMaxNF * kMaxNF];    // the same with a zero diagonal (flux differencing)
     R Vinv[kMaxNF * kMaxNF];  // Vandermonde inverse
     R w[kMaxNF];              // LGL weights
     R iw0;                    // 1 / w_0 (end weight)
@@ -233,6 +234,76 @@ __global__ void bathymetry_kernel(int64_t K, const double *__restrict__ x, const
 }
 
 // ------------------------------------------------------------------------
+// Cross-lane reductions inside one wave with DPP moves (GFX9 encodings:
+// quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E, row_mirror = 0x140,
+// row_half_mirror = 0x141, row_bcast:15 = 0x142, row_bcast:31 = 0x143).
+// Lanes of rows outside ROWMASK keep `old`.  Called in uniform control flow
+// with every lane of the wave active.
+// ------------------------------------------------------------------------
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_mov(double old, double v)
+{
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_mov(float old, float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF,
+                                                      false));
+}
+
+__device__ __forceinline__ double read_lane63(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float read_lane63(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+template <bool MIN, int CTRL, int ROWMASK, typename R>
+__device__ __forceinline__ R dpp_step(R v)
+{
+    const R o = dpp_mov<CTRL, ROWMASK>(MIN ? v : R(0), v);
+    return MIN ? (o < v ? o : v) : v + o;
+}
+
+// Sum (MIN: minimum) over the 16 lanes of each row, in every lane of the row.
+template <bool MIN, typename R>
+__device__ __forceinline__ R row16_reduce(R v)
+{
+    v = dpp_step<MIN, 0xB1, 0xF>(v);
+    v = dpp_step<MIN, 0x4E, 0xF>(v);
+    v = dpp_step<MIN, 0x141, 0xF>(v);
+    return dpp_step<MIN, 0x140, 0xF>(v);
+}
+
+// Sum (MIN: minimum) over the 64 lanes of the wave, in every lane.
+template <bool MIN, typename R>
+__device__ __forceinline__ R wave64_reduce(R v)
+{
+    v = row16_reduce<MIN>(v);
+    v = dpp_step<MIN, 0x142, 0xA>(v);
+    v = dpp_step<MIN, 0x143, 0xC>(v);
+    return read_lane63(v);
+}
+
+// True in every thread if pred holds in some thread of the workgroup.
+template <int T>
+__device__ __forceinline__ bool block_any(bool pred)
+{
+    if constexpr (T == 64) return __ballot(pred) != 0ull;   // one wave
+    else return __syncthreads_or(pred) != 0;
+}
+
+// ------------------------------------------------------------------------
 // Workgroup-level per-element reductions over the nodes of each element.
 // red: LDS scratch of T*NQ reals; returns the element total in every thread.
 // ------------------------------------------------------------------------
@@ -326,6 +397,26 @@ __device__ __forceinline__ void elem_totals(R (&v)[NQ], R *red, int t, int el, i
     }
 }
 
+// Element totals as elem_totals (valid at least in thread p == 0): with lane
+// exchanges where an element is one whole wave (np = 64) or one 16-lane row
+// of a one-wave workgroup (np = 16), through LDS otherwise.
+template <int N, typename R, int NQ, bool MINLAST>
+__device__ __forceinline__ void elem_totals_any(R (&v)[NQ], R *red, int t, int el, int p, bool lane)
+{
+    constexpr int np = (N + 1) * (N + 1);
+    if constexpr (Shape<N>::T == 64 && np == 64) {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c)
+            v[c] = (MINLAST && c == NQ - 1) ? wave64_reduce<true>(v[c]) : wave64_reduce<false>(v[c]);
+    } else if constexpr (Shape<N>::T == 64 && np == 16) {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c)
+            v[c] = (MINLAST && c == NQ - 1) ? row16_reduce<true>(v[c]) : row16_reduce<false>(v[c]);
+    } else {
+        elem_totals<N, R, NQ, MINLAST>(v, red, t, el, p, lane);
+    }
+}
+
 // ------------------------------------------------------------------------
 // Artificial viscosity (appendix A, Theorem 1)
 // ------------------------------------------------------------------------
@@ -377,10 +468,11 @@ __device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phy
     }
     const R q2 = Qh * Qh;
     const int mx = i > j ? i : j;
-    R vals[5] = {q2, mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0),
+    // the energy of all modes is the top shell's plus that of the modes up to N-1
+    R vals[4] = {mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0),
                  lane ? -h : R(3.0e38)};
-    elem_totals<N, R, 5, true>(vals, red, t, el, p, lane);
-    return viscosity_from_totals<R>(vals[0], vals[1], vals[2], vals[3], -vals[4], P);
+    elem_totals_any<N, R, 4, true>(vals, red, t, el, p, lane);
+    return viscosity_from_totals<R>(vals[0] + vals[1], vals[0], vals[1], vals[2], -vals[3], P);
 }
 
 // Viscous physical fluxes at node (i,j) of the element whose u, v are in
@@ -422,7 +514,8 @@ __device__ __forceinline__ void viscous_flux_at(int i, int j, const R *su, const
 template <int N, typename R>
 struct IndicatorArgs {
     Phys<R> P;
-    Tab<R> tab;
+    Tab<R> tab;                  // uniform entries (read as scalars)
+    const Tab<R> *tg;            // the same tables in device memory: per-lane entries
     int64_t K;
     const R *h;
     R *eps;             // [K]
@@ -447,7 +540,7 @@ __global__ __launch_bounds__(Shape<N>::T) void indicator_kernel(IndicatorArgs<N,
     const R h = act ? a.h[e * np + p] : R(0);
     s_h[t] = h;
     __syncthreads();
-    const R eps = element_viscosity<N, R>(s_h, s_red, a.tab, a.P, t, el, p, lane, h);
+    const R eps = element_viscosity<N, R>(s_h, s_red, *a.tg, a.P, t, el, p, lane, h);
     if (act && p == 0) {
         a.eps[e] = eps;
         if (eps > R(0)) a.list[atomicAdd(a.count, 1)] = (int32_t)e;
@@ -460,7 +553,8 @@ template <int N, typename R>
 struct ListArgs {
     Mesh<R> m;
     Phys<R> P;
-    Tab<R> tab;
+    Tab<R> tab;                  // uniform entries (read as scalars)
+    const Tab<R> *tg;            // the same tables in device memory: per-lane entries
     const R *h, *hu, *hv;     // stage input state
     const R *eps;             // [K] viscosity of this state
     const int32_t *list;      // elements with eps > 0
@@ -544,7 +638,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_faces_kernel(ListArgs<N, R> a)
             R Fv2, Fv3, Gv2, Gv3;
             viscous_flux_at<N, R>(fi, fj, s_u + fel * np, s_v + fel * np, s_us + fel * 4 * nf,
                                   s_vs + fel * 4 * nf, a.m.Ax[qo], a.m.Cx[qo], a.m.Ae[qo], a.m.Ce[qo],
-                                  s_h[lp] * a.eps[fe], a.tab, Fv2, Fv3, Gv2, Gv3);
+                                  s_h[lp] * a.eps[fe], *a.tg, Fv2, Fv3, Gv2, Gv3);
             R *o = a.vtr + ((fe * 4 + s) * nf + k) * 4;
             o[0] = Fv2;
             o[1] = Fv3;
@@ -598,7 +692,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
         if (act) {
             Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
             viscous_flux_at<N, R>(i, j, s_u + el * np, s_v + el * np, s_us + el * 4 * nf, s_vs + el * 4 * nf,
-                                  Ax, Cx, Ae, Ce, h * a.eps[e], a.tab, Fv2, Fv3, Gv2, Gv3);
+                                  Ax, Cx, Ae, Ce, h * a.eps[e], *a.tg, Fv2, Fv3, Gv2, Gv3);
         }
         // contravariant fluxes: F~v = J grad(xi) . (Fv, Gv), G~v = J grad(eta) . (Fv, Gv)
         s_Fv[0][t] = Ax * Fv2 + Cx * Gv2;
@@ -611,7 +705,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
             const int base = el * np;
 #pragma unroll
             for (int mm = 0; mm < nf; ++mm) {
-                const R di = a.tab.D[i * kMaxNF + mm], dj = a.tab.D[j * kMaxNF + mm];
+                const R di = a.tg->D[i * kMaxNF + mm], dj = a.tg->D[j * kMaxNF + mm];
                 Lv2 += di * s_Fv[0][base + mm * nf + j] + dj * s_Fv[2][base + i * nf + mm];
                 Lv3 += di * s_Fv[1][base + mm * nf + j] + dj * s_Fv[3][base + i * nf + mm];
             }
@@ -659,11 +753,16 @@ __device__ __forceinline__ R visc_bound(R eps, R gmax, const Phys<R> &P)
     return P.visc_c / (P.br1 * eps * gmax);
 }
 
+template <typename R> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 template <typename R>
 struct StageArgs {
     Mesh<R> m;
     Phys<R> P;
-    Tab<R> tab;
+    Tab<R> tab;                  // uniform entries (read as scalars)
+    const Tab<R> *tg;            // the same tables in device memory: per-lane entries
     const R *h, *hu, *hv;        // stage input W
     const R *h0, *hu0, *hv0;     // SSP: W^n
     R *oh, *ohu, *ohv;           // output: R (rhs mode) or the new state
@@ -689,12 +788,15 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
     using S = Shape<N>;
     constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
     static_assert((T & (T - 1)) == 0, "workgroup size must be a power of two");
-    // one contiguous staging region: reused as reduction scratch at the end
-    __shared__ R s_st[9 * T];
-    R *const s_h = s_st, *const s_hu = s_st + T, *const s_hv = s_st + 2 * T;
-    R *const s_u = s_st + 3 * T, *const s_v = s_st + 4 * T;
-    R *const s_Ax = s_st + 5 * T, *const s_Cx = s_st + 6 * T;
-    R *const s_Ae = s_st + 7 * T, *const s_Ce = s_st + 8 * T;
+    using V2 = typename Vec2<R>::type;
+    // one contiguous staging region: reused as reduction scratch at the end.
+    // Pairs read together are stored together (one 16-byte LDS read in FP64).
+    __shared__ __align__(16) R s_st[9 * T];
+    V2 *const s_q = (V2 *)s_st;               // (hu, hv)
+    V2 *const s_w = (V2 *)(s_st + 2 * T);     // (u, v)
+    V2 *const s_a = (V2 *)(s_st + 4 * T);     // J grad(xi)  = (Ax, Cx)
+    V2 *const s_b = (V2 *)(s_st + 6 * T);     // J grad(eta) = (Ae, Ce)
+    R *const s_h = s_st + 8 * T;
     __shared__ R s_fl[3][NF];
     __shared__ R s_lim[4 * E];
 
@@ -718,8 +820,11 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
     }
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
-    s_h[t] = h; s_hu[t] = hu; s_hv[t] = hv; s_u[t] = u; s_v[t] = v;
-    s_Ax[t] = Ax; s_Cx[t] = Cx; s_Ae[t] = Ae; s_Ce[t] = Ce;
+    s_h[t] = h;
+    s_q[t] = V2{hu, hv};
+    s_w[t] = V2{u, v};
+    s_a[t] = V2{Ax, Cx};
+    s_b[t] = V2{Ae, Ce};
     __syncthreads();
 
     // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node; for
@@ -736,18 +841,19 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             const int lp = fel * np + fi * nf + fj;
             const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
             // outward scaled normal: +-J grad(xi) on xi = +-1, +-J grad(eta) on eta = +-1
-            R snx, sny;
-            if (s == 1) { snx = s_Ax[lp]; sny = s_Cx[lp]; }
-            else if (s == 3) { snx = -s_Ax[lp]; sny = -s_Cx[lp]; }
-            else if (s == 2) { snx = s_Ae[lp]; sny = s_Ce[lp]; }
-            else { snx = -s_Ae[lp]; sny = -s_Ce[lp]; }
+            const V2 dir = (s & 1) ? s_a[lp] : s_b[lp];
+            const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
+            const R snx = sg * dir.x, sny = sg * dir.y;
             const R js = sqrt(snx * snx + sny * sny);
             const R ijs = R(1) / js;
             // neighbour trace: from LDS when the neighbour is in this workgroup
             const int64_t ql = qn - e0 * np;
             R hn, un, vn;
             if (ql >= 0 && ql < E * np) {
-                hn = s_h[ql]; un = s_u[ql]; vn = s_v[ql];
+                hn = s_h[ql];
+                const V2 w = s_w[ql];
+                un = w.x;
+                vn = w.y;
             } else {
                 hn = a.h[qn];
                 const R in = rcp_wet(hn, P.h_tol);
@@ -757,7 +863,8 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             const R bo = a.m.bface[(fe * 4 + s) * nf + k];
             const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
             R F0, F1, F2;
-            interface_flux<R>(s_h[lp], s_u[lp], s_v[lp], bo, hn, un, vn, bn, snx * ijs, sny * ijs, P, F0,
+            const V2 wl = s_w[lp];
+            interface_flux<R>(s_h[lp], wl.x, wl.y, bo, hn, un, vn, bn, snx * ijs, sny * ijs, P, F0,
                               F1, F2);
             const R sc = js * a.tab.iw0;
             c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
@@ -781,27 +888,28 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
         const int base = el * np;
 #pragma unroll
         for (int mm = 0; mm < nf; ++mm) {
-            if (mm == i) continue;
+            // the self pair has coefficient 0 (no branch: D~ has a zero diagonal)
             const int qq = base + mm * nf + j;
-            const R d = a.tab.D[i * kMaxNF + mm];
-            const R sA = Ax + s_Ax[qq], sC = Cx + s_Cx[qq];
-            const R f1 = (hu + s_hu[qq]) * sA + (hv + s_hv[qq]) * sC;
+            const R d = a.tg->Dz[i * kMaxNF + mm];
+            const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
+            const R sA = Ax + am.x, sC = Cx + am.y;
+            const R f1 = (hu + qm.x) * sA + (hv + qm.y) * sC;
             const R pp = h2g * s_h[qq];
             a1 += d * f1;
-            a2 += d * ((u + s_u[qq]) * f1 + pp * sA);
-            a3 += d * ((v + s_v[qq]) * f1 + pp * sC);
+            a2 += d * ((u + wm.x) * f1 + pp * sA);
+            a3 += d * ((v + wm.y) * f1 + pp * sC);
         }
 #pragma unroll
         for (int mm = 0; mm < nf; ++mm) {
-            if (mm == j) continue;
             const int qq = base + i * nf + mm;
-            const R d = a.tab.D[j * kMaxNF + mm];
-            const R sA = Ae + s_Ae[qq], sC = Ce + s_Ce[qq];
-            const R f1 = (hu + s_hu[qq]) * sA + (hv + s_hv[qq]) * sC;
+            const R d = a.tg->Dz[j * kMaxNF + mm];
+            const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
+            const R sA = Ae + bm.x, sC = Ce + bm.y;
+            const R f1 = (hu + qm.x) * sA + (hv + qm.y) * sC;
             const R pp = h2g * s_h[qq];
             b1 += d * f1;
-            b2 += d * ((u + s_u[qq]) * f1 + pp * sA);
-            b3 += d * ((v + s_v[qq]) * f1 + pp * sC);
+            b2 += d * ((u + wm.x) * f1 + pp * sA);
+            b3 += d * ((v + wm.y) * f1 + pp * sC);
         }
     }
     R L1 = R(0.5) * (a1 + b1), L2 = R(0.25) * (a2 + b2), L3 = R(0.25) * (a3 + b3);
@@ -848,11 +956,13 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             nhu = a.ca * w1 + a.cb * (hu + dt * R2);
             nhv = a.ca * w2 + a.cb * (hv + dt * R3);
         }
-        if (P.limiter_on) {
-            // positivity limiter (eq. PosPres) toward the J-weighted means
-            const R wq = act ? J * a.tab.w[i] * a.tab.w[j] : R(0);
+        // positivity limiter (eq. PosPres) toward the J-weighted means; an
+        // element without a negative node keeps theta = 1, so the means are
+        // only formed when some element of the workgroup has one
+        if (P.limiter_on && block_any<T>(act && nh < R(0))) {
+            const R wq = act ? J * a.tg->w[i] * a.tg->w[j] : R(0);
             R vals[5] = {wq, wq * nh, wq * nhu, wq * nhv, act ? nh : R(3.0e38)};
-            elem_totals<N, R, 5, true>(vals, s_st, t, el, p, lane);
+            elem_totals_any<N, R, 5, true>(vals, s_st, t, el, p, lane);
             if (lane && p == 0) {
                 const R area = vals[0];
                 const R mh = vals[1] / area, mhu = vals[2] / area, mhv = vals[3] / area, mn = vals[4];
@@ -878,8 +988,8 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
                 nhu = th * (nhu - mhu) + mhu;
                 nhv = th * (nhv - mhv) + mhv;
             }
-            if (nh < P.h_tol) { nhu = R(0); nhv = R(0); }
         }
+        if (P.limiter_on && nh < P.h_tol) { nhu = R(0); nhv = R(0); }
         if (act) {
             a.oh[q] = nh; a.ohu[q] = nhu; a.ohv[q] = nhv;
             if constexpr (MODE == kModeLsrk) { a.dh[q] = d0; a.dhu[q] = d1; a.dhv[q] = d2; }
@@ -889,7 +999,7 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             // viscosity of the new state for the next stage (appendix A)
             s_st[8 * T + t] = nh;
             __syncthreads();
-            en = element_viscosity<N, R>(s_st + 8 * T, s_st, a.tab, P, t, el, p, lane, nh);
+            en = element_viscosity<N, R>(s_st + 8 * T, s_st, *a.tg, P, t, el, p, lane, nh);
             if (act && p == 0) {
                 a.eps_out[e] = en;
                 if (en > R(0)) a.list_out[atomicAdd(a.count_out, 1)] = (int32_t)e;
@@ -899,7 +1009,7 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             // CFL and viscous bounds of the new state for the next step
             R vals[1] = {act ? cfl_bound<N, R>(nh, nhu, nhv, Ax, Cx, Ae, Ce, J, P) : R(3.0e38)};
             __syncthreads();   // scratch free
-            elem_totals<N, R, 1, true>(vals, s_st, t, el, p, lane);
+            elem_totals_any<N, R, 1, true>(vals, s_st, t, el, p, lane);
             if (act && p == 0) {
                 a.dtc_out[e] = vals[0];
                 if (a.dtv_out) a.dtv_out[e] = en > R(0) ? visc_bound<R>(en, a.gmax[e], P) : R(3.0e38);

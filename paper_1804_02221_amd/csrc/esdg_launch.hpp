@@ -22,6 +22,7 @@ struct Bufs {
     void *dU[3] = {};        // LSRK register
     void *Rb[3] = {};        // right-hand side output scratch
     void *gmax = nullptr;    // [K] max |grad xi|^2 + |grad eta|^2 per element (mesh constant)
+    void *tabg = nullptr;    // Tab<R> in device memory
     void *fgeo = nullptr;    // [K][4][nf][3] face unit normals and w_0 J / J^surf (mesh constant)
     void *dtc = nullptr, *dtv = nullptr;  // [K] per-element CFL / viscous bounds of one state
     void *eps[3] = {};       // [K] element viscosity of each state buffer

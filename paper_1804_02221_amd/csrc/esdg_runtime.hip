@@ -235,7 +235,7 @@ void free_bufs(esdg_ctx *c)
 {
     Bufs &B = c->B;
     void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
-                  B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
+                  B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
                   B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2]};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -616,6 +616,8 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         for (int j = 0; j <= N; ++j) {
             ctx->td.D[i * kMaxNF + j] = (double)ctx->ht.D[i][j];
             ctx->tf.D[i * kMaxNF + j] = (float)ctx->ht.D[i][j];
+            ctx->td.Dz[i * kMaxNF + j] = i == j ? 0.0 : (double)ctx->ht.D[i][j];
+            ctx->tf.Dz[i * kMaxNF + j] = i == j ? 0.0f : (float)ctx->ht.D[i][j];
             ctx->td.Vinv[i * kMaxNF + j] = (double)ctx->ht.Vinv[i][j];
             ctx->tf.Vinv[i * kMaxNF + j] = (float)ctx->ht.Vinv[i][j];
         }
@@ -641,6 +643,11 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     TRY(alloc(ctx, &B.dtc, K * r));
     TRY(alloc(ctx, &B.dtv, K * r));
     TRY(alloc(ctx, &B.fgeo, K * 4 * nf * 3 * r));
+    TRY(alloc(ctx, &B.tabg, ctx->prec == 64 ? sizeof(Tab<double>) : sizeof(Tab<float>)));
+    if (ctx->prec == 64)
+        CK(hipMemcpyAsync(B.tabg, &ctx->td, sizeof(Tab<double>), hipMemcpyHostToDevice, ctx->stream));
+    else
+        CK(hipMemcpyAsync(B.tabg, &ctx->tf, sizeof(Tab<float>), hipMemcpyHostToDevice, ctx->stream));
     for (int32_t *&p : B.list) TRY(alloc(ctx, &p, K * sizeof(int32_t)));
     TRY(alloc(ctx, &B.count, 4 * sizeof(int)));
     TRY(alloc(ctx, &B.lv[0], n * r));
