@@ -40,6 +40,14 @@ struct Shape {
     static_assert(E * np <= T, "elements must fit the workgroup");
 };
 
+// Waves per SIMD the stage kernel is compiled for (its register budget):
+// five for the FP64 update modes where that fits without spilling, else no
+// constraint.
+template <int N, typename R, int MODE>
+struct StageWaves {
+    static constexpr int value = (sizeof(R) == 8 && MODE != 0 && (N == 3 || N == 5 || N == 7)) ? 5 : 1;
+};
+
 constexpr int kXcds = 8;
 constexpr int kDtSlots = 64;
 
@@ -109,10 +117,24 @@ __device__ __forceinline__ int64_t nbr_node(const Mesh<R> &m, int64_t e, int s, 
     return en * np + i * nf + j;
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r) (quadratic convergence; normal positive x)
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <typename R>
 __device__ __forceinline__ R rcp_wet(R h, R h_tol)
 {
-    return h > h_tol ? R(1) / h : R(0);
+    return h > h_tol ? rcp_nr(h) : R(0);
 }
 
 // Rotated numerical interface flux along the unit normal (nx, ny), '-' =
@@ -126,8 +148,8 @@ __device__ __forceinline__ void interface_flux(R hm, R um, R vm, R bm, R hp, R u
     const R g = P.g;
     const R utm = nx * um + ny * vm, vtm = nx * vm - ny * um;
     const R utp = nx * up + ny * vp, vtp = nx * vp - ny * up;
-    const R cm = sqrt(g * (hm > R(0) ? hm : R(0)));
-    const R cp = sqrt(g * (hp > R(0) ? hp : R(0)));
+    const R cm = sqrt(g * fmax(hm, R(0)));
+    const R cp = sqrt(g * fmax(hp, R(0)));
     const R ah = R(0.5) * (hm + hp), au = R(0.5) * (utm + utp), av = R(0.5) * (vtm + vtp);
     const R ah2 = R(0.5) * (hm * hm + hp * hp), ac = R(0.5) * (cm + cp);
     R f0 = ah * au;
@@ -237,23 +259,22 @@ __global__ void bathymetry_kernel(int64_t K, const double *__restrict__ x, const
 // Cross-lane reductions inside one wave with DPP moves (GFX9 encodings:
 // quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E, row_mirror = 0x140,
 // row_half_mirror = 0x141, row_bcast:15 = 0x142, row_bcast:31 = 0x143).
-// Lanes of rows outside ROWMASK keep `old`.  Called in uniform control flow
-// with every lane of the wave active.
+// Lanes of rows outside ROWMASK receive an unspecified value.  Called in
+// uniform control flow with every lane of the wave active.
 // ------------------------------------------------------------------------
 template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_mov(double old, double v)
+__device__ __forceinline__ double dpp_mov(double v)
 {
-    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWMASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xF, false);
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, ROWMASK, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_mov(float old, float v)
+__device__ __forceinline__ float dpp_mov(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF,
-                                                      false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
 
 __device__ __forceinline__ double read_lane63(double v)
@@ -271,11 +292,12 @@ __device__ __forceinline__ float read_lane63(float v)
 template <bool MIN, int CTRL, int ROWMASK, typename R>
 __device__ __forceinline__ R dpp_step(R v)
 {
-    const R o = dpp_mov<CTRL, ROWMASK>(MIN ? v : R(0), v);
-    return MIN ? (o < v ? o : v) : v + o;
+    const R o = dpp_mov<CTRL, ROWMASK>(v);
+    return MIN ? fmin(o, v) : v + o;
 }
 
-// Sum (MIN: minimum) over the 16 lanes of each row, in every lane of the row.
+// Sum (MIN: minimum) over the 16 lanes of each row, in every lane of the row
+// (the four patterns read valid lanes only).
 template <bool MIN, typename R>
 __device__ __forceinline__ R row16_reduce(R v)
 {
@@ -285,7 +307,9 @@ __device__ __forceinline__ R row16_reduce(R v)
     return dpp_step<MIN, 0x140, 0xF>(v);
 }
 
-// Sum (MIN: minimum) over the 64 lanes of the wave, in every lane.
+// Sum (MIN: minimum) over the 64 lanes of the wave, in every lane: the row
+// totals are carried into lane 63 (rows 1, 3 add row 0, 2; rows 2, 3 add
+// lane 31), whose value is broadcast; the other lanes' partials are not used.
 template <bool MIN, typename R>
 __device__ __forceinline__ R wave64_reduce(R v)
 {
@@ -740,7 +764,7 @@ __device__ __forceinline__ R cfl_bound(R h, R hu, R hv, R Ax, R Cx, R Ae, R Ce, 
 {
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
-    const R cs = sqrt(P.g * (h > R(0) ? h : R(0)));
+    const R cs = sqrt(P.g * fmax(h, R(0)));
     const R lx = fabs(Ax * u + Cx * v) + cs * sqrt(Ax * Ax + Cx * Cx);
     const R le = fabs(Ae * u + Ce * v) + cs * sqrt(Ae * Ae + Ce * Ce);
     return lx + le > R(0) ? P.cfl * (R(2) / R(N + 1)) * J / (lx + le) : R(3.0e38);
@@ -783,7 +807,7 @@ struct StageArgs {
 };
 
 template <int N, typename R, int MODE>
-__global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
+__global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void stage_kernel(StageArgs<R> a)
 {
     using S = Shape<N>;
     constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
@@ -845,7 +869,7 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
             const R snx = sg * dir.x, sny = sg * dir.y;
             const R js = sqrt(snx * snx + sny * sny);
-            const R ijs = R(1) / js;
+            const R ijs = rcp_nr(js);
             // neighbour trace: from LDS when the neighbour is in this workgroup
             const int64_t ql = qn - e0 * np;
             R hn, un, vn;
@@ -929,7 +953,7 @@ __global__ __launch_bounds__(Shape<N>::T) void stage_kernel(StageArgs<R> a)
         bxv = a.m.bx[q]; byv = a.m.by[q];
         if (av && a.eps[e] > R(0)) { Lv2 = a.lv2[q]; Lv3 = a.lv3[q]; }
     }
-    const R iJ = act ? R(1) / J : R(0);
+    const R iJ = act ? rcp_nr(J) : R(0);
     const R hg = R(0.5) * P.g * h;
     const R R1 = -L1 * iJ;
     const R R2 = (-L2 - hg * bxv + Lv2) * iJ;
