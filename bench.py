@@ -37,18 +37,56 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int) -> float:
+def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_visc: int = 0) -> float:
     """Algorithmic HBM bytes of one launch of the fused stage kernel: every
     datum the stage must read or write, counted once.
     Reads: W (3/node), dU (3/node, not on the first LSRK stage), metric
     directions (4/node), split bathymetry derivatives (2/node), face
-    bathymetry (4(N+1)/element), with AV the element viscosity (1/element) and
-    the viscous face fluxes (16(N+1)/element).  Writes: W (3/node), dU (3/node)."""
+    bathymetry (4(N+1)/element); with AV the element viscosity (1/element)
+    and, for the n_visc elements with viscosity, their viscous face fluxes
+    (16(N+1)/element, read by their neighbours) and viscous terms (2/node).
+    Writes: W (3/node), dU (3/node, not on the last stage: the next step's
+    first stage does not read it)."""
     nf = N + 1
-    n = K * nf * nf
-    per_node = 3 + (3 if stage_index > 0 else 0) + 4 + 2 + 3 + 3
-    per_elem = 4 * nf + ((1 + 16 * nf) if av else 0)
-    return (per_node * n + per_elem * K) * real_bytes
+    np_ = nf * nf
+    n = K * np_
+    per_node = 3 + (3 if stage_index > 0 else 0) + 4 + 2 + 3 + (3 if stage_index < 4 else 0)
+    per_elem = 4 * nf + (1 if av else 0)
+    visc = (16 * nf + 2 * np_) * n_visc if av else 0
+    return (per_node * n + per_elem * K + visc) * real_bytes
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic_N7_512x512_fp64.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_1804_02221_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(src)):
+        if fn.endswith((".hpp", ".hip")):
+            h.update(fn.encode())
+            with open(os.path.join(src, fn), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per stage-kernel launch from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when it is missing or was taken on
+    other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(N: int, n_patch: int):
@@ -122,15 +160,16 @@ def main():
         prof = s.profile_read()
         s.profile(False)
         d = s.diagnostics()
+        n_visc = int((s.get_eps() > 0).sum()) if not args.no_av else 0
         log(f"N={N}: {steps} steps in {el:.3f} s, t={t_sim:.4g}, min h={d[5]:.3g}")
         rb = 8 if precision == 64 else 4
         av = not args.no_av
-        per_step = sum(stage_bytes(N, K, av, rb, k) for k in range(5))
+        per_step = sum(stage_bytes(N, K, av, rb, k, n_visc) for k in range(5))
         stage_total = per_step * steps
         stage_launch = prof["stage_launches"]
         stage_mean_ms = prof["stage_ms"] / max(stage_launch, 1)
         achieved = stage_total / (prof["stage_ms"] * 1e-3) / 1e9
-        res = dict(N=N, precision=precision, K=K, nodes=nodes, elapsed=el, t_sim=t_sim,
+        res = dict(N=N, precision=precision, K=K, nodes=nodes, elapsed=el, t_sim=t_sim, n_visc=n_visc,
                    value=nodes * 5 * steps / el,
                    ms_per_step=el * 1e3 / steps,
                    stage_mean_ms=stage_mean_ms, stage_launches=stage_launch,
@@ -179,6 +218,9 @@ def main():
         cpu = cpu_baseline(args.N, args.cpu_patch)
 
     frac = main_res["stage_GBs"] / HBM_PEAK_GBS
+    traffic = None
+    if args.N == 7 and args.n == 512 and args.precision == 64 and not args.no_av:
+        traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": main_res["value"],
@@ -201,8 +243,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": main_res["stage_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": frac, "traffic": None, "kernel": "stage_kernel",
+            "frac": frac, "traffic": traffic, "kernel": "stage_kernel",
             "bytes_per_launch": main_res["stage_bytes_per_launch"],
+            "viscous_elements": main_res["n_visc"],
             "mean_launch_ms": main_res["stage_mean_ms"],
         },
         "cpu_baseline": cpu,

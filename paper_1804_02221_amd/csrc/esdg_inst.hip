@@ -172,6 +172,7 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.dh = (R *)B.dU[0];
     a.dhu = (R *)B.dU[1];
     a.dhv = (R *)B.dU[2];
+    a.store_du = c.store_du ? 1 : 0;
     a.eps = c.av ? (const R *)B.eps[c.in] : nullptr;
     a.vtr = (const R *)B.vtr;
     a.lv2 = (const R *)B.lv[0];

@@ -48,6 +48,18 @@ struct StageWaves {
     static constexpr int value = (sizeof(R) == 8 && MODE != 0 && (N == 3 || N == 5 || N == 7)) ? 5 : 1;
 };
 
+// Workgroup barrier for exchanges through LDS only: orders LDS accesses
+// without waiting for outstanding global loads and stores (which
+// __syncthreads() would).  A one-wave workgroup needs no barrier.
+template <int T>
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if constexpr (T > 64) __builtin_amdgcn_s_barrier();
+    else __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 constexpr int kXcds = 8;
 constexpr int kDtSlots = 64;
 
@@ -340,7 +352,7 @@ struct ElemReduce {
     {
 #pragma unroll
         for (int c = 0; c < NQ; ++c) red[c * T + t] = v[c];
-        __syncthreads();
+        lds_sync<T>();
         R part[NQ];
         const bool row = (t < E * np) && (p < nf);   // thread (el, p<nf) reduces column p
         if (row) {
@@ -356,12 +368,12 @@ struct ElemReduce {
                 part[c] = s;
             }
         }
-        __syncthreads();
+        lds_sync<T>();
         if (row) {
 #pragma unroll
             for (int c = 0; c < NQ; ++c) red[c * T + el * np + p] = part[c];
         }
-        __syncthreads();
+        lds_sync<T>();
         if (t < E * np) {
 #pragma unroll
             for (int c = 0; c < NQ; ++c) {
@@ -375,7 +387,7 @@ struct ElemReduce {
                 v[c] = s;
             }
         }
-        __syncthreads();
+        lds_sync<T>();
     }
 };
 
@@ -389,7 +401,7 @@ __device__ __forceinline__ void elem_totals(R (&v)[NQ], R *red, int t, int el, i
     constexpr int nf = N + 1, np = nf * nf, T = Shape<N>::T;
 #pragma unroll
     for (int c = 0; c < NQ; ++c) red[c * T + t] = v[c];
-    __syncthreads();
+    lds_sync<T>();
     if (lane && p < nf) {
         // column p of element el; its total goes to the column's first slot,
         // which only this thread reads
@@ -405,7 +417,7 @@ __device__ __forceinline__ void elem_totals(R (&v)[NQ], R *red, int t, int el, i
             red[c * T + el * np + p] = s;
         }
     }
-    __syncthreads();
+    lds_sync<T>();
     if (lane && p == 0) {
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
@@ -484,7 +496,7 @@ __device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phy
         for (int r = 0; r < nf; ++r) Tq += tab.Vinv[i * kMaxNF + r] * sh[el * np + r * nf + j];
     }
     red[5 * T + t] = Tq;
-    __syncthreads();
+    lds_sync<T>();
     R Qh = 0;
     if (lane) {
 #pragma unroll
@@ -563,7 +575,7 @@ __global__ __launch_bounds__(Shape<N>::T) void indicator_kernel(IndicatorArgs<N,
     const bool act = lane && (e < a.K);
     const R h = act ? a.h[e * np + p] : R(0);
     s_h[t] = h;
-    __syncthreads();
+    lds_sync<T>();
     const R eps = element_viscosity<N, R>(s_h, s_red, *a.tg, a.P, t, el, p, lane, h);
     if (act && p == 0) {
         a.eps[e] = eps;
@@ -598,7 +610,7 @@ __device__ __forceinline__ void load_viscous_element(const ListArgs<N, R> &a, in
     using S = Shape<N>;
     constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
     if (lane && p == 0) s_e[el] = (g * E + el < cnt) ? (int64_t)a.list[g * E + el] : int64_t(-1);
-    __syncthreads();
+    lds_sync<T>();
     e = s_e[el];
     const bool act = lane && e >= 0;
     const int64_t q = e * np + p;
@@ -613,7 +625,7 @@ __device__ __forceinline__ void load_viscous_element(const ListArgs<N, R> &a, in
     s_h[t] = h;
     s_u[t] = u;
     s_v[t] = v;
-    __syncthreads();
+    lds_sync<T>();
     for (int f = t; f < NF; f += T) {
         const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
         const int64_t fe = s_e[fel];
@@ -631,7 +643,7 @@ __device__ __forceinline__ void load_viscous_element(const ListArgs<N, R> &a, in
         s_us[f] = us;
         s_vs[f] = vs;
     }
-    __syncthreads();
+    lds_sync<T>();
 }
 
 // Pass 1: the physical viscous fluxes h eps (U1, V1), h eps (U2, V2) on the
@@ -669,7 +681,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_faces_kernel(ListArgs<N, R> a)
             o[2] = Gv2;
             o[3] = Gv3;
         }
-        __syncthreads();
+        lds_sync<T>();
     }
 }
 
@@ -723,7 +735,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
         s_Fv[1][t] = Ax * Fv3 + Cx * Gv3;
         s_Fv[2][t] = Ae * Fv2 + Ce * Gv2;
         s_Fv[3][t] = Ae * Fv3 + Ce * Gv3;
-        __syncthreads();
+        lds_sync<T>();
         if (act) {
             R Lv2 = 0, Lv3 = 0;
             const int base = el * np;
@@ -748,7 +760,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
             a.lv2[q] = Lv2;
             a.lv3[q] = Lv3;
         }
-        __syncthreads();
+        lds_sync<T>();
     }
 }
 
@@ -791,6 +803,7 @@ struct StageArgs {
     const R *h0, *hu0, *hv0;     // SSP: W^n
     R *oh, *ohu, *ohv;           // output: R (rhs mode) or the new state
     R *dh, *dhu, *dhv;           // LSRK register dU (in place)
+    int store_du;                // 0 on the last LSRK stage: the next step's first stage does not read dU
     // artificial viscosity (nullptr eps: off)
     const R *eps;                // [K] viscosity of the input state
     const R *vtr;                // [K][4][nf][4] face viscous fluxes of viscous elements
@@ -849,7 +862,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
     s_w[t] = V2{u, v};
     s_a[t] = V2{Ax, Cx};
     s_b[t] = V2{Ae, Ce};
-    __syncthreads();
+    lds_sync<T>();
 
     // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node; for
     // an element without viscosity next to one with viscosity, also its only
@@ -937,7 +950,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
         }
     }
     R L1 = R(0.5) * (a1 + b1), L2 = R(0.25) * (a2 + b2), L3 = R(0.25) * (a3 + b3);
-    __syncthreads();   // face slots complete; staging region free from here on
+    lds_sync<T>();   // face slots complete; staging region free from here on
     {
         const int fb = el * 4 * nf;
         if (j == 0) { L1 += s_fl[0][fb + 0 * nf + i]; L2 += s_fl[1][fb + 0 * nf + i]; L3 += s_fl[2][fb + 0 * nf + i]; }
@@ -1004,7 +1017,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
                 s_lim[4 * el + 0] = th; s_lim[4 * el + 1] = mh;
                 s_lim[4 * el + 2] = mhu; s_lim[4 * el + 3] = mhv;
             }
-            __syncthreads();
+            lds_sync<T>();
             const R th = s_lim[4 * el];
             if (act && th != R(1)) {
                 const R mh = s_lim[4 * el + 1], mhu = s_lim[4 * el + 2], mhv = s_lim[4 * el + 3];
@@ -1016,13 +1029,15 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
         if (P.limiter_on && nh < P.h_tol) { nhu = R(0); nhv = R(0); }
         if (act) {
             a.oh[q] = nh; a.ohu[q] = nhu; a.ohv[q] = nhv;
-            if constexpr (MODE == kModeLsrk) { a.dh[q] = d0; a.dhu[q] = d1; a.dhv[q] = d2; }
+            if constexpr (MODE == kModeLsrk) {
+                if (a.store_du) { a.dh[q] = d0; a.dhu[q] = d1; a.dhv[q] = d2; }
+            }
         }
         R en = R(0);
         if (av) {
             // viscosity of the new state for the next stage (appendix A)
             s_st[8 * T + t] = nh;
-            __syncthreads();
+            lds_sync<T>();
             en = element_viscosity<N, R>(s_st + 8 * T, s_st, *a.tg, P, t, el, p, lane, nh);
             if (act && p == 0) {
                 a.eps_out[e] = en;
@@ -1032,7 +1047,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
         if (a.dtc_out) {
             // CFL and viscous bounds of the new state for the next step
             R vals[1] = {act ? cfl_bound<N, R>(nh, nhu, nhv, Ax, Cx, Ae, Ce, J, P) : R(3.0e38)};
-            __syncthreads();   // scratch free
+            lds_sync<T>();   // scratch free
             elem_totals_any<N, R, 1, true>(vals, s_st, t, el, p, lane);
             if (act && p == 0) {
                 a.dtc_out[e] = vals[0];
@@ -1264,7 +1279,7 @@ __global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
         s_w[1][wv] = viscb;
         s_w[2][wv] = posb;
     }
-    __syncthreads();
+    lds_sync<T>();
     if (t < 3) {
         R v = s_w[t][0];
 #pragma unroll
@@ -1306,7 +1321,7 @@ __global__ __launch_bounds__(Shape<N>::T) void diag_kernel(Mesh<R> m, Phys<R> P,
         v[7] = h > P.h_tol ? 0.0 : 1.0;
     }
     for (int c = 0; c < 8; ++c) s[c][t] = v[c];
-    __syncthreads();
+    lds_sync<T>();
     for (int st = T / 2; st > 0; st >>= 1) {
         if (t < st) {
             for (int c = 0; c < 5; ++c) s[c][t] += s[c][t + st];
@@ -1314,7 +1329,7 @@ __global__ __launch_bounds__(Shape<N>::T) void diag_kernel(Mesh<R> m, Phys<R> P,
             s[6][t] = fmax(s[6][t], s[6][t + st]);
             s[7][t] += s[7][t + st];
         }
-        __syncthreads();
+        lds_sync<T>();
     }
     if (t < 8) part[blockIdx.x * 8 + t] = s[t][0];
 }

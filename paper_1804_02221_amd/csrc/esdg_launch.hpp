@@ -49,6 +49,7 @@ struct StageCall {
     bool out_rhs;      // write into Rb instead of W[out]
     double ca, cb;     // stage coefficients
     bool dt_next;      // last stage of a step: leave the output's dt bounds in dtc/dtv
+    bool store_du;     // LSRK: write the register dU (not needed after the last stage)
 };
 
 template <int N, typename R>

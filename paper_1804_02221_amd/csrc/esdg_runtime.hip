@@ -826,7 +826,8 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 if (av) TRY(launch_viscous(ctx, in, out));
                 const bool last = k == nst - 1;
                 StageCall sc = ssp ? StageCall{kModeSsp, av, in, out, base, false, al[k], be[k], last}
-                                   : StageCall{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k], last};
+                                   : StageCall{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k], last,
+                                               !last};
                 TRY(launch_stage(ctx, sc));
                 ctx->eps_valid[out] = av;   // written by the stage epilogue
                 in = out;
