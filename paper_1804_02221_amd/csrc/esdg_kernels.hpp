@@ -40,12 +40,13 @@ struct Shape {
     static_assert(E * np <= T, "elements must fit the workgroup");
 };
 
-// Waves per SIMD the stage kernel is compiled for (its register budget):
-// five for the FP64 update modes where that fits without spilling, else no
-// constraint.
+// Waves per SIMD the stage kernel is compiled for (its register budget) in
+// the FP64 update modes: five (four at N = 8); a few spilled bytes at N = 2,
+// 4, 6, 8 cost less than the occupancy they buy (measured).  No constraint
+// otherwise.
 template <int N, typename R, int MODE>
 struct StageWaves {
-    static constexpr int value = (sizeof(R) == 8 && MODE != 0 && (N == 3 || N == 5 || N == 7)) ? 5 : 1;
+    static constexpr int value = (sizeof(R) == 8 && MODE != 0) ? (N == 8 ? 4 : 5) : 1;
 };
 
 // Workgroup barrier for exchanges through LDS only: orders LDS accesses
