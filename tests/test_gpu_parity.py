@@ -191,7 +191,56 @@ def test_step_parity_lake_bump_lsrk(esdg, orc):
     s.close()
 
 
-@pytest.mark.parametrize("N", [3, 7])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8])
+def test_step_parity_every_degree(esdg, orc, N):
+    """Two adaptive LSRK(5,4) steps with AV and limiter at every degree
+    (every workgroup shape, ragged last tiles, rotated element frames)."""
+    w = smooth_sweep(5, N, seed=40 + N, rotate_seed=N)
+    rng = np.random.default_rng(100 + N)
+    w.hu = w.hu + 0.05 * rng.standard_normal(w.hu.shape)
+    s, P = make_solver(esdg, w, av_on=1, limiter_on=1, eps0=0.05, sigma_min=-30.0, sigma_max=-1.0)
+    Po = oparams(orc, P)
+    t_gpu, _ = s.step(2, 0.0)
+    h, hu, hv, t_orc, _ = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 2, 0.0)
+    assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+    sc = term_scale(orc, w.mesh, w.h, w.b)
+    check_fields(s.get_state(), (h, hu, hv), 20.0 * sc * t_orc, 1e-12, f"step N={N}")
+    s.close()
+
+
+@pytest.mark.parametrize("N", [2, 5, 8])
+def test_two_by_two_mesh(esdg, orc, N):
+    """2 x 2 periodic elements: each element meets the same neighbour across
+    two opposite sides (and itself nowhere); RHS and one step."""
+    w = smooth_sweep(2, N, seed=50 + N, rotate_seed=N)
+    s, P = make_solver(esdg, w, av_on=1, limiter_on=1, eps0=0.05, sigma_min=-30.0, sigma_max=-1.0)
+    Po = oparams(orc, P)
+    Ro = orc.rhs(Po, w.mesh, w.b, w.h, w.hu, w.hv)
+    sc = term_scale(orc, w.mesh, w.h, w.b)
+    check_fields(s.rhs(), Ro[:3], sc, TOL64, f"2x2 rhs N={N}")
+    t_gpu, _ = s.step(1, 0.0)
+    h, hu, hv, t_orc, _ = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
+    check_fields(s.get_state(), (h, hu, hv), 20.0 * sc * t_orc, 1e-12, f"2x2 step N={N}")
+    s.close()
+
+
+def test_full_size_step_parity(esdg, orc):
+    """One adaptive LSRK(5,4) step with AV and limiter on the 512 x 512
+    curvilinear N = 7 workload the benchmark times, every node against the
+    oracle."""
+    w = smooth_sweep(512, 7, seed=3)
+    s, P = make_solver(esdg, w, av_on=1, limiter_on=1, eps0=0.025)
+    Po = oparams(orc, P)
+    t_gpu, _ = s.step(1, 0.0)
+    got = s.get_state()
+    s.close()
+    h, hu, hv, t_orc, _ = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
+    assert abs(t_gpu - t_orc) <= 1e-12 * t_orc
+    sc = term_scale(orc, w.mesh, w.h, w.b)
+    check_fields(got, (h, hu, hv), 20.0 * sc * t_orc, 1e-12, "full-size step")
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8])
 def test_fp32_variant(esdg, orc, N):
     w = smooth_sweep(5, N, seed=30 + N)
     s, P = make_solver(esdg, w, prec=32, av_on=1, eps0=0.05, sigma_min=-30.0, sigma_max=-1.0)
