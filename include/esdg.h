@@ -194,6 +194,45 @@ const char *esdg_last_error(const esdg_ctx *ctx);
 /* ABI version (major*100 + minor). */
 int esdg_abi_version(void);
 
+/* ------------------------------------------------------------------------
+ * Ensembles (batched instances)
+ * ------------------------------------------------------------------------
+ * Many independent problems -- each with its own mesh, degree, bathymetry,
+ * initial state, time step and time -- advanced together.  The instances of
+ * one degree form one context whose mesh is the disjoint union of their
+ * meshes, so that every kernel launch covers all of them (small meshes that
+ * would not fill the GPU alone share the launch); each instance keeps its
+ * own adaptive step (the same bounds as esdg_compute_dt, reduced per
+ * instance) and its own time.  Different degrees run on separate streams.
+ * The arithmetic of every instance is that of a single-instance context.
+ *
+ * esdg_ensemble_add copies the instance (host pointers only; arrays as in
+ * esdg_upload_mesh, esdg_set_bathymetry and esdg_set_state) and returns
+ * its id (0, 1, ...).  Instances of one degree must have identical
+ * parameters; max_dt_retries must be 0 (ESDG_EINVAL otherwise).
+ * esdg_ensemble_build uploads everything (done by the first step or query
+ * if not called); no instance can be added afterwards.
+ * esdg_ensemble_step advances every instance by nsteps adaptive steps and
+ * returns when they are done (ESDG_ENEGMEAN / ESDG_EDTPOS if any instance
+ * met a negative element mean / had no admissible step).
+ * esdg_ensemble_get_state / _get_time return one instance's state (mem:
+ * 0 host, 1 device destination) and time.
+ */
+typedef struct esdg_ensemble esdg_ensemble;
+
+int esdg_ensemble_create(esdg_ensemble **out, int device, int precision);
+int esdg_ensemble_destroy(esdg_ensemble *en);
+int esdg_ensemble_add(esdg_ensemble *en, const esdg_params *p, int N, int64_t K, const double *x,
+                      const double *y, const int32_t *nbr_elem, const int8_t *nbr_side,
+                      const int8_t *flip, const double *b, const double *h, const double *hu,
+                      const double *hv, int *id);
+int esdg_ensemble_build(esdg_ensemble *en);
+int esdg_ensemble_step(esdg_ensemble *en, int nsteps);
+int esdg_ensemble_size(const esdg_ensemble *en, int *n);
+int esdg_ensemble_get_state(esdg_ensemble *en, int id, double *h, double *hu, double *hv, int mem);
+int esdg_ensemble_get_time(esdg_ensemble *en, int id, double *t);
+const char *esdg_ensemble_last_error(const esdg_ensemble *en);
+
 #ifdef __cplusplus
 }
 #endif

@@ -183,6 +183,7 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.dtc_out = c.dt_next && !c.out_rhs ? (R *)B.dtc : nullptr;
     a.dtv_out = c.dt_next && !c.out_rhs && c.av ? (R *)B.dtv : nullptr;
     a.gmax = (const R *)B.gmax;
+    a.inst = B.n_inst > 1 ? B.inst : nullptr;
     a.dt = B.dscal;
     a.ca = (R)c.ca;
     a.cb = (R)c.cb;
@@ -217,6 +218,14 @@ hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, bool fused, const Ph
     a.gmax = (const R *)B.gmax;
     a.fgeo = (const R *)B.fgeo;
     a.slots = B.slots;
+    a.cstart = B.cstart;
+    a.cinst = B.cinst;
+    a.nchunks = B.nchunks;
+    if (B.n_inst > 1) {
+        const unsigned grid = (unsigned)(B.nchunks < (int64_t)kDtMaxBlocks ? B.nchunks : (int64_t)kDtMaxBlocks);
+        hipLaunchKernelGGL((dt_batch_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, a);
+        return hipGetLastError();
+    }
     constexpr int64_t np = (N + 1) * (N + 1);
     const int64_t items = fused ? B.K * 4 * (N + 1) : B.K * np;
     const int64_t want = ((items + kDtThreads * kXcds - 1) / (kDtThreads * kXcds)) * kXcds;

@@ -813,8 +813,9 @@ struct StageArgs {
     int32_t *list_out;           // elements of the output state with eps > 0
     int *count_out;
     R *dtc_out, *dtv_out;        // last stage of a step: per-element CFL / viscous bounds of the output
+    const int32_t *inst;         // [K] instance of each element (ensembles), nullptr: one instance
     const R *gmax;               // [K] max |grad xi|^2 + |grad eta|^2 (viscous bound)
-    const double *dt;            // device scalar: current step
+    const double *dt;            // per instance k: the current step at dt[8k]
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
     int *flags;                  // [0]: negative mean seen, [1]: limited elements
     int64_t ntiles;
@@ -977,7 +978,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
         if (act) { a.oh[q] = R1; a.ohu[q] = R2; a.ohv[q] = R3; }
         return;
     } else {
-        const R dt = (R)(*a.dt);
+        const R dt = (R)a.dt[a.inst ? 8 * (int64_t)a.inst[act ? e : e0] : 0];
         R nh, nhu, nhv;
         R d0 = 0, d1 = 0, d2 = 0;
         if constexpr (MODE == kModeLsrk) {
@@ -1120,6 +1121,7 @@ __global__ __launch_bounds__(Shape<N>::T) void limit_kernel(Mesh<R> m, Phys<R> P
 // issues one atomic per bound.
 // ------------------------------------------------------------------------
 constexpr int kDtThreads = 256;
+constexpr int64_t kDtChunk = 256;   // elements per chunk of the ensemble time-step pass
 constexpr unsigned kDtMaxBlocks = 2048;
 
 template <typename R>
@@ -1131,7 +1133,10 @@ struct DtArgs {
     const R *dtc, *dtv;        // per-element CFL / viscous bounds from the stage epilogue (nullptr: full pass)
     const R *gmax;             // [K] max over the element's nodes of |grad xi|^2 + |grad eta|^2
     const R *fgeo;             // [K][4][nf][3] outward unit normal and w_0 J / J^surf per face node
-    unsigned long long *slots; // [3][kDtSlots]
+    unsigned long long *slots; // [instance][3][kDtSlots]
+    const int64_t *cstart;     // ensembles: element chunks [cstart[c], cstart[c+1]) inside one instance
+    const int32_t *cinst;      //   and the instance of chunk c
+    int64_t nchunks;
 };
 
 __device__ __forceinline__ void slot_min(unsigned long long *slot, double v)
@@ -1210,67 +1215,49 @@ struct XcdRange {
     }
 };
 
+// Lemma 2 bounds at face node f (own trace '-', neighbour '+').
 template <int N, typename R>
-__global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
+__device__ __forceinline__ R lemma2_bound(const DtArgs<R> &a, int64_t f)
 {
-    constexpr int nf = N + 1, np = nf * nf, T = kDtThreads;
-    __shared__ R s_w[3][T / 64];
+    constexpr int nf = N + 1, np = nf * nf;
     const Phys<R> &P = a.P;
-    const int64_t K = a.m.K;
-    R cflb = R(3.0e38), viscb = R(3.0e38), posb = R(3.0e38);
-    if (a.dtc) {
-        // per-element bounds left by the stage epilogue
-        for (XcdRange r(K, T); r.b < r.e; r.b += r.stride) {
-            const R c = a.dtc[r.b];
-            cflb = c < cflb ? c : cflb;
-            if (a.dtv) {
-                const R v = a.dtv[r.b];
-                viscb = v < viscb ? v : viscb;
-            }
-        }
-    } else {
-        for (XcdRange r(K * np, T); r.b < r.e; r.b += r.stride) {
-            const int64_t q = r.b;
-            const R Ax = a.m.Ax[q], Cx = a.m.Cx[q], Ae = a.m.Ae[q], Ce = a.m.Ce[q];
-            const R c = cfl_bound<N, R>(a.h[q], a.hu[q], a.hv[q], Ax, Cx, Ae, Ce, Ce * Ax - Cx * Ae, P);
-            cflb = c < cflb ? c : cflb;
-        }
-        if (a.eps) {
-            for (XcdRange r(K, T); r.b < r.e; r.b += r.stride) {
-                const R eps = a.eps[r.b];
-                if (eps > R(0)) {
-                    const R v = visc_bound<R>(eps, a.gmax[r.b], P);
-                    viscb = v < viscb ? v : viscb;
-                }
-            }
-        }
-    }
-    if (P.limiter_on) {
-        // Lemma 2 at every face node: own trace '-', neighbour '+'
-        for (XcdRange r(K * 4 * nf, T); r.b < r.e; r.b += r.stride) {
-            const int64_t f = r.b;
-            const int64_t fe = f / (4 * nf);
-            const int rr = (int)(f - fe * 4 * nf), s = rr / nf, k = rr - s * nf;
-            int fi, fj, ns, kk;
-            int64_t en;
-            side_node<N>(s, k, fi, fj);
-            const int64_t qo = fe * np + fi * nf + fj;
-            const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
-            const R nx = a.fgeo[f * 3 + 0], ny = a.fgeo[f * 3 + 1], w0a = a.fgeo[f * 3 + 2];
-            const R hm = a.h[qo], hp = a.h[qn];
-            const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
-            const R utm = nx * (a.hu[qo] * im) + ny * (a.hv[qo] * im);
-            const R utp = nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
-            const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
-            const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
-            const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
-            const R den1 = A + R(2) * au;
-            if (den1 > R(0)) { const R bnd = w0a / den1; posb = bnd < posb ? bnd : posb; }
-            const R den2 = ac * B * (utp - utm);
-            if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0a * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
-        }
-    }
-    // workgroup minima: within each wave by lane exchange, then across waves
+    const int64_t fe = f / (4 * nf);
+    const int rr = (int)(f - fe * 4 * nf), s = rr / nf, k = rr - s * nf;
+    int fi, fj, ns, kk;
+    int64_t en;
+    side_node<N>(s, k, fi, fj);
+    const int64_t qo = fe * np + fi * nf + fj;
+    const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+    const R nx = a.fgeo[f * 3 + 0], ny = a.fgeo[f * 3 + 1], w0a = a.fgeo[f * 3 + 2];
+    const R hm = a.h[qo], hp = a.h[qn];
+    const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
+    const R utm = nx * (a.hu[qo] * im) + ny * (a.hv[qo] * im);
+    const R utp = nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
+    const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
+    const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
+    const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
+    R posb = R(3.0e38);
+    const R den1 = A + R(2) * au;
+    if (den1 > R(0)) { const R bnd = w0a / den1; posb = bnd < posb ? bnd : posb; }
+    const R den2 = ac * B * (utp - utm);
+    if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0a * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
+    return posb;
+}
+
+// CFL bound at node q from the stored state and metric.
+template <int N, typename R>
+__device__ __forceinline__ R cfl_node(const DtArgs<R> &a, int64_t q)
+{
+    const R Ax = a.m.Ax[q], Cx = a.m.Cx[q], Ae = a.m.Ae[q], Ce = a.m.Ce[q];
+    return cfl_bound<N, R>(a.h[q], a.hu[q], a.hv[q], Ax, Cx, Ae, Ce, Ce * Ax - Cx * Ae, a.P);
+}
+
+// Workgroup minima of the three bounds into slots[3][kDtSlots] (slot sl).
+template <typename R>
+__device__ __forceinline__ void dt_block_min(R cflb, R viscb, R posb, unsigned long long *slots, int sl)
+{
+    constexpr int T = kDtThreads;
+    __shared__ R s_w[3][T / 64];
     cflb = wave_min(cflb);
     viscb = wave_min(viscb);
     posb = wave_min(posb);
@@ -1285,7 +1272,93 @@ __global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
         R v = s_w[t][0];
 #pragma unroll
         for (int w = 1; w < T / 64; ++w) v = s_w[t][w] < v ? s_w[t][w] : v;
-        if (v < R(1.0e38)) slot_min(&a.slots[t * kDtSlots + (blockIdx.x % kDtSlots)], (double)v);
+        if (v < R(1.0e38)) slot_min(&slots[t * kDtSlots + sl], (double)v);
+    }
+    lds_sync<T>();
+}
+
+template <int N, typename R>
+__global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
+{
+    constexpr int nf = N + 1, np = nf * nf, T = kDtThreads;
+    const int64_t K = a.m.K;
+    R cflb = R(3.0e38), viscb = R(3.0e38), posb = R(3.0e38);
+    if (a.dtc) {
+        // per-element bounds left by the stage epilogue
+        for (XcdRange r(K, T); r.b < r.e; r.b += r.stride) {
+            const R c = a.dtc[r.b];
+            cflb = c < cflb ? c : cflb;
+            if (a.dtv) {
+                const R v = a.dtv[r.b];
+                viscb = v < viscb ? v : viscb;
+            }
+        }
+    } else {
+        for (XcdRange r(K * np, T); r.b < r.e; r.b += r.stride) {
+            const R c = cfl_node<N, R>(a, r.b);
+            cflb = c < cflb ? c : cflb;
+        }
+        if (a.eps) {
+            for (XcdRange r(K, T); r.b < r.e; r.b += r.stride) {
+                const R eps = a.eps[r.b];
+                if (eps > R(0)) {
+                    const R v = visc_bound<R>(eps, a.gmax[r.b], a.P);
+                    viscb = v < viscb ? v : viscb;
+                }
+            }
+        }
+    }
+    if (a.P.limiter_on) {
+        for (XcdRange r(K * 4 * nf, T); r.b < r.e; r.b += r.stride) {
+            const R v = lemma2_bound<N, R>(a, r.b);
+            posb = v < posb ? v : posb;
+        }
+    }
+    dt_block_min<R>(cflb, viscb, posb, a.slots, blockIdx.x % kDtSlots);
+}
+
+// The same per instance of an ensemble: each workgroup takes whole chunks
+// of elements (a chunk lies inside one instance) and adds its minima to that
+// instance's slots.
+template <int N, typename R>
+__global__ __launch_bounds__(kDtThreads) void dt_batch_kernel(DtArgs<R> a)
+{
+    constexpr int nf = N + 1, np = nf * nf, T = kDtThreads;
+    const int t = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+        const int64_t lo = a.cstart[c], hi = a.cstart[c + 1];
+        R cflb = R(3.0e38), viscb = R(3.0e38), posb = R(3.0e38);
+        if (a.dtc) {
+            for (int64_t e = lo + t; e < hi; e += T) {
+                const R v = a.dtc[e];
+                cflb = v < cflb ? v : cflb;
+                if (a.dtv) {
+                    const R w = a.dtv[e];
+                    viscb = w < viscb ? w : viscb;
+                }
+            }
+        } else {
+            for (int64_t q = lo * np + t; q < hi * np; q += T) {
+                const R v = cfl_node<N, R>(a, q);
+                cflb = v < cflb ? v : cflb;
+            }
+            if (a.eps) {
+                for (int64_t e = lo + t; e < hi; e += T) {
+                    const R eps = a.eps[e];
+                    if (eps > R(0)) {
+                        const R v = visc_bound<R>(eps, a.gmax[e], a.P);
+                        viscb = v < viscb ? v : viscb;
+                    }
+                }
+            }
+        }
+        if (a.P.limiter_on) {
+            for (int64_t f = lo * 4 * nf + t; f < hi * 4 * nf; f += T) {
+                const R v = lemma2_bound<N, R>(a, f);
+                posb = v < posb ? v : posb;
+            }
+        }
+        dt_block_min<R>(cflb, viscb, posb, a.slots + (int64_t)a.cinst[c] * 3 * kDtSlots, (int)(c % kDtSlots));
     }
 }
 

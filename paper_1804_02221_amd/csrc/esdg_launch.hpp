@@ -30,8 +30,13 @@ struct Bufs {
     int *count = nullptr;    // [3] list lengths
     void *vtr = nullptr;     // [K][4][nf][4] viscous face fluxes (elements with eps > 0)
     void *lv[2] = {};        // [K][np] viscous terms L^v (momentum rows)
-    double *dscal = nullptr; // [0..3] dt bounds, [4] time, [5..7] spare
-    unsigned long long *slots = nullptr;  // [3][kDtSlots]
+    double *dscal = nullptr; // per instance k: [8k..8k+3] dt and its bounds, [8k+4] time, [8k+5..7] spare
+    unsigned long long *slots = nullptr;  // [instance][3][kDtSlots]
+    int n_inst = 1;          // instances (ensembles); > 1: the arrays below are set
+    int32_t *inst = nullptr;    // [K] instance of each internal element
+    int64_t *cstart = nullptr;  // [nchunks + 1] element chunks of the time-step pass (never across instances)
+    int32_t *cinst = nullptr;   // [nchunks] instance of each chunk
+    int64_t nchunks = 0;
     int *flags = nullptr;    // [0] neg mean, [1] limited count, [2] bad dt, [3] bad J
     double *part = nullptr;  // diagnostics partial sums
     int64_t part_cap = 0;

@@ -21,9 +21,13 @@ namespace esdg {
 // Reduce the dt slots: dt[0] = step, dt[1..3] = CFL, viscous, Lemma 2
 // bounds; fixed > 0 overrides the step.  Adds the step to *tacc when
 // advance.  Resets the slots to +inf.
-__global__ void dt_finalize_kernel(unsigned long long *slots, double *dt, double fixed, int use_pos,
-                                   int advance, double *tacc, int *flags)
+__global__ void dt_finalize_kernel(unsigned long long *slots_all, double *dt_all, double fixed, int use_pos,
+                                   int advance, int *flags)
 {
+    // workgroup k: instance k (slots [3][kDtSlots], scalars dt[8k..8k+7], time at dt[8k+4])
+    unsigned long long *slots = slots_all + (int64_t)blockIdx.x * 3 * kDtSlots;
+    double *dt = dt_all + 8 * (int64_t)blockIdx.x;
+    double *tacc = dt + 4;
     __shared__ double s[3][kDtSlots];
     const int t = threadIdx.x;
     const unsigned long long inf = 0x7FF0000000000000ull;
@@ -77,9 +81,11 @@ __global__ void scale_step_kernel(double *dt, double f, double *tacc)
     }
 }
 
-__global__ void set_scalar_kernel(double *p, double v)
+// p[8k] = v for the n instances k (times live at dscal[8k + 4]).
+__global__ void set_scalar_kernel(double *p, double v, int n)
 {
-    if (threadIdx.x == 0) p[0] = v;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[8 * k] = v;
 }
 
 // Element permutation between the caller's order and the internal
@@ -138,6 +144,10 @@ struct esdg_ctx {
     int cur = 0;
     bool eps_valid[3] = {false, false, false};   // viscosity/list of state buffer b are current
     int dtb_buf = -1;   // state buffer whose per-element dt bounds are in dtc/dtv (-1: none)
+    // instances (ensembles): element ranges [inst_off[k], inst_off[k+1]) in
+    // the caller's order and, since the locality order permutes inside each
+    // range, in the internal order too
+    std::vector<int64_t> inst_off{0, 0};
     HostTables ht{};
     Tab<double> td{};
     Tab<float> tf{};
@@ -180,6 +190,7 @@ int fail(esdg_ctx *c, int code, const char *fmt, ...)
     } while (0)
 
 int64_t nodes(const esdg_ctx *c) { return c->K * (int64_t)(c->N + 1) * (c->N + 1); }
+int n_inst(const esdg_ctx *c) { return (int)c->inst_off.size() - 1; }
 size_t rsz(const esdg_ctx *c) { return c->prec == 64 ? sizeof(double) : sizeof(float); }
 
 template <typename R>
@@ -236,7 +247,7 @@ void free_bufs(esdg_ctx *c)
     Bufs &B = c->B;
     void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
                   B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
-                  B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2]};
+                  B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2], B.inst, B.cstart, B.cinst};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (auto &w : B.W)
@@ -251,6 +262,7 @@ void free_bufs(esdg_ctx *c)
     c->perm = nullptr;
     c->stage_d = nullptr;
     c->have_mesh = c->have_b = c->have_state = false;
+    c->inst_off = {0, 0};
 }
 
 hipEvent_t next_event(esdg_ctx *c)
@@ -332,8 +344,8 @@ int launch_stage(esdg_ctx *ctx, const StageCall &sc)
     });
 }
 
-// Time step of state buffer buf (fixed > 0: that step); the bounds the last
-// stage left for buf are used when current.
+// Time step of state buffer buf (fixed > 0: that step) for every instance;
+// the bounds the last stage left for buf are used when current.
 int launch_dt(esdg_ctx *ctx, int buf, double fixed, int advance)
 {
     const bool av = ctx->P.av_on != 0;
@@ -345,9 +357,8 @@ int launch_dt(esdg_ctx *ctx, int buf, double fixed, int advance)
             return decltype(L)::dt(ctx->B, buf, av, fused, phys<R>(ctx), ctx->stream);
         }));
     }
-    hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
-                       ctx->B.dscal, fixed, ctx->P.limiter_on ? 1 : 0, advance, ctx->B.dscal + 4,
-                       ctx->B.flags);
+    hipLaunchKernelGGL(dt_finalize_kernel, dim3(n_inst(ctx)), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
+                       ctx->B.dscal, fixed, ctx->P.limiter_on ? 1 : 0, advance, ctx->B.flags);
     CK(hipGetLastError());
     return ESDG_OK;
 }
@@ -452,6 +463,37 @@ bool check_ctx(esdg_ctx *ctx, bool need_state)
     return hipSetDevice(ctx->device) == hipSuccess;
 }
 
+// One time step launched on the context stream, no host synchronisation and
+// no retry: the dt pass (dt > 0: that step for every instance; skipped when
+// !with_dt, the step already in place) and the stages.
+int launch_one_step(esdg_ctx *ctx, double dt, bool with_dt = true)
+{
+    const bool av = ctx->P.av_on != 0;
+    const bool ssp = ctx->P.integrator == 1;
+    const int nst = ssp ? 3 : 5;
+    const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
+    // W^n stays untouched in its buffer for the whole step: the stages
+    // alternate between the other two (the last one ends in o1), so a retry
+    // restarts from it without a copy
+    const int base = ctx->cur;
+    const int o1 = (base + 1) % 3, o2 = (base + 2) % 3;
+    if (with_dt) TRY(launch_dt(ctx, base, dt > 0.0 ? dt : 0.0, 1));
+    int in = base;
+    for (int k = 0; k < nst; ++k) {
+        const int out = (k % 2 == 0) ? o1 : o2;
+        if (av) TRY(launch_viscous(ctx, in, out));
+        const bool last = k == nst - 1;
+        StageCall sc = ssp ? StageCall{kModeSsp, av, in, out, base, false, al[k], be[k], last}
+                           : StageCall{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k], last, !last};
+        TRY(launch_stage(ctx, sc));
+        ctx->eps_valid[out] = av;   // written by the stage epilogue
+        in = out;
+    }
+    ctx->cur = o1;
+    ctx->dtb_buf = o1;   // the last stage left its dt bounds
+    return ESDG_OK;
+}
+
 int run_rhs(esdg_ctx *ctx, int buf)
 {
     if (ctx->P.av_on) TRY(launch_viscous(ctx, buf, -1));
@@ -463,7 +505,7 @@ int run_rhs(esdg_ctx *ctx, int buf)
 
 extern "C" {
 
-int esdg_abi_version(void) { return 100; }
+int esdg_abi_version(void) { return 101; }
 
 void esdg_default_params(esdg_params *p, int N)
 {
@@ -539,8 +581,14 @@ int esdg_get_params(const esdg_ctx *ctx, esdg_params *p)
     return ESDG_OK;
 }
 
-int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const double *y,
-                     const int32_t *nbr_elem, const int8_t *nbr_side, const int8_t *flip, int mem)
+}  // extern "C"
+
+namespace {
+
+// Mesh upload for one or several instances: off = element ranges of the
+// instances (caller's order; the face map must not cross them).
+int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const double *y, const int32_t *nbr_elem,
+                     const int8_t *nbr_side, const int8_t *flip, int mem, const std::vector<int64_t> &off)
 {
     if (!ctx) return ESDG_EINVAL;
     if (N < 2 || N > kMaxN) return fail(ctx, ESDG_EINVAL, "N=%d outside [2, %d]", N, kMaxN);
@@ -591,9 +639,20 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         cxv[e] = sx / npn;
         cyv[e] = sy / npn;
     }
+    const int ni = (int)off.size() - 1;
+    if (ni < 1 || off[0] != 0 || off[ni] != K) return fail(ctx, ESDG_EINVAL, "bad instance ranges");
+    std::vector<int32_t> inst_of(K);
+    for (int k = 0; k < ni; ++k) {
+        if (off[k + 1] <= off[k]) return fail(ctx, ESDG_EINVAL, "empty instance %d", k);
+        for (int64_t e = off[k]; e < off[k + 1]; ++e) inst_of[e] = k;
+    }
+    for (int64_t f = 0; f < 4 * K; ++f)
+        if (inst_of[ne[f]] != inst_of[f / 4])
+            return fail(ctx, ESDG_EMESH, "face map connects two instances at element %lld", (long long)(f / 4));
+    // locality order inside each instance (instances stay contiguous)
     std::vector<int32_t> perm(K), inv(K);
     for (int64_t e = 0; e < K; ++e) perm[e] = (int32_t)e;
-    rcb_order(perm.data(), K, cxv, cyv);
+    for (int k = 0; k < ni; ++k) rcb_order(perm.data() + off[k], off[k + 1] - off[k], cxv, cyv);
     for (int64_t e = 0; e < K; ++e) inv[perm[e]] = (int32_t)e;
     std::vector<int32_t> ne2(4 * K);
     std::vector<int8_t> code2(4 * K);
@@ -653,8 +712,28 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     TRY(alloc(ctx, &B.lv[0], n * r));
     TRY(alloc(ctx, &B.lv[1], n * r));
     TRY(alloc(ctx, &B.vtr, K * 4 * nf * 4 * r));
-    TRY(alloc(ctx, &B.dscal, 8 * sizeof(double)));
-    TRY(alloc(ctx, &B.slots, 3 * kDtSlots * sizeof(unsigned long long)));
+    TRY(alloc(ctx, &B.dscal, 8 * ni * sizeof(double)));
+    TRY(alloc(ctx, &B.slots, (size_t)3 * kDtSlots * ni * sizeof(unsigned long long)));
+    B.n_inst = ni;
+    if (ni > 1) {
+        // instance of every (internal) element and chunks of the time-step pass
+        std::vector<int64_t> cst;
+        std::vector<int32_t> cin;
+        for (int k = 0; k < ni; ++k)
+            for (int64_t e = off[k]; e < off[k + 1]; e += kDtChunk) {
+                cst.push_back(e);
+                cin.push_back(k);
+            }
+        cst.push_back(K);
+        B.nchunks = (int64_t)cin.size();
+        TRY(alloc(ctx, &B.inst, K * sizeof(int32_t)));
+        TRY(alloc(ctx, &B.cstart, cst.size() * sizeof(int64_t)));
+        TRY(alloc(ctx, &B.cinst, cin.size() * sizeof(int32_t)));
+        CK(hipMemcpyAsync(B.inst, inst_of.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        CK(hipMemcpyAsync(B.cstart, cst.data(), cst.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        CK(hipMemcpyAsync(B.cinst, cin.data(), cin.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+    }
     TRY(alloc(ctx, &B.flags, 4 * sizeof(int)));
     int64_t T = 0;
     (void)dispatch(ctx, [&](auto L, auto) {
@@ -670,10 +749,10 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     for (void *p : B.eps) CK(hipMemsetAsync(p, 0, K * r, ctx->stream));
     CK(hipMemsetAsync(B.count, 0, 4 * sizeof(int), ctx->stream));
     invalidate_eps(ctx);
-    CK(hipMemsetAsync(B.dscal, 0, 8 * sizeof(double), ctx->stream));
+    CK(hipMemsetAsync(B.dscal, 0, 8 * ni * sizeof(double), ctx->stream));
     CK(hipMemsetAsync(B.flags, 0, 4 * sizeof(int), ctx->stream));
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(3 * kDtSlots), 0, ctx->stream, B.slots,
-                       0x7FF0000000000000ull, 3 * kDtSlots);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)ni), dim3(3 * kDtSlots), 0, ctx->stream, B.slots,
+                       0x7FF0000000000000ull, 3 * kDtSlots * ni);
     CK(hipGetLastError());
     TRY(alloc(ctx, &ctx->perm, K * sizeof(int32_t)));
     CK(hipMemcpyAsync(ctx->perm, perm.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
@@ -701,9 +780,20 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         free_bufs(ctx);
         return fail(ctx, ESDG_EMESH, "Jacobian not positive at some node");
     }
+    ctx->inst_off = off;
     ctx->have_mesh = true;
     ctx->cur = 0;
     return ESDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const double *y,
+                     const int32_t *nbr_elem, const int8_t *nbr_side, const int8_t *flip, int mem)
+{
+    return upload_mesh_impl(ctx, N, K, x, y, nbr_elem, nbr_side, flip, mem, std::vector<int64_t>{0, K});
 }
 
 int esdg_set_bathymetry(esdg_ctx *ctx, const double *b, int mem)
@@ -738,7 +828,8 @@ int esdg_set_state(esdg_ctx *ctx, const double *h, const double *hu, const doubl
     TRY(upload_field(ctx, ctx->B.W[0][0], h, per, mem));
     TRY(upload_field(ctx, ctx->B.W[0][1], hu, per, mem));
     TRY(upload_field(ctx, ctx->B.W[0][2], hv, per, mem));
-    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal + 4, 0.0);
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.dscal + 4, 0.0,
+                       n_inst(ctx));
     CK(hipGetLastError());
     invalidate_eps(ctx);
     ctx->have_state = true;
@@ -803,45 +894,32 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
 {
     if (!check_ctx(ctx, true)) return ESDG_EINVAL;
     if (nsteps < 0) return fail(ctx, ESDG_EINVAL, "nsteps < 0");
-    const bool av = ctx->P.av_on != 0;
-    const bool adaptive = !(dt > 0.0);
-    const bool ssp = ctx->P.integrator == 1;
     const int retries = ctx->P.max_dt_retries;
-    const int nst = ssp ? 3 : 5;
-    const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
+    if (retries > 0 && n_inst(ctx) > 1) return fail(ctx, ESDG_EINVAL, "dt retries need a single instance");
     TRY(reset_flags(ctx));
     int status = ESDG_OK;
     for (int it = 0; it < nsteps; ++it) {
-        // W^n stays untouched in its buffer for the whole step: the stages
-        // alternate between the other two (the last one ends in o1), so a
-        // retry restarts from it without a copy
+        if (retries <= 0) {
+            TRY(launch_one_step(ctx, dt));
+            continue;
+        }
         const int base = ctx->cur;
-        const int o1 = (base + 1) % 3, o2 = (base + 2) % 3;
-        if (retries > 0) TRY(reset_flags(ctx));
-        TRY(launch_dt(ctx, base, adaptive ? 0.0 : dt, 1));
+        TRY(reset_flags(ctx));
         for (int attempt = 0;; ++attempt) {
-            int in = base;
-            for (int k = 0; k < nst; ++k) {
-                const int out = (k % 2 == 0) ? o1 : o2;
-                if (av) TRY(launch_viscous(ctx, in, out));
-                const bool last = k == nst - 1;
-                StageCall sc = ssp ? StageCall{kModeSsp, av, in, out, base, false, al[k], be[k], last}
-                                   : StageCall{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k], last,
-                                               !last};
-                TRY(launch_stage(ctx, sc));
-                ctx->eps_valid[out] = av;   // written by the stage epilogue
-                in = out;
+            if (attempt == 0) {
+                TRY(launch_one_step(ctx, dt));
+            } else {
+                // the halved step is already in place: replay the stages with it
+                ctx->cur = base;
+                TRY(launch_one_step(ctx, dt, false));
             }
-            ctx->cur = o1;
-            ctx->dtb_buf = o1;   // the last stage left its dt bounds
-            if (retries <= 0) break;
             int flags[4];
             TRY(read_flags(ctx, flags));
             if (!flags[0] || attempt >= retries) {
                 if (flags[0]) status = ESDG_ENEGMEAN;
                 break;
             }
-            // negative mean: restart from W^n with half the step
+            // negative mean: restart from W^n (untouched) with half the step
             ctx->cur = base;
             hipLaunchKernelGGL(scale_step_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal, 0.5,
                                ctx->B.dscal + 4);
@@ -871,7 +949,7 @@ int esdg_set_time(esdg_ctx *ctx, double t)
 {
     if (!ctx || !ctx->have_mesh) return ESDG_EINVAL;
     CK(hipSetDevice(ctx->device));
-    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal + 4, t);
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.dscal + 4, t, n_inst(ctx));
     CK(hipGetLastError());
     CK(hipStreamSynchronize(ctx->stream));
     return ESDG_OK;
@@ -970,6 +1048,272 @@ int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_n, double 
     ctx->ev_av.clear();
     ctx->ev_next = 0;
     return ESDG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Ensembles: instances of one degree share a context whose mesh is the
+// disjoint union of their meshes (one launch per stage for all of them),
+// with a time step and a time per instance.  Degrees run on their own
+// streams.
+// ------------------------------------------------------------------------
+struct esdg_ensemble {
+    struct Inst {
+        esdg_params P{};
+        int N = 0;
+        int64_t K = 0;
+        std::vector<double> x, y, b, h, hu, hv;
+        std::vector<int32_t> ne;
+        std::vector<int8_t> ns, fl;
+        int group = -1, local = -1;
+        int64_t off = 0;   // first element in the group's union
+    };
+    struct Group {
+        int N = 0;
+        esdg_ctx *ctx = nullptr;
+        hipStream_t stream = nullptr;
+        std::vector<int> members;
+        double *scratch = nullptr;   // [3][nodes] device copy of the union state (get_state)
+    };
+    int device = 0, prec = 64;
+    std::vector<Inst> inst;
+    std::vector<Group> groups;
+    bool built = false;
+    std::string err = "no error";
+};
+
+namespace {
+
+int efail(esdg_ensemble *en, int code, const char *msg)
+{
+    if (en) en->err = msg;
+    return code;
+}
+
+int efail_ctx(esdg_ensemble *en, esdg_ctx *c, int code)
+{
+    if (en) en->err = c ? c->err : std::string("context failure");
+    return code;
+}
+
+bool same_params(const esdg_params &a, const esdg_params &b)
+{
+    return a.g == b.g && a.h_tol == b.h_tol && a.eps0 == b.eps0 && a.sigma_min == b.sigma_min &&
+           a.sigma_max == b.sigma_max && a.cfl == b.cfl && a.cfl_visc == b.cfl_visc &&
+           a.surface_flux == b.surface_flux && a.av_on == b.av_on && a.limiter_on == b.limiter_on &&
+           a.integrator == b.integrator && a.max_dt_retries == b.max_dt_retries;
+}
+
+int ensemble_build(esdg_ensemble *en)
+{
+    if (en->built) return ESDG_OK;
+    if (en->inst.empty()) return efail(en, ESDG_EINVAL, "no instances");
+    if (hipSetDevice(en->device) != hipSuccess) return efail(en, ESDG_EHIP, "hipSetDevice failed");
+    for (size_t k = 0; k < en->inst.size(); ++k) {
+        auto &I = en->inst[k];
+        int g = -1;
+        for (size_t j = 0; j < en->groups.size(); ++j)
+            if (en->groups[j].N == I.N) g = (int)j;
+        if (g < 0) {
+            en->groups.push_back({});
+            g = (int)en->groups.size() - 1;
+            en->groups[g].N = I.N;
+        }
+        auto &G = en->groups[g];
+        if (!G.members.empty() && !same_params(en->inst[G.members[0]].P, I.P))
+            return efail(en, ESDG_EINVAL, "instances of one degree must share their parameters");
+        I.group = g;
+        I.local = (int)G.members.size();
+        G.members.push_back((int)k);
+    }
+    for (auto &G : en->groups) {
+        const int N = G.N;
+        const int64_t npn = (int64_t)(N + 1) * (N + 1);
+        std::vector<int64_t> off{0};
+        for (int m : G.members) {
+            en->inst[m].off = off.back();
+            off.push_back(off.back() + en->inst[m].K);
+        }
+        const int64_t K = off.back();
+        std::vector<double> x(K * npn), y(K * npn), b(K * npn), h(K * npn), hu(K * npn), hv(K * npn);
+        std::vector<int32_t> ne(4 * K);
+        std::vector<int8_t> ns(4 * K), fl(4 * K);
+        for (int m : G.members) {
+            const auto &I = en->inst[m];
+            const int64_t o = I.off;
+            std::copy(I.x.begin(), I.x.end(), x.begin() + o * npn);
+            std::copy(I.y.begin(), I.y.end(), y.begin() + o * npn);
+            std::copy(I.b.begin(), I.b.end(), b.begin() + o * npn);
+            std::copy(I.h.begin(), I.h.end(), h.begin() + o * npn);
+            std::copy(I.hu.begin(), I.hu.end(), hu.begin() + o * npn);
+            std::copy(I.hv.begin(), I.hv.end(), hv.begin() + o * npn);
+            for (int64_t f = 0; f < 4 * I.K; ++f) {
+                ne[4 * o + f] = (int32_t)(I.ne[f] + o);
+                ns[4 * o + f] = I.ns[f];
+                fl[4 * o + f] = I.fl[f];
+            }
+        }
+        int st = esdg_create(&G.ctx, en->device, en->prec);
+        if (st) return efail(en, st, "esdg_create failed");
+        if (hipStreamCreate(&G.stream) != hipSuccess) return efail(en, ESDG_EHIP, "hipStreamCreate failed");
+        esdg_ctx *c = G.ctx;
+        if ((st = esdg_set_stream(c, G.stream))) return efail_ctx(en, c, st);
+        if ((st = esdg_set_params(c, &en->inst[G.members[0]].P))) return efail_ctx(en, c, st);
+        if ((st = upload_mesh_impl(c, N, K, x.data(), y.data(), ne.data(), ns.data(), fl.data(), 0, off)))
+            return efail_ctx(en, c, st);
+        if ((st = esdg_set_bathymetry(c, b.data(), 0))) return efail_ctx(en, c, st);
+        if ((st = esdg_set_state(c, h.data(), hu.data(), hv.data(), 0))) return efail_ctx(en, c, st);
+        if (hipMalloc((void **)&G.scratch, 3 * K * npn * sizeof(double)) != hipSuccess)
+            return efail(en, ESDG_ENOMEM, "hipMalloc failed");
+    }
+    for (auto &I : en->inst) {   // the host copies are no longer needed
+        std::vector<double>().swap(I.x); std::vector<double>().swap(I.y); std::vector<double>().swap(I.b);
+        std::vector<double>().swap(I.h); std::vector<double>().swap(I.hu); std::vector<double>().swap(I.hv);
+        std::vector<int32_t>().swap(I.ne); std::vector<int8_t>().swap(I.ns); std::vector<int8_t>().swap(I.fl);
+    }
+    en->built = true;
+    return ESDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int esdg_ensemble_create(esdg_ensemble **out, int device, int precision)
+{
+    if (!out || (precision != 64 && precision != 32)) return ESDG_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ESDG_EINVAL;
+    auto *en = new esdg_ensemble;
+    en->device = device;
+    en->prec = precision;
+    *out = en;
+    return ESDG_OK;
+}
+
+int esdg_ensemble_destroy(esdg_ensemble *en)
+{
+    if (!en) return ESDG_EINVAL;
+    (void)hipSetDevice(en->device);
+    for (auto &G : en->groups) {
+        if (G.stream) (void)hipStreamSynchronize(G.stream);
+        if (G.ctx) esdg_destroy(G.ctx);
+        if (G.scratch) (void)hipFree(G.scratch);
+        if (G.stream) (void)hipStreamDestroy(G.stream);
+    }
+    delete en;
+    return ESDG_OK;
+}
+
+int esdg_ensemble_add(esdg_ensemble *en, const esdg_params *p, int N, int64_t K, const double *x, const double *y,
+                      const int32_t *nbr_elem, const int8_t *nbr_side, const int8_t *flip, const double *b,
+                      const double *h, const double *hu, const double *hv, int *id)
+{
+    if (!en) return ESDG_EINVAL;
+    if (en->built) return efail(en, ESDG_EINVAL, "instances must be added before the first step");
+    if (!p || !x || !y || !nbr_elem || !nbr_side || !flip || !b || !h || !hu || !hv)
+        return efail(en, ESDG_EINVAL, "null pointer");
+    if (N < 2 || N > kMaxN || K < 1) return efail(en, ESDG_EINVAL, "N or K out of range");
+    if (p->max_dt_retries > 0) return efail(en, ESDG_EINVAL, "dt retries need a single instance");
+    for (int64_t f = 0; f < 4 * K; ++f)
+        if (nbr_elem[f] < 0 || nbr_elem[f] >= K) return efail(en, ESDG_EMESH, "face map entry out of range");
+    esdg_ensemble::Inst I;
+    I.P = *p;
+    I.N = N;
+    I.K = K;
+    const int64_t n = K * (int64_t)(N + 1) * (N + 1);
+    I.x.assign(x, x + n); I.y.assign(y, y + n); I.b.assign(b, b + n);
+    I.h.assign(h, h + n); I.hu.assign(hu, hu + n); I.hv.assign(hv, hv + n);
+    I.ne.assign(nbr_elem, nbr_elem + 4 * K);
+    I.ns.assign(nbr_side, nbr_side + 4 * K);
+    I.fl.assign(flip, flip + 4 * K);
+    en->inst.push_back(std::move(I));
+    if (id) *id = (int)en->inst.size() - 1;
+    return ESDG_OK;
+}
+
+int esdg_ensemble_build(esdg_ensemble *en)
+{
+    if (!en) return ESDG_EINVAL;
+    return ensemble_build(en);
+}
+
+int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
+{
+    if (!en) return ESDG_EINVAL;
+    if (nsteps < 0) return efail(en, ESDG_EINVAL, "nsteps < 0");
+    TRY(ensemble_build(en));
+    if (hipSetDevice(en->device) != hipSuccess) return efail(en, ESDG_EHIP, "hipSetDevice failed");
+    for (auto &G : en->groups) {
+        const int st = reset_flags(G.ctx);
+        if (st) return efail_ctx(en, G.ctx, st);
+    }
+    // interleave the degrees step by step; each degree's launches are
+    // ordered on its own stream
+    for (int it = 0; it < nsteps; ++it)
+        for (auto &G : en->groups) {
+            const int st = launch_one_step(G.ctx, 0.0);
+            if (st) return efail_ctx(en, G.ctx, st);
+        }
+    int status = ESDG_OK;
+    for (auto &G : en->groups) {
+        int flags[4];
+        const int st = read_flags(G.ctx, flags);
+        if (st) return efail_ctx(en, G.ctx, st);
+        if (flags[2]) return efail(en, ESDG_EDTPOS, "no admissible time step");
+        if (flags[0]) status = ESDG_ENEGMEAN;
+    }
+    if (status) return efail(en, status, "negative element mean in the limiter");
+    return ESDG_OK;
+}
+
+int esdg_ensemble_size(const esdg_ensemble *en, int *n)
+{
+    if (!en || !n) return ESDG_EINVAL;
+    *n = (int)en->inst.size();
+    return ESDG_OK;
+}
+
+int esdg_ensemble_get_state(esdg_ensemble *en, int id, double *h, double *hu, double *hv, int mem)
+{
+    if (!en || !h || !hu || !hv) return ESDG_EINVAL;
+    if (id < 0 || id >= (int)en->inst.size()) return efail(en, ESDG_EINVAL, "no such instance");
+    TRY(ensemble_build(en));
+    if (hipSetDevice(en->device) != hipSuccess) return efail(en, ESDG_EHIP, "hipSetDevice failed");
+    const auto &I = en->inst[id];
+    auto &G = en->groups[I.group];
+    const int64_t npn = (int64_t)(G.N + 1) * (G.N + 1);
+    const int64_t n = nodes(G.ctx);
+    int st = esdg_get_state(G.ctx, G.scratch, G.scratch + n, G.scratch + 2 * n, 1);
+    if (st) return efail_ctx(en, G.ctx, st);
+    double *dst[3] = {h, hu, hv};
+    for (int c = 0; c < 3; ++c)
+        if (hipMemcpyAsync(dst[c], G.scratch + c * n + I.off * npn, I.K * npn * sizeof(double),
+                           mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, G.stream) != hipSuccess)
+            return efail(en, ESDG_EHIP, "hipMemcpyAsync failed");
+    if (hipStreamSynchronize(G.stream) != hipSuccess) return efail(en, ESDG_EHIP, "hipStreamSynchronize failed");
+    return ESDG_OK;
+}
+
+int esdg_ensemble_get_time(esdg_ensemble *en, int id, double *t)
+{
+    if (!en || !t) return ESDG_EINVAL;
+    if (id < 0 || id >= (int)en->inst.size()) return efail(en, ESDG_EINVAL, "no such instance");
+    TRY(ensemble_build(en));
+    const auto &I = en->inst[id];
+    auto &G = en->groups[I.group];
+    if (hipSetDevice(en->device) != hipSuccess ||
+        hipMemcpyAsync(t, G.ctx->B.dscal + 8 * I.local + 4, sizeof(double), hipMemcpyDeviceToHost, G.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(G.stream) != hipSuccess)
+        return efail(en, ESDG_EHIP, "time download failed");
+    return ESDG_OK;
+}
+
+const char *esdg_ensemble_last_error(const esdg_ensemble *en)
+{
+    return en ? en->err.c_str() : "null ensemble";
 }
 
 }  // extern "C"

@@ -73,6 +73,15 @@ def lib() -> C.CDLL:
             "esdg_profile_read": ([P, P, P, P, P], I),
             "esdg_last_error": ([P], C.c_char_p),
             "esdg_abi_version": ([], I),
+            "esdg_ensemble_create": ([P, I, I], I),
+            "esdg_ensemble_destroy": ([P], I),
+            "esdg_ensemble_add": ([P, P, I, I64, P, P, P, P, P, P, P, P, P, P], I),
+            "esdg_ensemble_build": ([P], I),
+            "esdg_ensemble_step": ([P, I], I),
+            "esdg_ensemble_size": ([P, P], I),
+            "esdg_ensemble_get_state": ([P, I, P, P, P, I], I),
+            "esdg_ensemble_get_time": ([P, I, P], I),
+            "esdg_ensemble_last_error": ([P], C.c_char_p),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -292,6 +301,80 @@ class Solver:
         sm, sn, am, an = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
         self._check(lib().esdg_profile_read(self._ctx, C.byref(sm), C.byref(sn), C.byref(am), C.byref(an)))
         return dict(stage_ms=sm.value, stage_launches=sn.value, av_ms=am.value, av_launches=an.value)
+
+
+class Ensemble:
+    """Independent instances (own mesh, degree, bathymetry, state, step and
+    time) advanced together: one launch per stage covers all instances of a
+    degree (``esdg_ensemble_*`` in include/esdg.h)."""
+
+    def __init__(self, device: int = 0, precision: int = 64):
+        self._h = C.c_void_p()
+        st = lib().esdg_ensemble_create(C.byref(self._h), int(device), int(precision))
+        if st != OK:
+            raise EsdgError(st, "esdg_ensemble_create failed")
+        self.device = device
+        self._shapes = []
+
+    def _check(self, st):
+        if st != OK:
+            raise EsdgError(st, lib().esdg_ensemble_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if self._h:
+            lib().esdg_ensemble_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, mesh, b, h, hu, hv, params: Params) -> int:
+        """Add one instance (host arrays); returns its id."""
+        N, K = mesh.N, mesh.x.shape[0]
+        n = K * (N + 1) ** 2
+        args = [_Arg(mesh.x, n), _Arg(mesh.y, n), _Arg(mesh.nbr_elem, 4 * K, np.int32),
+                _Arg(mesh.nbr_side, 4 * K, np.int8), _Arg(mesh.flip, 4 * K, np.int8),
+                _Arg(b, n), _Arg(h, n), _Arg(hu, n), _Arg(hv, n)]
+        if any(a.mem for a in args):
+            raise ValueError("ensemble instances are added from host arrays")
+        i = C.c_int(-1)
+        self._check(lib().esdg_ensemble_add(self._h, C.byref(params), int(N), int(K), *[a.ptr for a in args],
+                                            C.byref(i)))
+        self._shapes.append((N, K))
+        return i.value
+
+    def add_workload(self, w, **params) -> int:
+        P = default_params(w.mesh.N)
+        for k, v in {**w.params, **params}.items():
+            setattr(P, k, v)
+        return self.add(w.mesh, w.b, w.h, w.hu, w.hv, P)
+
+    def build(self):
+        self._check(lib().esdg_ensemble_build(self._h))
+
+    def step(self, nsteps: int):
+        self._check(lib().esdg_ensemble_step(self._h, int(nsteps)))
+
+    def __len__(self):
+        n = C.c_int(0)
+        self._check(lib().esdg_ensemble_size(self._h, C.byref(n)))
+        return n.value
+
+    def get_state(self, i: int):
+        N, K = self._shapes[i]
+        outs = [np.empty((K, (N + 1) ** 2)) for _ in range(3)]
+        self._check(lib().esdg_ensemble_get_state(self._h, int(i), *[o.ctypes.data_as(C.c_void_p) for o in outs],
+                                                  0))
+        return outs
+
+    def get_time(self, i: int) -> float:
+        t = C.c_double(0.0)
+        self._check(lib().esdg_ensemble_get_time(self._h, int(i), C.byref(t)))
+        return t.value
 
 
 def solver_for(workload, device: int = 0, precision: int = 64, **params) -> Solver:

@@ -1,0 +1,145 @@
+"""GPU: ensembles (instances of several degrees and mesh sizes advanced
+together) against single-instance solves of the same library (bitwise) and
+the CPU oracle; the dt-halving retry against the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_1804_02221_amd.inputs import dam_break, lake_bump, smooth_sweep
+
+COMMON = dict(av_on=1, limiter_on=1, eps0=0.05, sigma_min=-30.0, sigma_max=-1.0, integrator=0)
+
+
+@pytest.fixture(scope="module")
+def esdg():
+    from paper_1804_02221_amd import esdg as m
+    m.lib()
+    return m
+
+
+def workloads():
+    rng = np.random.default_rng(7)
+    ws = [dam_break(4, 3, seed=11, rotate_seed=1), smooth_sweep(5, 5, seed=12, rotate_seed=2),
+          dam_break(3, 7, seed=13), lake_bump(6, 3, seed=14), smooth_sweep(2, 5, seed=15),
+          smooth_sweep(3, 7, seed=16, rotate_seed=4), dam_break(5, 5, seed=17, rotate_seed=5)]
+    for w in ws[1::2]:
+        w.hu = w.hu + 0.05 * rng.standard_normal(w.hu.shape)
+    return ws
+
+
+def single(esdg, w, steps, **kw):
+    s = esdg.Solver(0, 64)
+    s.upload_mesh(w.mesh)
+    P = esdg.default_params(w.mesh.N)
+    for k, v in {**w.params, **kw}.items():
+        setattr(P, k, v)
+    s.set_params(P)
+    s.set_bathymetry(w.b)
+    s.set_state(w.h, w.hu, w.hv)
+    t, _ = s.step(steps, 0.0)
+    out = s.get_state()
+    s.close()
+    return out, t
+
+
+def test_ensemble_equals_single_instances(esdg):
+    ws = workloads()
+    ens = esdg.Ensemble(0, 64)
+    ids = [ens.add_workload(w, **COMMON) for w in ws]
+    assert len(ens) == len(ws)
+    ens.step(3)
+    for w, i in zip(ws, ids):
+        ref, t_ref = single(esdg, w, 3, **COMMON)
+        got = ens.get_state(i)
+        for c in range(3):
+            assert np.array_equal(got[c], ref[c]), (i, w.mesh.N, c, np.abs(got[c] - ref[c]).max())
+        assert ens.get_time(i) == t_ref
+    # different instances took different steps
+    assert len({ens.get_time(i) for i in ids}) > 2
+    ens.close()
+
+
+def test_ensemble_against_oracle(esdg, orc):
+    ws = workloads()[:3]
+    ens = esdg.Ensemble(0, 64)
+    ids = [ens.add_workload(w, **COMMON) for w in ws]
+    ens.step(2)
+    for w, i in zip(ws, ids):
+        P = esdg.default_params(w.mesh.N)
+        for k, v in {**w.params, **COMMON}.items():
+            setattr(P, k, v)
+        Po = orc.params(3, **P.as_dict())
+        h, hu, hv, t, st = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 2, 0.0)
+        assert st == 0
+        assert abs(ens.get_time(i) - t) <= 1e-12 * t
+        got = ens.get_state(i)
+        for g_, o_ in zip(got, (h, hu, hv)):
+            assert np.abs(g_ - o_).max() <= 1e-10 * max(1.0, np.abs(o_).max())
+    ens.close()
+
+
+def test_ensemble_argument_errors(esdg):
+    w = dam_break(3, 3, seed=1)
+    ens = esdg.Ensemble(0, 64)
+    with pytest.raises(esdg.EsdgError) as ei:
+        ens.add_workload(w, max_dt_retries=2)
+    assert ei.value.code == esdg.EINVAL
+    ens.add_workload(w, eps0=0.05)
+    ens.add_workload(dam_break(4, 3, seed=2), eps0=0.025)   # same degree, other parameters
+    with pytest.raises(esdg.EsdgError) as ei:
+        ens.step(1)
+    assert ei.value.code == esdg.EINVAL
+    ens.close()
+    ens = esdg.Ensemble(0, 64)
+    ens.add_workload(w)
+    ens.build()
+    with pytest.raises(esdg.EsdgError) as ei:
+        ens.add_workload(w)
+    assert ei.value.code == esdg.EINVAL
+    ens.close()
+
+
+def _solver(esdg, w, **kw):
+    s = esdg.Solver(0, 64)
+    s.upload_mesh(w.mesh)
+    P = esdg.default_params(w.mesh.N, **kw)
+    s.set_params(P)
+    s.set_bathymetry(w.b)
+    s.set_state(w.h, w.hu, w.hv)
+    return s, P
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_dt_retry_against_oracle(esdg, orc, integrator):
+    """A fixed step 16x the Lemma 2 bound makes an element mean negative; with
+    three retries the step is halved until it is admissible (2x for LSRK,
+    4x for SSPRK on this state).  The retried step must equal a direct step
+    of the accepted size (bitwise, on each side), and the two sides agree.
+    The accepted step is still far above the bound and limits elements whose
+    mean is close to zero, where theta = mean / (mean - min h) amplifies
+    rounding; the cross-check tolerance is 1e-9 of the field size."""
+    w = dam_break(6, 3, seed=4, rotate_seed=3)
+    kw = dict(av_on=1, limiter_on=1, eps0=0.05, integrator=integrator, max_dt_retries=3)
+    s, P = _solver(esdg, w, **kw)
+    Po = orc.params(3, **P.as_dict())
+    dpos = orc.dt(Po, w.mesh, w.b, w.h, w.hu, w.hv)[3]
+    t_gpu, st = s.step(1, 16 * dpos)
+    got = s.get_state()
+    s.close()
+    h, hu, hv, t_orc, sto = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 1, 16 * dpos)
+    assert st == 0 and sto == 0
+    assert t_gpu == t_orc and t_orc < 16 * dpos
+    # direct steps of the accepted size
+    s, _ = _solver(esdg, w, **{**kw, "max_dt_retries": 0})
+    s.step(1, t_gpu)
+    direct = s.get_state()
+    s.close()
+    Pd = orc.params(3, **{**P.as_dict(), "max_dt_retries": 0})
+    hd, hud, hvd, _, _ = orc.step(Pd, w.mesh, w.b, w.h, w.hu, w.hv, 1, t_orc)
+    for c in range(3):
+        assert np.array_equal(got[c], direct[c])
+    for a_, b_ in zip((h, hu, hv), (hd, hud, hvd)):
+        assert np.array_equal(a_, b_)
+    for g_, o_ in zip(got, (h, hu, hv)):
+        assert np.abs(g_ - o_).max() <= 1e-9 * max(1.0, np.abs(o_).max())
