@@ -89,6 +89,67 @@ def measured_traffic():
     return float(kv["traffic_bytes_per_launch"])
 
 
+ENSEMBLE_GRIDS = (32, 64, 128, 256)
+ENSEMBLE_DEGREES = (3, 5, 7)
+
+
+def ensemble_specs(n_inst: int, seed: int = 4):
+    """Batched-ensemble recipe: per instance a grid from {32,...,256}^2, a
+    degree from {3, 5, 7}, dam break or bump, its own bathymetry seed."""
+    rng = np.random.default_rng(seed)
+    return [(int(rng.choice(ENSEMBLE_GRIDS)), int(rng.choice(ENSEMBLE_DEGREES)), bool(rng.integers(2)), seed + i)
+            for i in range(n_inst)]
+
+
+def _member(spec):
+    from paper_1804_02221_amd.inputs import ensemble_member
+    return ensemble_member(*spec)
+
+
+def generate_ensemble(specs, workers: int):
+    """Generate the members on the host, in worker processes (before any GPU
+    use in this process)."""
+    if workers <= 1:
+        return [_member(sp) for sp in specs]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_member, specs))
+
+
+def ensemble_bench(esdg, dev, members, steps: int):
+    """Time `steps` adaptive steps of all members as one ensemble, then the
+    same steps as sequential single-instance solves; DOF-updates per second
+    per RK stage over all members."""
+    import torch
+    nodes = sum(w.mesh.K * (w.mesh.N + 1) ** 2 for w in members)
+    ens = esdg.Ensemble(dev, 64)
+    for w in members:
+        ens.add_workload(w)
+    ens.build()
+    ens.step(1)                       # warm-up (also builds the time-step bounds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(steps)
+    torch.cuda.synchronize()
+    t_ens = time.perf_counter() - t0
+    ens.close()
+    t_seq = 0.0
+    for w in members:
+        s = esdg.solver_for(w, dev)
+        s.step(1, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, 0.0)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        s.close()
+    return dict(instances=len(members), nodes=nodes, steps=steps,
+                value=nodes * 5 * steps / t_ens, ms_per_step=t_ens * 1e3 / steps,
+                sequential_value=nodes * 5 * steps / t_seq, sequential_ms_per_step=t_seq * 1e3 / steps,
+                speedup=t_seq / t_ens)
+
+
 def cpu_baseline(N: int, n_patch: int):
     import oracle
     from paper_1804_02221_amd.inputs import smooth_sweep
@@ -120,6 +181,9 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=10)
     ap.add_argument("--fp32-check", type=int, default=1,
                     help="also time the main N in FP32 (reported beside, not as value)")
+    ap.add_argument("--ensemble", type=int, default=64,
+                    help="instances of the batched-ensemble comparison (0: skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=5)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,6 +191,13 @@ def main():
               "(the halo-exchange design for several GPUs is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+
+    members = []
+    if args.ensemble > 0:
+        log(f"generating the {args.ensemble}-instance ensemble on the host")
+        t0 = time.perf_counter()
+        members = generate_ensemble(ensemble_specs(args.ensemble), min(16, os.cpu_count() or 1))
+        log(f"ensemble generated in {time.perf_counter() - t0:.1f} s")
 
     import torch
     from paper_1804_02221_amd import esdg
@@ -212,6 +283,14 @@ def main():
         r = run(args.N, precision=32, steps=args.sweep_steps, warmup=2)
         sweep.append({k: r[k] for k in keys})
 
+    ens = None
+    if members:
+        log("ensemble vs sequential solves")
+        ens = ensemble_bench(esdg, dev, members, args.ensemble_steps)
+        ens["recipe"] = ("grids {32,64,128,256}^2, N in {3,5,7}, dam break or Gaussian bump over a "
+                         "Gaussian-sum bed, AV + limiter, LSRK(5,4), adaptive dt per instance")
+        del members
+
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         log(f"CPU oracle baseline on a {args.cpu_patch}^2 patch")
@@ -256,6 +335,8 @@ def main():
     }
     if sweep:
         out["sweep"] = sweep
+    if ens:
+        out["ensemble"] = ens
     print(json.dumps(out), flush=True)
 
 

@@ -188,6 +188,21 @@ int esdg_profile(esdg_ctx *ctx, int enable);
 int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_launches,
                       double *av_ms, int64_t *av_launches);
 
+/*
+ * Autotuner of the stage kernel's tile (elements per workgroup): every
+ * degree has two compiled workgroup sizes, the default (one 64-lane wave
+ * where whole elements fill it -- N = 2, 3, 7 -- else 256 threads) and an
+ * alternative (256 resp. 128 threads).  esdg_autotune times reps launches
+ * of each on the context's mesh and current state (trial stages write only
+ * a scratch state buffer: the state, the LSRK register and the time are
+ * unchanged), keeps the faster for all later launches and returns the choice
+ * (0 default, 1 alternative) and the mean launch times in ms (either output
+ * may be NULL).  esdg_set_stage_variant sets the choice directly.  Results
+ * do not depend on the choice (same arithmetic per element).
+ */
+int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2]);
+int esdg_set_stage_variant(esdg_ctx *ctx, int variant);
+
 /* Last error message of ctx (never NULL). */
 const char *esdg_last_error(const esdg_ctx *ctx);
 
@@ -231,6 +246,10 @@ int esdg_ensemble_step(esdg_ensemble *en, int nsteps);
 int esdg_ensemble_size(const esdg_ensemble *en, int *n);
 int esdg_ensemble_get_state(esdg_ensemble *en, int id, double *h, double *hu, double *hv, int mem);
 int esdg_ensemble_get_time(esdg_ensemble *en, int id, double *t);
+/* The degrees of the ensemble (n of them, in N[0..n-1] when N != NULL) and
+ * the autotuner per degree (choices[g] for degree N[g], may be NULL). */
+int esdg_ensemble_degrees(const esdg_ensemble *en, int *n, int *N);
+int esdg_ensemble_autotune(esdg_ensemble *en, int reps, int *choices);
 const char *esdg_ensemble_last_error(const esdg_ensemble *en);
 
 #ifdef __cplusplus

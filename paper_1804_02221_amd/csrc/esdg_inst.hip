@@ -145,9 +145,20 @@ hipError_t Launch<N, R>::av_div(const Bufs &B, int in, int reset, const Phys<R> 
 }
 
 template <int N, typename R, int MODE>
-static void launch_stage(const StageArgs<R> &a, int64_t K, hipStream_t s, Ev ev)
+static void launch_stage(StageArgs<R> a, int64_t K, hipStream_t s, Ev ev)
 {
-    hipExtLaunchKernelGGL((stage_kernel<N, R, MODE>), tile_grid<N>(K), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0, a);
+    // both workgroup sizes of the stage kernel (the autotuner picks one)
+    if (a.variant == 0) {
+        using S = TileShape<N, Shape<N>::T>;
+        a.ntiles = (K + S::E - 1) / S::E;
+        const dim3 grid((unsigned)(((a.ntiles + kXcds - 1) / kXcds) * kXcds));
+        hipExtLaunchKernelGGL((stage_kernel<N, R, MODE, S::T>), grid, dim3(S::T), 0, s, ev.a, ev.b, 0, a);
+    } else {
+        using S = TileShape<N, AltThreads<N>::value>;
+        a.ntiles = (K + S::E - 1) / S::E;
+        const dim3 grid((unsigned)(((a.ntiles + kXcds - 1) / kXcds) * kXcds));
+        hipExtLaunchKernelGGL((stage_kernel<N, R, MODE, S::T>), grid, dim3(S::T), 0, s, ev.a, ev.b, 0, a);
+    }
 }
 
 template <int N, typename R>
@@ -188,7 +199,7 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.ca = (R)c.ca;
     a.cb = (R)c.cb;
     a.flags = B.flags;
-    a.ntiles = ntiles_of<N>(B.K);
+    a.variant = c.variant;
     if (c.mode == kModeRhs) launch_stage<N, R, kModeRhs>(a, B.K, s, ev);
     else if (c.mode == kModeLsrk) launch_stage<N, R, kModeLsrk>(a, B.K, s, ev);
     else launch_stage<N, R, kModeSsp>(a, B.K, s, ev);

@@ -40,13 +40,31 @@ struct Shape {
     static_assert(E * np <= T, "elements must fit the workgroup");
 };
 
+// The stage kernel comes in two workgroup sizes per degree, chosen at run
+// time (esdg_autotune): the default above and an alternative (256 threads
+// where the default is one wave, else 128).
+template <int N>
+struct AltThreads {
+    static constexpr int value = Shape<N>::T == 64 ? 256 : 128;
+};
+
+template <int N, int TT>
+struct TileShape {
+    static constexpr int nf = N + 1;
+    static constexpr int np = nf * nf;
+    static constexpr int T = TT;
+    static constexpr int E = (T / np) > 0 ? (T / np) : 1;
+    static constexpr int NFACE = E * 4 * nf;
+    static_assert(E * np <= T, "elements must fit the workgroup");
+};
+
 // Waves per SIMD the stage kernel is compiled for (its register budget) in
-// the FP64 update modes: five (four at N = 8); a few spilled bytes at N = 2,
-// 4, 6, 8 cost less than the occupancy they buy (measured).  No constraint
-// otherwise.
-template <int N, typename R, int MODE>
+// the FP64 update modes with the default shape: five (four at N = 8); a few
+// spilled bytes at N = 2, 4, 6, 8 cost less than the occupancy they buy
+// (measured).  No constraint otherwise.
+template <int N, typename R, int MODE, int TT = Shape<N>::T>
 struct StageWaves {
-    static constexpr int value = (sizeof(R) == 8 && MODE != 0) ? (N == 8 ? 4 : 5) : 1;
+    static constexpr int value = (sizeof(R) == 8 && MODE != 0 && TT == Shape<N>::T) ? (N == 8 ? 4 : 5) : 1;
 };
 
 // Workgroup barrier for exchanges through LDS only: orders LDS accesses
@@ -396,10 +414,10 @@ struct ElemReduce {
 // (the last reduced by min when MINLAST); only thread p == 0 of each element
 // receives the totals.  Two barriers; red: NQ*T reals of LDS.  The caller
 // synchronises before reusing red.
-template <int N, typename R, int NQ, bool MINLAST>
+template <int N, typename R, int NQ, bool MINLAST, int T = Shape<N>::T>
 __device__ __forceinline__ void elem_totals(R (&v)[NQ], R *red, int t, int el, int p, bool lane)
 {
-    constexpr int nf = N + 1, np = nf * nf, T = Shape<N>::T;
+    constexpr int nf = N + 1, np = nf * nf;
 #pragma unroll
     for (int c = 0; c < NQ; ++c) red[c * T + t] = v[c];
     lds_sync<T>();
@@ -437,20 +455,22 @@ __device__ __forceinline__ void elem_totals(R (&v)[NQ], R *red, int t, int el, i
 // Element totals as elem_totals (valid at least in thread p == 0): with lane
 // exchanges where an element is one whole wave (np = 64) or one 16-lane row
 // of a one-wave workgroup (np = 16), through LDS otherwise.
-template <int N, typename R, int NQ, bool MINLAST>
+template <int N, typename R, int NQ, bool MINLAST, int T = Shape<N>::T>
 __device__ __forceinline__ void elem_totals_any(R (&v)[NQ], R *red, int t, int el, int p, bool lane)
 {
     constexpr int np = (N + 1) * (N + 1);
-    if constexpr (Shape<N>::T == 64 && np == 64) {
+    if constexpr (np == 64 && T % 64 == 0) {
+        // one element per wave
 #pragma unroll
         for (int c = 0; c < NQ; ++c)
             v[c] = (MINLAST && c == NQ - 1) ? wave64_reduce<true>(v[c]) : wave64_reduce<false>(v[c]);
-    } else if constexpr (Shape<N>::T == 64 && np == 16) {
+    } else if constexpr (np == 16 && T % 64 == 0) {
+        // one element per 16-lane row
 #pragma unroll
         for (int c = 0; c < NQ; ++c)
             v[c] = (MINLAST && c == NQ - 1) ? row16_reduce<true>(v[c]) : row16_reduce<false>(v[c]);
     } else {
-        elem_totals<N, R, NQ, MINLAST>(v, red, t, el, p, lane);
+        elem_totals<N, R, NQ, MINLAST, T>(v, red, t, el, p, lane);
     }
 }
 
@@ -485,11 +505,11 @@ __device__ __forceinline__ R viscosity_from_totals(R all, R top, R allM, R topM,
 // sine ramp between sigma_min and sigma_max; zero for dry elements.  The
 // result is valid in thread p == 0 of each element.  red: 6*T reals of LDS
 // (the last T hold the intermediate V^{-1} h).  Three barriers.
-template <int N, typename R>
+template <int N, typename R, int T = Shape<N>::T>
 __device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phys<R> &P, int t, int el,
                                int p, bool lane, R h)
 {
-    constexpr int nf = N + 1, np = nf * nf, T = Shape<N>::T;
+    constexpr int nf = N + 1, np = nf * nf;
     const int i = p / nf, j = p - i * nf;
     R Tq = 0;
     if (lane) {
@@ -508,7 +528,7 @@ __device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phy
     // the energy of all modes is the top shell's plus that of the modes up to N-1
     R vals[4] = {mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0),
                  lane ? -h : R(3.0e38)};
-    elem_totals_any<N, R, 4, true>(vals, red, t, el, p, lane);
+    elem_totals_any<N, R, 4, true, T>(vals, red, t, el, p, lane);
     return viscosity_from_totals<R>(vals[0] + vals[1], vals[0], vals[1], vals[2], -vals[3], P);
 }
 
@@ -819,12 +839,13 @@ struct StageArgs {
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
     int *flags;                  // [0]: negative mean seen, [1]: limited elements
     int64_t ntiles;
+    int variant;                 // workgroup size: 0 the default, 1 the alternative (launch side)
 };
 
-template <int N, typename R, int MODE>
-__global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void stage_kernel(StageArgs<R> a)
+template <int N, typename R, int MODE, int TT>
+__global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage_kernel(StageArgs<R> a)
 {
-    using S = Shape<N>;
+    using S = TileShape<N, TT>;
     constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
     static_assert((T & (T - 1)) == 0, "workgroup size must be a power of two");
     using V2 = typename Vec2<R>::type;
@@ -1001,7 +1022,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
         if (P.limiter_on && block_any<T>(act && nh < R(0))) {
             const R wq = act ? J * a.tg->w[i] * a.tg->w[j] : R(0);
             R vals[5] = {wq, wq * nh, wq * nhu, wq * nhv, act ? nh : R(3.0e38)};
-            elem_totals_any<N, R, 5, true>(vals, s_st, t, el, p, lane);
+            elem_totals_any<N, R, 5, true, T>(vals, s_st, t, el, p, lane);
             if (lane && p == 0) {
                 const R area = vals[0];
                 const R mh = vals[1] / area, mhu = vals[2] / area, mhv = vals[3] / area, mn = vals[4];
@@ -1040,7 +1061,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
             // viscosity of the new state for the next stage (appendix A)
             s_st[8 * T + t] = nh;
             lds_sync<T>();
-            en = element_viscosity<N, R>(s_st + 8 * T, s_st, *a.tg, P, t, el, p, lane, nh);
+            en = element_viscosity<N, R, T>(s_st + 8 * T, s_st, *a.tg, P, t, el, p, lane, nh);
             if (act && p == 0) {
                 a.eps_out[e] = en;
                 if (en > R(0)) a.list_out[atomicAdd(a.count_out, 1)] = (int32_t)e;
@@ -1050,7 +1071,7 @@ __global__ __launch_bounds__(Shape<N>::T, (StageWaves<N, R, MODE>::value)) void 
             // CFL and viscous bounds of the new state for the next step
             R vals[1] = {act ? cfl_bound<N, R>(nh, nhu, nhv, Ax, Cx, Ae, Ce, J, P) : R(3.0e38)};
             lds_sync<T>();   // scratch free
-            elem_totals_any<N, R, 1, true>(vals, s_st, t, el, p, lane);
+            elem_totals_any<N, R, 1, true, T>(vals, s_st, t, el, p, lane);
             if (act && p == 0) {
                 a.dtc_out[e] = vals[0];
                 if (a.dtv_out) a.dtv_out[e] = en > R(0) ? visc_bound<R>(en, a.gmax[e], P) : R(3.0e38);

@@ -55,6 +55,7 @@ struct StageCall {
     double ca, cb;     // stage coefficients
     bool dt_next;      // last stage of a step: leave the output's dt bounds in dtc/dtv
     bool store_du;     // LSRK: write the register dU (not needed after the last stage)
+    int variant;       // stage-kernel workgroup size: 0 default, 1 alternative
 };
 
 template <int N, typename R>

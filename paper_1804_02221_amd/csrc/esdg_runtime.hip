@@ -144,6 +144,7 @@ struct esdg_ctx {
     int cur = 0;
     bool eps_valid[3] = {false, false, false};   // viscosity/list of state buffer b are current
     int dtb_buf = -1;   // state buffer whose per-element dt bounds are in dtc/dtv (-1: none)
+    int stage_variant = 0;   // stage-kernel workgroup size (esdg_autotune)
     // instances (ensembles): element ranges [inst_off[k], inst_off[k+1]) in
     // the caller's order and, since the locality order permutes inside each
     // range, in the internal order too
@@ -334,8 +335,9 @@ int launch_viscous(esdg_ctx *ctx, int buf, int reset)
     });
 }
 
-int launch_stage(esdg_ctx *ctx, const StageCall &sc)
+int launch_stage(esdg_ctx *ctx, StageCall sc)
 {
+    sc.variant = ctx->stage_variant;
     return timed(ctx, ctx->ev_stage, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
@@ -1017,6 +1019,60 @@ int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, dou
     return ESDG_OK;
 }
 
+int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2])
+{
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    if (reps < 1 || reps > 1000) return fail(ctx, ESDG_EINVAL, "reps outside [1, 1000]");
+    const bool av = ctx->P.av_on != 0;
+    const int base = ctx->cur, o1 = (base + 1) % 3;
+    TRY(reset_flags(ctx));
+    if (av) TRY(launch_viscous(ctx, base, -1));
+    // trial stages: SSP form W^n -> o1 (W^n and dU untouched), each variant
+    // timed over reps launches, twice, alternating
+    hipEvent_t e0 = next_event(ctx), e1 = next_event(ctx);
+    if (!e0 || !e1) return fail(ctx, ESDG_EHIP, "hipEventCreate failed");
+    double best[2] = {1e300, 1e300};
+    const int keep = ctx->stage_variant;
+    for (int round = 0; round < 2; ++round)
+        for (int v = 0; v < 2; ++v) {
+            ctx->stage_variant = v;
+            CK(hipEventRecord(e0, ctx->stream));
+            for (int r = 0; r < reps; ++r) {
+                // the epilogue appends to o1's viscous-element list: empty it first
+                hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.count + o1, 0, 1);
+                StageCall sc{kModeSsp, av, base, o1, base, false, 0.0, 1.0, false, false, v};
+                const int st = launch_stage(ctx, sc);
+                if (st) {
+                    ctx->stage_variant = keep;
+                    return st;
+                }
+            }
+            CK(hipEventRecord(e1, ctx->stream));
+            CK(hipEventSynchronize(e1));
+            float t = 0;
+            CK(hipEventElapsedTime(&t, e0, e1));
+            best[v] = std::min(best[v], (double)t / reps);
+        }
+    ctx->ev_next = 0;
+    ctx->stage_variant = best[1] < best[0] ? 1 : 0;
+    ctx->eps_valid[o1] = false;
+    if (ctx->dtb_buf == o1) ctx->dtb_buf = -1;
+    TRY(reset_flags(ctx));
+    if (choice) *choice = ctx->stage_variant;
+    if (ms) {
+        ms[0] = best[0];
+        ms[1] = best[1];
+    }
+    return ESDG_OK;
+}
+
+int esdg_set_stage_variant(esdg_ctx *ctx, int variant)
+{
+    if (!ctx || (variant != 0 && variant != 1)) return ctx ? fail(ctx, ESDG_EINVAL, "variant must be 0 or 1") : ESDG_EINVAL;
+    ctx->stage_variant = variant;
+    return ESDG_OK;
+}
+
 int esdg_profile(esdg_ctx *ctx, int enable)
 {
     if (!ctx) return ESDG_EINVAL;
@@ -1308,6 +1364,28 @@ int esdg_ensemble_get_time(esdg_ensemble *en, int id, double *t)
             hipSuccess ||
         hipStreamSynchronize(G.stream) != hipSuccess)
         return efail(en, ESDG_EHIP, "time download failed");
+    return ESDG_OK;
+}
+
+int esdg_ensemble_autotune(esdg_ensemble *en, int reps, int *choices)
+{
+    if (!en) return ESDG_EINVAL;
+    TRY(ensemble_build(en));
+    for (size_t g = 0; g < en->groups.size(); ++g) {
+        int c = 0;
+        const int st = esdg_autotune(en->groups[g].ctx, reps, &c, nullptr);
+        if (st) return efail_ctx(en, en->groups[g].ctx, st);
+        if (choices) choices[g] = c;
+    }
+    return ESDG_OK;
+}
+
+int esdg_ensemble_degrees(const esdg_ensemble *en, int *n, int *N)
+{
+    if (!en || !n) return ESDG_EINVAL;
+    *n = (int)en->groups.size();
+    if (N)
+        for (size_t g = 0; g < en->groups.size(); ++g) N[g] = en->groups[g].N;
     return ESDG_OK;
 }
 

@@ -82,6 +82,10 @@ def lib() -> C.CDLL:
             "esdg_ensemble_get_state": ([P, I, P, P, P, I], I),
             "esdg_ensemble_get_time": ([P, I, P], I),
             "esdg_ensemble_last_error": ([P], C.c_char_p),
+            "esdg_ensemble_degrees": ([P, P, P], I),
+            "esdg_ensemble_autotune": ([P, I, P], I),
+            "esdg_autotune": ([P, I, P, P], I),
+            "esdg_set_stage_variant": ([P, I], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -294,6 +298,16 @@ class Solver:
         self._check(lib().esdg_get_geometry(self._ctx, *[p.ptr for p in ps], 0))
         return dict(zip(("xxi", "xeta", "yxi", "yeta", "J"), self._shape(outs)))
 
+    def autotune(self, reps: int = 5):
+        """Pick the faster stage-kernel workgroup size; returns (choice, [ms0, ms1])."""
+        c = C.c_int(0)
+        ms = np.zeros(2)
+        self._check(lib().esdg_autotune(self._ctx, int(reps), C.byref(c), ms.ctypes.data_as(C.c_void_p)))
+        return c.value, ms
+
+    def set_stage_variant(self, variant: int):
+        self._check(lib().esdg_set_stage_variant(self._ctx, int(variant)))
+
     def profile(self, enable: bool = True):
         self._check(lib().esdg_profile(self._ctx, int(bool(enable))))
 
@@ -375,6 +389,23 @@ class Ensemble:
         t = C.c_double(0.0)
         self._check(lib().esdg_ensemble_get_time(self._h, int(i), C.byref(t)))
         return t.value
+
+    def degrees(self):
+        n = C.c_int(0)
+        Ns = (C.c_int * 16)()
+        self._check(lib().esdg_ensemble_degrees(self._h, C.byref(n), Ns))
+        return [Ns[g] for g in range(n.value)]
+
+    def autotune(self, reps: int = 5):
+        """Autotune every degree's stage kernel; returns {N: choice}."""
+        degs = self.degrees() if self._built_or_build() else []
+        ch = (C.c_int * 16)()
+        self._check(lib().esdg_ensemble_autotune(self._h, int(reps), ch))
+        return {N: ch[g] for g, N in enumerate(degs)}
+
+    def _built_or_build(self):
+        self.build()
+        return True
 
 
 def solver_for(workload, device: int = 0, precision: int = 64, **params) -> Solver:

@@ -311,6 +311,34 @@ def smooth_sweep(n: int = 512, N: int = 7, seed: int = 3, rotate_seed: int | Non
                     dict(g=9.81, surface_flux=0, av_on=1, limiter_on=1, eps0=0.025, cfl=0.5))
 
 
+def ensemble_member(n: int, N: int, dam: bool, seed: int) -> Workload:
+    """One instance of the batched-ensemble recipe: n x n curvilinear
+    periodic elements of [0,10]^2 (the sin map of dam_break), bathymetry of 8
+    periodised Gaussians (amplitude U(0,0.3), width U(0.5,2)); initial data
+    the dam break (h = 1 for undeformed centroid X < 5, else dry) or, when
+    not dam, a wet Gaussian surface bump H = 1.2 + 0.1 exp(-|x - x0|^2) over
+    the bed (h = max(H - b, 0)); at rest.  AV and limiter on; eps0 = 0.05 at
+    N = 3, 0.025 otherwise."""
+    if dam:
+        w = dam_break(n, N, seed=seed)
+    else:
+        mesh = make_periodic_mesh(N, n, n, 10.0, 10.0, amp=0.1)
+        rng = np.random.default_rng(seed)
+        amps = rng.uniform(0.0, 0.3, 8)
+        widths = rng.uniform(0.5, 2.0, 8)
+        centers = rng.uniform(0.0, 10.0, (8, 2))
+        b = periodic_gaussians(mesh, [tuple(cc) for cc in centers], amps, widths)
+        x0 = tuple(rng.uniform(2.0, 8.0, 2))
+        H = 1.2 + periodic_gaussians(mesh, [x0], [0.1], [1.0])
+        h = np.maximum(H - b, 0.0)
+        z = np.zeros_like(h)
+        w = Workload("bump", mesh, _c(b), _c(h), _c(z), _c(z.copy()),
+                     dict(g=9.81, surface_flux=0, av_on=1, limiter_on=1, eps0=0.025, cfl=0.5))
+    w.name = f"{'dam' if dam else 'bump'}_{n}x{n}_N{N}"
+    w.params = dict(w.params, eps0=0.05 if N == 3 else 0.025)
+    return w
+
+
 def random_states(rng: np.random.Generator, n: int, dry_fraction: float = 0.0,
                   hmax: float = 2.0, umax: float = 1.0):
     """Independent random point states (h, hu, hv, b) for flux-level tests."""
