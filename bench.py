@@ -128,6 +128,7 @@ def ensemble_bench(esdg, dev, members, steps: int):
         ens.add_workload(w)
     ens.build()
     ens.step(1)                       # warm-up (also builds the time-step bounds)
+    tuned = ens.autotune(5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ens.step(steps)
@@ -138,6 +139,7 @@ def ensemble_bench(esdg, dev, members, steps: int):
     for w in members:
         s = esdg.solver_for(w, dev)
         s.step(1, 0.0)
+        s.autotune(5)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(steps, 0.0)
@@ -147,7 +149,7 @@ def ensemble_bench(esdg, dev, members, steps: int):
     return dict(instances=len(members), nodes=nodes, steps=steps,
                 value=nodes * 5 * steps / t_ens, ms_per_step=t_ens * 1e3 / steps,
                 sequential_value=nodes * 5 * steps / t_seq, sequential_ms_per_step=t_seq * 1e3 / steps,
-                speedup=t_seq / t_ens)
+                speedup=t_seq / t_ens, stage_variant={str(k): v for k, v in tuned.items()})
 
 
 def cpu_baseline(N: int, n_patch: int):
@@ -184,6 +186,8 @@ def main():
     ap.add_argument("--ensemble", type=int, default=64,
                     help="instances of the batched-ensemble comparison (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=5)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick the stage-kernel workgroup size per run with the library's autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -220,6 +224,9 @@ def main():
         nodes = K * (N + 1) ** 2
         log(f"uploaded K={K} nodes={nodes}; warmup {warmup} steps")
         s.step(warmup, 0.0)
+        choice, tune_ms = s.autotune(5) if args.autotune else (0, None)
+        if args.autotune:
+            log(f"autotune: stage workgroup variant {choice} (ms {tune_ms[0]:.3f} / {tune_ms[1]:.3f})")
         torch.cuda.synchronize()
         s.profile(True)
         s.profile_read()
@@ -241,6 +248,7 @@ def main():
         stage_mean_ms = prof["stage_ms"] / max(stage_launch, 1)
         achieved = stage_total / (prof["stage_ms"] * 1e-3) / 1e9
         res = dict(N=N, precision=precision, K=K, nodes=nodes, elapsed=el, t_sim=t_sim, n_visc=n_visc,
+                   stage_variant=choice,
                    value=nodes * 5 * steps / el,
                    ms_per_step=el * 1e3 / steps,
                    stage_mean_ms=stage_mean_ms, stage_launches=stage_launch,
@@ -275,7 +283,8 @@ def main():
     log("memcopy probe")
     mc = memcopy_probe(main_res["stage_bytes_per_launch"])
     sweep = []
-    keys = ("N", "precision", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs", "roofline_frac")
+    keys = ("N", "precision", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs", "roofline_frac",
+            "stage_variant")
     for tok in [t for t in args.sweep.split(",") if t.strip()]:
         r = run(int(tok), steps=args.sweep_steps, warmup=2)
         sweep.append({k: r[k] for k in keys})
@@ -318,6 +327,7 @@ def main():
                          f"elements of [0,10]^2, N={args.N}, {'AV + ' if not args.no_av else ''}"
                          f"limiter, ES flux, LSRK(5,4), adaptive dt"),
             "N": args.N, "elements": main_res["K"], "nodes": main_res["nodes"],
+            "stage_variant": main_res["stage_variant"],
             "stages_per_step": 5, "parallelism": "single GPU",
         },
         "roofline": {
