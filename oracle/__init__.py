@@ -73,6 +73,9 @@ def lib():
         L.orc_step.argtypes = [P, P, P, P, P, P, I, C.c_double, P, P]
         L.orc_diagnostics.argtypes = [P, P, P, P, P, P, P]
         L.orc_lsrk_coefficients.argtypes = [P, P]
+        L.orc_rhs_vjp.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_gauge_adjoint.argtypes = [P, P, P, P, P, P, I, C.c_double, I, P, P, P, P, P, P,
+                                        P, P, P, P]
         _lib = L
     return _lib
 
@@ -230,3 +233,39 @@ def lsrk_coefficients():
     a, b = np.zeros(5), np.zeros(5)
     lib().orc_lsrk_coefficients(_p(a), _p(b))
     return a, b
+
+
+def rhs_vjp(P: Params, mesh, b, h, hu, hv, lh, lhu, lhv):
+    """Reverse mode of the inviscid right-hand side at (W, b): returns
+    (dR/dW)^T lam as (gh, ghu, ghv) and (dR/db)^T lam as gb."""
+    M = _MeshRef(mesh)
+    args = [_f64(a) for a in (b, h, hu, hv, lh, lhu, lhv)]
+    out = [np.zeros_like(args[1]) for _ in range(4)]
+    _check(lib().orc_rhs_vjp(C.byref(P), C.byref(M.c), *[_p(a) for a in args],
+                             *[_p(o) for o in out]), "rhs_vjp")
+    return tuple(out)
+
+
+def gauge_adjoint(P: Params, mesh, b, h0, hu0, hv0, nsteps: int, dt: float, gelem, gxi, geta,
+                  target, gradient: bool = True) -> dict:
+    """Gauge-misfit loss L = 1/2 sum_n sum_g (H_g(t_n) - target[n-1, g])^2 dt over
+    nsteps fixed LSRK(5,4) steps, the surface H = h + b at the gauges (element
+    gelem[g], reference point (gxi[g], geta[g])).  Returns loss, H [nsteps, ng]
+    and, with gradient, gb = dL/db (initial state fixed) and gW0 = dL/dW(0)."""
+    M = _MeshRef(mesh)
+    b, h0, hu0, hv0 = _f64(b), _f64(h0), _f64(hu0), _f64(hv0)
+    gelem = np.ascontiguousarray(gelem, dtype=np.int32)
+    gxi, geta = _f64(gxi), _f64(geta)
+    ng = gelem.shape[0]
+    target = _f64(target).reshape(nsteps, ng)
+    loss = np.zeros(1)
+    H = np.zeros((nsteps, ng))
+    out = [np.zeros_like(h0) for _ in range(4)] if gradient else [None] * 4
+    st = lib().orc_gauge_adjoint(C.byref(P), C.byref(M.c), _p(b), _p(h0), _p(hu0), _p(hv0),
+                                 int(nsteps), float(dt), int(ng), _p(gelem), _p(gxi), _p(geta),
+                                 _p(target), _p(loss), _p(H), *[_p(o) for o in out])
+    _check(st, "gauge_adjoint")
+    r = dict(loss=float(loss[0]), H=H)
+    if gradient:
+        r.update(gb=out[0], gh0=out[1], ghu0=out[2], ghv0=out[3])
+    return r

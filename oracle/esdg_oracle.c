@@ -1060,3 +1060,397 @@ int orc_diagnostics(const orc_params *P, const orc_mesh *m, const double *b, con
     geom_free(&G);
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint: reverse mode of the inviscid right-hand side and of     */
+/* LSRK(5,4) steps, for a gauge-misfit loss in the bathymetry.               */
+/*                                                                            */
+/* Scope of the adjoint: artificial viscosity off (the viscosity is frozen   */
+/* at zero) and a limiter that never acts (all elements wet, so theta = 1    */
+/* and no velocity is cut off).  The derivative of |x| is sign(x) with       */
+/* sign(0) = 0; velocities below the dry cut-off are constants.              */
+/* ------------------------------------------------------------------------ */
+
+/* Forward-mode dual numbers with 8 tangent slots.  The local Jacobians of
+ * the two-point volume flux (6 inputs) and of the interface flux (8 inputs:
+ * own h, hu, hv, b, neighbour h, hu, hv, b) are obtained by evaluating the
+ * flux formulas on duals, so the chain rule is applied mechanically. */
+#define ORC_ND 8
+typedef struct { double v, d[ORC_ND]; } dn;
+
+static dn dn_c(double v) { dn r; r.v = v; for (int k = 0; k < ORC_ND; ++k) r.d[k] = 0.0; return r; }
+static dn dn_var(double v, int k) { dn r = dn_c(v); r.d[k] = 1.0; return r; }
+static dn dn_add(dn a, dn b) { dn r; r.v = a.v + b.v; for (int k = 0; k < ORC_ND; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+static dn dn_sub(dn a, dn b) { dn r; r.v = a.v - b.v; for (int k = 0; k < ORC_ND; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+static dn dn_scl(double s, dn a) { dn r; r.v = s * a.v; for (int k = 0; k < ORC_ND; ++k) r.d[k] = s * a.d[k]; return r; }
+static dn dn_mul(dn a, dn b)
+{
+    dn r; r.v = a.v * b.v;
+    for (int k = 0; k < ORC_ND; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+static dn dn_div(dn a, dn b)
+{
+    dn r; r.v = a.v / b.v;
+    for (int k = 0; k < ORC_ND; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+}
+static dn dn_sqrt(dn a)   /* a.v > 0 where the derivative is used */
+{
+    dn r; r.v = sqrt(a.v);
+    for (int k = 0; k < ORC_ND; ++k) r.d[k] = r.v > 0.0 ? 0.5 * a.d[k] / r.v : 0.0;
+    return r;
+}
+static dn dn_abs(dn a)
+{
+    double s = a.v > 0.0 ? 1.0 : (a.v < 0.0 ? -1.0 : 0.0);
+    return dn_scl(s, a);
+}
+
+/* velocity with the dry cut-off (constant zero where h <= h_tol) */
+static dn dn_velocity(dn hq, dn h, double h_tol)
+{
+    return (h.v > h_tol) ? dn_div(hq, h) : dn_c(0.0);
+}
+
+/* Two-point volume fluxes F#, G# (eq. volumeFluxes) on duals. */
+static void volume_flux_dn(double g, double h_tol, const dn *wa, const dn *wb, dn *Fs, dn *Gs)
+{
+    dn ua = dn_velocity(wa[1], wa[0], h_tol), ub = dn_velocity(wb[1], wb[0], h_tol);
+    dn va = dn_velocity(wa[2], wa[0], h_tol), vb = dn_velocity(wb[2], wb[0], h_tol);
+    dn avg_h = dn_scl(0.5, dn_add(wa[0], wb[0]));
+    dn avg_h2 = dn_scl(0.5, dn_add(dn_mul(wa[0], wa[0]), dn_mul(wb[0], wb[0])));
+    dn avg_hu = dn_scl(0.5, dn_add(wa[1], wb[1]));
+    dn avg_hv = dn_scl(0.5, dn_add(wa[2], wb[2]));
+    dn avg_u = dn_scl(0.5, dn_add(ua, ub));
+    dn avg_v = dn_scl(0.5, dn_add(va, vb));
+    dn p = dn_sub(dn_scl(g, dn_mul(avg_h, avg_h)), dn_scl(0.5 * g, avg_h2));
+    Fs[0] = avg_hu;
+    Fs[1] = dn_add(dn_mul(avg_hu, avg_u), p);
+    Fs[2] = dn_mul(avg_hu, avg_v);
+    Gs[0] = avg_hv;
+    Gs[1] = dn_mul(avg_hv, avg_u);
+    Gs[2] = dn_add(dn_mul(avg_hv, avg_v), p);
+}
+
+/* Interface flux along the unit normal (appendix B) on duals: the same
+ * rotated EC flux and, for the ES flux, the dissipation R|Lambda|R^T [[q~]]
+ * as a matrix product. */
+static void surface_flux_dn(const orc_params *P, const dn *wm, dn bm, const dn *wp, dn bp,
+                            double nx, double ny, dn *F)
+{
+    double g = P->g;
+    dn hm = wm[0], hp = wp[0];
+    dn um = dn_velocity(wm[1], hm, P->h_tol), vm = dn_velocity(wm[2], hm, P->h_tol);
+    dn up = dn_velocity(wp[1], hp, P->h_tol), vp = dn_velocity(wp[2], hp, P->h_tol);
+    dn utm = dn_add(dn_scl(nx, um), dn_scl(ny, vm)), vtm = dn_add(dn_scl(-ny, um), dn_scl(nx, vm));
+    dn utp = dn_add(dn_scl(nx, up), dn_scl(ny, vp)), vtp = dn_add(dn_scl(-ny, up), dn_scl(nx, vp));
+    dn cm = hm.v > 0.0 ? dn_sqrt(dn_scl(g, hm)) : dn_c(0.0);
+    dn cp = hp.v > 0.0 ? dn_sqrt(dn_scl(g, hp)) : dn_c(0.0);
+    dn ah = dn_scl(0.5, dn_add(hm, hp)), au = dn_scl(0.5, dn_add(utm, utp));
+    dn av = dn_scl(0.5, dn_add(vtm, vtp));
+    dn ah2 = dn_scl(0.5, dn_add(dn_mul(hm, hm), dn_mul(hp, hp))), ac = dn_scl(0.5, dn_add(cm, cp));
+    dn Fr[3];
+    Fr[0] = dn_mul(ah, au);
+    Fr[1] = dn_add(dn_mul(ah, dn_mul(au, au)), dn_scl(0.5 * g, ah2));
+    Fr[2] = dn_mul(ah, dn_mul(au, av));
+    if (P->surface_flux == 0) {
+        dn qm0 = dn_sub(dn_scl(g, dn_add(hm, bm)),
+                        dn_scl(0.5, dn_add(dn_mul(utm, utm), dn_mul(vtm, vtm))));
+        dn qp0 = dn_sub(dn_scl(g, dn_add(hp, bp)),
+                        dn_scl(0.5, dn_add(dn_mul(utp, utp), dn_mul(vtp, vtp))));
+        dn dq[3] = {dn_sub(qp0, qm0), dn_sub(utp, utm), dn_sub(vtp, vtm)};
+        dn R[3][3] = {{dn_c(1.0), dn_c(0.0), dn_c(1.0)},
+                      {dn_add(au, ac), dn_c(0.0), dn_sub(au, ac)},
+                      {av, dn_c(1.0), av}};
+        dn Lam[3] = {dn_scl(1.0 / (2.0 * g), dn_abs(dn_add(au, ac))),
+                     dn_abs(dn_mul(ah, au)),
+                     dn_scl(1.0 / (2.0 * g), dn_abs(dn_sub(au, ac)))};
+        dn RTdq[3];
+        for (int a = 0; a < 3; ++a) {
+            RTdq[a] = dn_c(0.0);
+            for (int c = 0; c < 3; ++c) RTdq[a] = dn_add(RTdq[a], dn_mul(R[c][a], dq[c]));
+            RTdq[a] = dn_mul(Lam[a], RTdq[a]);
+        }
+        for (int a = 0; a < 3; ++a) {
+            dn dis = dn_c(0.0);
+            for (int c = 0; c < 3; ++c) dis = dn_add(dis, dn_mul(R[a][c], RTdq[c]));
+            Fr[a] = dn_sub(Fr[a], dn_scl(0.5, dis));
+        }
+    }
+    F[0] = Fr[0];
+    F[1] = dn_sub(dn_scl(nx, Fr[1]), dn_scl(ny, Fr[2]));
+    F[2] = dn_add(dn_scl(ny, Fr[1]), dn_scl(nx, Fr[2]));
+}
+
+/* Adds scale * (dR/dW)^T lam to gw and scale * (dR/db)^T lam to gb, R the
+ * inviscid right-hand side of rhs_impl.  Every term of the forward
+ * computation is visited in the forward's order and its local partial
+ * derivatives are scattered to the nodes it reads (reverse mode). */
+static int rhs_vjp_acc(const orc_params *P, const orc_ops *op, const orc_mesh *m,
+                       const orc_geom *G, const double *b, const double *h, const double *hu,
+                       const double *hv, const double *const lam[3], double scale,
+                       double *const gw[3], double *gb)
+{
+    if (P->av_on) return ORC_EINVAL;
+    const int N = op->N, n1 = N + 1, np = n1 * n1;
+    const double g = P->g, htol = P->h_tol;
+    for (int64_t e = 0; e < m->K; ++e) {
+        const int64_t o = e * np;
+        /* R = -(1/J)(L - S): dPhi/dL_p = mu_p, dPhi/dS_p = -mu_p for
+         * Phi = scale * sum_p lam_p . R_p */
+        double mu[3][(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+        for (int p = 0; p < np; ++p)
+            for (int c = 0; c < 3; ++c) mu[c][p] = -scale * lam[c][o + p] / G->J[o + p];
+        /* volume: L[c][p] += D~_im (F#[c] {y_eta} - G#[c] {x_eta}) along xi and
+         * D~_jm (-F#[c] {y_xi} + G#[c] {x_xi}) along eta */
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                int p = i * n1 + j;
+                for (int dir = 0; dir < 2; ++dir)
+                    for (int mm = 0; mm <= N; ++mm) {
+                        int pm = dir == 0 ? mm * n1 + j : i * n1 + mm;
+                        dn wa[3] = {dn_var(h[o + p], 0), dn_var(hu[o + p], 1), dn_var(hv[o + p], 2)};
+                        dn wb[3] = {dn_var(h[o + pm], 3), dn_var(hu[o + pm], 4), dn_var(hv[o + pm], 5)};
+                        dn Fs[3], Gs[3];
+                        volume_flux_dn(g, htol, wa, wb, Fs, Gs);
+                        double cF, cG, dcoef;
+                        if (dir == 0) {
+                            cF = 0.5 * (G->yeta[o + p] + G->yeta[o + pm]);
+                            cG = -0.5 * (G->xeta[o + p] + G->xeta[o + pm]);
+                            dcoef = op->Dt[i][mm];
+                        } else {
+                            cF = -0.5 * (G->yxi[o + p] + G->yxi[o + pm]);
+                            cG = 0.5 * (G->xxi[o + p] + G->xxi[o + pm]);
+                            dcoef = op->Dt[j][mm];
+                        }
+                        for (int c = 0; c < 3; ++c) {
+                            double coef = dcoef * mu[c][p];
+                            for (int k = 0; k < 3; ++k) {
+                                gw[k][o + p] += coef * (cF * Fs[c].d[k] + cG * Gs[c].d[k]);
+                                gw[k][o + pm] += coef * (cF * Fs[c].d[3 + k] + cG * Gs[c].d[3 + k]);
+                            }
+                        }
+                    }
+            }
+        /* interface: L[c][p] += (+-) J^surf F*_n[c] / w at the face nodes, with
+         * the signs of rhs_impl (own trace '-', neighbour '+') */
+        for (int s = 0; s < 4; ++s)
+            for (int k = 0; k <= N; ++k) {
+                int i, j;
+                side_node(N, s, k, &i, &j);
+                int p = i * n1 + j;
+                int64_t q = o + p, qn = nbr_node(m, e, s, k);
+                double snx, sny;
+                scaled_normal(G, s, q, &snx, &sny);
+                double Js = sqrt(snx * snx + sny * sny);
+                dn wm[3] = {dn_var(h[q], 0), dn_var(hu[q], 1), dn_var(hv[q], 2)};
+                dn wp[3] = {dn_var(h[qn], 4), dn_var(hu[qn], 5), dn_var(hv[qn], 6)};
+                dn Fn[3];
+                surface_flux_dn(P, wm, dn_var(b[q], 3), wp, dn_var(b[qn], 7), snx / Js, sny / Js, Fn);
+                double contra = (s == 1 || s == 2) ? Js : -Js;       /* F~* = +-J^surf F*_n */
+                double fac = (s == 1 || s == 2) ? contra / op->w[N] : -contra / op->w[0];
+                for (int c = 0; c < 3; ++c) {
+                    double coef = fac * mu[c][p];
+                    for (int kk = 0; kk < 3; ++kk) {
+                        gw[kk][q] += coef * Fn[c].d[kk];
+                        gw[kk][qn] += coef * Fn[c].d[4 + kk];
+                    }
+                    gb[q] += coef * Fn[c].d[3];
+                    gb[qn] += coef * Fn[c].d[7];
+                }
+            }
+        /* source S = (g/2)(-h b_x, -h b_y) (eq. SourceDisc) with the split
+         * derivatives of rhs_impl, reversed term by term */
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j) {
+                int p = i * n1 + j;
+                double Db_xi = 0, Dyb_xi = 0, Dxb_xi = 0, Db_eta = 0, Dyb_eta = 0, Dxb_eta = 0;
+                for (int mm = 0; mm <= N; ++mm) {
+                    int pa = mm * n1 + j, pb = i * n1 + mm;
+                    Db_xi += op->D[i][mm] * b[o + pa];
+                    Dyb_xi += op->D[i][mm] * (G->yeta[o + pa] * b[o + pa]);
+                    Dxb_xi += op->D[i][mm] * (G->xeta[o + pa] * b[o + pa]);
+                    Db_eta += op->D[j][mm] * b[o + pb];
+                    Dyb_eta += op->D[j][mm] * (G->yxi[o + pb] * b[o + pb]);
+                    Dxb_eta += op->D[j][mm] * (G->xxi[o + pb] * b[o + pb]);
+                }
+                double bx = G->yeta[o + p] * Db_xi + Dyb_xi - G->yxi[o + p] * Db_eta - Dyb_eta;
+                double by = -G->xeta[o + p] * Db_xi - Dxb_xi + G->xxi[o + p] * Db_eta + Dxb_eta;
+                double sx_bar = -mu[1][p], sy_bar = -mu[2][p];          /* dPhi/dS */
+                gw[0][o + p] += sx_bar * (-0.5 * g * bx) + sy_bar * (-0.5 * g * by);
+                double bx_bar = sx_bar * (-0.5 * g * h[o + p]);
+                double by_bar = sy_bar * (-0.5 * g * h[o + p]);
+                double Db_xi_bar = G->yeta[o + p] * bx_bar - G->xeta[o + p] * by_bar;
+                double Dyb_xi_bar = bx_bar, Dxb_xi_bar = -by_bar;
+                double Db_eta_bar = -G->yxi[o + p] * bx_bar + G->xxi[o + p] * by_bar;
+                double Dyb_eta_bar = -bx_bar, Dxb_eta_bar = by_bar;
+                for (int mm = 0; mm <= N; ++mm) {
+                    int pa = mm * n1 + j, pb = i * n1 + mm;
+                    gb[o + pa] += op->D[i][mm] * (Db_xi_bar + G->yeta[o + pa] * Dyb_xi_bar +
+                                                  G->xeta[o + pa] * Dxb_xi_bar);
+                    gb[o + pb] += op->D[j][mm] * (Db_eta_bar + G->yxi[o + pb] * Dyb_eta_bar +
+                                                  G->xxi[o + pb] * Dxb_eta_bar);
+                }
+            }
+    }
+    return ORC_OK;
+}
+
+/* (dR/dW)^T lam and (dR/db)^T lam of the inviscid right-hand side at (W, b). */
+int orc_rhs_vjp(const orc_params *P, const orc_mesh *m, const double *b, const double *h,
+                const double *hu, const double *hv, const double *lh, const double *lhu,
+                const double *lhv, double *gh, double *ghu, double *ghv, double *gb)
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    if (P->av_on) return ORC_EINVAL;
+    orc_ops op;
+    build_ops(m->N, &op);
+    orc_geom G;
+    int64_t n = m->K * (int64_t)(m->N + 1) * (m->N + 1);
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    memset(gh, 0, sizeof(double) * n);
+    memset(ghu, 0, sizeof(double) * n);
+    memset(ghv, 0, sizeof(double) * n);
+    memset(gb, 0, sizeof(double) * n);
+    const double *lam[3] = {lh, lhu, lhv};
+    double *gw[3] = {gh, ghu, ghv};
+    st = rhs_vjp_acc(P, &op, m, &G, b, h, hu, hv, lam, 1.0, gw, gb);
+    geom_free(&G);
+    return st;
+}
+
+/* Gauge-misfit loss over nsteps fixed LSRK(5,4) steps of size dt from
+ * (h0, hu0, hv0):
+ *     L = 1/2 sum_{n=1..nsteps} sum_g (H_g(t_n) - target[n-1][g])^2 dt,
+ * H_g the water surface h + b interpolated at reference point (xi_g, eta_g)
+ * of element gelem[g] with the LGL Lagrange basis.  H_out [nsteps][ng]
+ * receives H_g(t_n).  With gb != NULL also the gradient: gb = dL/db for the
+ * initial state held fixed, and g{h,hu,hv}0 = dL/dW(0) (each may be NULL
+ * except gb).  All stage states are kept (no checkpointing): a plain
+ * reverse sweep.  Returns ORC_EINVAL if the limiter would act in any stage
+ * (the adjoint assumes it inactive) or the setup is out of scope. */
+int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
+                      const double *h0, const double *hu0, const double *hv0, int nsteps,
+                      double dt, int ng, const int32_t *gelem, const double *gxi,
+                      const double *geta, const double *target, double *loss, double *H_out,
+                      double *gb, double *gh0, double *ghu0, double *ghv0)
+{
+    int st = check_mesh(m);
+    if (st) return st;
+    if (P->av_on || P->integrator != 0 || nsteps < 1 || ng < 0 || !(dt > 0.0)) return ORC_EINVAL;
+    const int N = m->N, n1 = N + 1, np = n1 * n1;
+    for (int gg = 0; gg < ng; ++gg)
+        if (gelem[gg] < 0 || gelem[gg] >= m->K) return ORC_EINVAL;
+    orc_ops op;
+    build_ops(N, &op);
+    orc_geom G;
+    const int64_t n = m->K * (int64_t)np;
+    if (geom_alloc(&G, n)) { geom_free(&G); return ORC_ENOMEM; }
+    geometry(&op, m, &G);
+    /* gauge weights l_i(xi_g) l_j(eta_g) */
+    double *gw = malloc(sizeof(double) * (size_t)(ng > 0 ? ng : 1) * np);
+    /* every stage input of every step, plus the final state */
+    const int64_t nslot = (int64_t)nsteps * 5 + 1;
+    double *Ws = malloc(sizeof(double) * 3 * n * nslot);
+    double *R = malloc(sizeof(double) * 3 * n), *d = malloc(sizeof(double) * 3 * n);
+    double *Hg = malloc(sizeof(double) * (size_t)nsteps * (ng > 0 ? ng : 1));
+    if (!gw || !Ws || !R || !d || !Hg) {
+        free(gw); free(Ws); free(R); free(d); free(Hg); geom_free(&G);
+        return ORC_ENOMEM;
+    }
+    for (int gg = 0; gg < ng; ++gg)
+        for (int i = 0; i <= N; ++i)
+            for (int j = 0; j <= N; ++j)
+                gw[gg * np + i * n1 + j] = (double)(lagrange(N, op.xi, i, gxi[gg]) *
+                                                    lagrange(N, op.xi, j, geta[gg]));
+    memcpy(Ws, h0, sizeof(double) * n);
+    memcpy(Ws + n, hu0, sizeof(double) * n);
+    memcpy(Ws + 2 * n, hv0, sizeof(double) * n);
+    double L = 0.0;
+    st = ORC_OK;
+    for (int64_t q = 0; q < n; ++q)
+        if (!(h0[q] >= P->h_tol)) st = ORC_EINVAL;   /* the initial state must be wet too */
+    for (int it = 0; it < nsteps && st == ORC_OK; ++it) {
+        memset(d, 0, sizeof(double) * 3 * n);
+        for (int k = 0; k < 5 && st == ORC_OK; ++k) {
+            const int64_t s = (int64_t)it * 5 + k;
+            const double *W = Ws + s * 3 * n;
+            double *Wn = Ws + (s + 1) * 3 * n;
+            st = rhs_impl(P, &op, m, &G, b, W, W + n, W + 2 * n, R, R + n, R + 2 * n, NULL, NULL,
+                          NULL);
+            if (st) break;
+            for (int64_t q = 0; q < 3 * n; ++q) {
+                d[q] = LSRK_A[k] * d[q] + dt * R[q];
+                Wn[q] = W[q] + LSRK_B[k] * d[q];
+            }
+            if (P->limiter_on) {
+                int64_t nl = 0;
+                double *hh = Wn, *hhu = Wn + n, *hhv = Wn + 2 * n;
+                for (int64_t q = 0; q < n; ++q)
+                    if (!(hh[q] >= P->h_tol)) st = ORC_EINVAL;   /* cut-off or limiter would act */
+                if (st == ORC_OK) {
+                    st = limit_impl(P, &op, m, &G, hh, hhu, hhv, &nl);
+                    if (st == ORC_OK && nl > 0) st = ORC_EINVAL;
+                }
+            }
+        }
+        if (st) break;
+        const double *W = Ws + ((int64_t)it * 5 + 5) * 3 * n;
+        for (int gg = 0; gg < ng; ++gg) {
+            double H = 0.0;
+            for (int p = 0; p < np; ++p) {
+                int64_t q = (int64_t)gelem[gg] * np + p;
+                H += gw[gg * np + p] * (W[q] + b[q]);
+            }
+            Hg[(int64_t)it * ng + gg] = H;
+            double r = H - target[(int64_t)it * ng + gg];
+            L += 0.5 * r * r * dt;
+        }
+    }
+    if (st == ORC_OK) {
+        if (loss) *loss = L;
+        if (H_out) memcpy(H_out, Hg, sizeof(double) * (size_t)nsteps * ng);
+    }
+    if (st == ORC_OK && gb) {
+        /* reverse sweep: a = dL/dW (running), c = dL/d(register) */
+        double *a = calloc((size_t)(3 * n), sizeof(double));
+        double *c = calloc((size_t)(3 * n), sizeof(double));
+        if (!a || !c) st = ORC_ENOMEM;
+        memset(gb, 0, sizeof(double) * n);
+        for (int it = nsteps - 1; it >= 0 && st == ORC_OK; --it) {
+            /* the loss reads W(t_{it+1}) = h + b at the gauges */
+            for (int gg = 0; gg < ng; ++gg) {
+                double r = (Hg[(int64_t)it * ng + gg] - target[(int64_t)it * ng + gg]) * dt;
+                for (int p = 0; p < np; ++p) {
+                    int64_t q = (int64_t)gelem[gg] * np + p;
+                    a[q] += r * gw[gg * np + p];
+                    gb[q] += r * gw[gg * np + p];
+                }
+            }
+            /* W_k = W_{k-1} + B_k d_k,  d_k = A_k d_{k-1} + dt R(W_{k-1}),
+             * with d_{-1} = 0 at the start of the step */
+            memset(c, 0, sizeof(double) * 3 * n);
+            for (int k = 4; k >= 0 && st == ORC_OK; --k) {
+                const int64_t s = (int64_t)it * 5 + k;
+                const double *W = Ws + s * 3 * n;
+                for (int64_t q = 0; q < 3 * n; ++q) c[q] += LSRK_B[k] * a[q];
+                const double *lam[3] = {c, c + n, c + 2 * n};
+                double *ga[3] = {a, a + n, a + 2 * n};
+                st = rhs_vjp_acc(P, &op, m, &G, b, W, W + n, W + 2 * n, lam, dt, ga, gb);
+                for (int64_t q = 0; q < 3 * n; ++q) c[q] *= LSRK_A[k];
+            }
+        }
+        if (st == ORC_OK) {
+            if (gh0) memcpy(gh0, a, sizeof(double) * n);
+            if (ghu0) memcpy(ghu0, a + n, sizeof(double) * n);
+            if (ghv0) memcpy(ghv0, a + 2 * n, sizeof(double) * n);
+        }
+        free(a); free(c);
+    }
+    free(gw); free(Ws); free(R); free(d); free(Hg);
+    geom_free(&G);
+    return st;
+}

@@ -339,6 +339,43 @@ def ensemble_member(n: int, N: int, dam: bool, seed: int) -> Workload:
     return w
 
 
+def bathymetry_gradient(n: int = 128, N: int = 5, seed: int = 4, target_seed: int = 5,
+                        n_gauges: int = 32):
+    """Adjoint workload: n x n curvilinear periodic elements of [0,10]^2 (the
+    sin map of dam_break), degree N; bathymetry of 8 periodised Gaussians
+    (amplitude U(0,0.3), width U(0.5,2)) scaled down to max b <= 0.8; water
+    surface H0 = 1 + 0.05 exp(-|x - x0|^2) (x0 ~ U([2,8]^2)), so h = H0 - b
+    >= 0.2 everywhere; at rest.  Gauges: n_gauges points, each a uniformly
+    drawn element and reference point (xi, eta) ~ U([-1,1]^2).  The target
+    run uses the bed b + db, db = 4 periodised Gaussians (amplitude
+    U(-0.05,0.05), width U(0.5,1.5)) drawn from target_seed.  AV off, limiter
+    on (it never acts on this wet state).
+
+    Returns (Workload, extras) with extras = dict(H0, db, gelem, gxi, geta)."""
+    mesh = make_periodic_mesh(N, n, n, 10.0, 10.0, amp=0.1)
+    rng = np.random.default_rng(seed)
+    amps = rng.uniform(0.0, 0.3, 8)
+    widths = rng.uniform(0.5, 2.0, 8)
+    centers = rng.uniform(0.0, 10.0, (8, 2))
+    b = periodic_gaussians(mesh, [tuple(cc) for cc in centers], amps, widths)
+    if b.max() > 0.8:
+        b = b * (0.8 / b.max())
+    x0 = tuple(rng.uniform(2.0, 8.0, 2))
+    H0 = 1.0 + periodic_gaussians(mesh, [x0], [0.05], [1.0])
+    K = mesh.x.shape[0]
+    gelem = rng.integers(0, K, n_gauges).astype(np.int32)
+    gxi = rng.uniform(-1.0, 1.0, n_gauges)
+    geta = rng.uniform(-1.0, 1.0, n_gauges)
+    rt = np.random.default_rng(target_seed)
+    db = periodic_gaussians(mesh, [tuple(cc) for cc in rt.uniform(0.0, 10.0, (4, 2))],
+                            rt.uniform(-0.05, 0.05, 4), rt.uniform(0.5, 1.5, 4))
+    h = H0 - b
+    z = np.zeros_like(h)
+    w = Workload(f"bathymetry_gradient_{n}x{n}_N{N}", mesh, _c(b), _c(h), _c(z), _c(z.copy()),
+                 dict(g=9.81, surface_flux=0, av_on=0, limiter_on=1, cfl=0.5))
+    return w, dict(H0=_c(H0), db=_c(db), gelem=gelem, gxi=_c(gxi), geta=_c(geta))
+
+
 def random_states(rng: np.random.Generator, n: int, dry_fraction: float = 0.0,
                   hmax: float = 2.0, umax: float = 1.0):
     """Independent random point states (h, hu, hv, b) for flux-level tests."""
