@@ -252,6 +252,59 @@ int esdg_ensemble_degrees(const esdg_ensemble *en, int *n, int *N);
 int esdg_ensemble_autotune(esdg_ensemble *en, int reps, int *choices);
 const char *esdg_ensemble_last_error(const esdg_ensemble *en);
 
+/* ------------------------------------------------------------------------
+ * Discrete adjoint (float64 contexts, inviscid operator: av_on = 0)
+ * ------------------------------------------------------------------------
+ * Reverse mode of the semi-discrete operator R of esdg_rhs (volume term of
+ * eqs. fluxDiffFormF, Fmij and volumeFluxes, interface flux of appendix B,
+ * source of eq. SourceDisc) and of LSRK(5,4) steps, for gradients with
+ * respect to the nodal bathymetry.  The artificial viscosity is frozen at
+ * zero (av_on must be 0: ESDG_EINVAL otherwise).  The limiter must not act:
+ * on a wet state (h >= h_tol everywhere, so theta = 1 and no velocity is cut
+ * off) it is the identity and so is its derivative.  |x| is differentiated
+ * as sign(x) with sign(0) = 0.
+ */
+
+/* gh, ghu, ghv = (dR/dW)^T lam and gb = (dR/db)^T lam at the current state
+ * and bathymetry, lam = (lh, lhu, lhv).  Arrays [K][(N+1)^2] (mem: 0 host,
+ * 1 device). */
+int esdg_rhs_vjp(esdg_ctx *ctx, const double *lh, const double *lhu, const double *lhv, double *gh,
+                 double *ghu, double *ghv, double *gb, int mem);
+
+/* Gauges: ng >= 1 points, gauge g at reference point (xi[g], eta[g]) in
+ * [-1,1]^2 of element elem[g] (host arrays).  A gauge reads the water surface
+ * H = h + b interpolated with the LGL Lagrange basis.  Replaces earlier
+ * gauges; a new mesh clears them.  esdg_gauge_values returns H at the gauges
+ * for the current state (ng values; mem as above). */
+int esdg_set_gauges(esdg_ctx *ctx, int ng, const int32_t *elem, const double *xi, const double *eta);
+int esdg_gauge_values(esdg_ctx *ctx, double *H, int mem);
+
+/*
+ * Forward sweep of the gauge-misfit loss
+ *     L = 1/2 sum_{n=1..nsteps} sum_g (H_g(t_n) - target[n-1][g])^2 dt
+ * over nsteps LSRK(5,4) steps of fixed size dt from the current state
+ * (integrator must be 0).  target is [nsteps][ng] (mem: 0 host, 1 device);
+ * *loss (may be NULL) receives L and H (may be NULL) the gauge values
+ * [nsteps][ng].  The state is advanced as by esdg_step; the states at steps
+ * 0, every, 2 every, ... are kept on the device for esdg_adjoint_backward
+ * (ceil(nsteps/every) states, plus 5 every + 1 stage states during the
+ * backward sweep).  ESDG_EINVAL if the limiter acted in any stage.
+ */
+int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const double *target, int mem,
+                         double *loss, double *H);
+
+/*
+ * Reverse sweep of the last esdg_adjoint_forward: gb = seed * dL/db (the
+ * initial state held fixed) and, when not NULL, g{h,hu,hv}0 = seed * dL/dW(0).
+ * Each segment between checkpoints is recomputed from its checkpoint, then
+ * its stages are reversed.  Leaves the current state alone.  ESDG_EINVAL if
+ * no forward sweep is recorded or the bathymetry changed since.  (For an
+ * initial state set through the surface, h(0) = H0 - b, the total gradient
+ * is gb - gh0.)
+ */
+int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, double *ghu0,
+                          double *ghv0, int mem);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,9 @@
 // build, one object file per degree so the degrees compile in parallel).
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
+#include "esdg_adjoint.hpp"
 #include "esdg_kernels.hpp"
 #include "esdg_launch.hpp"
 
@@ -257,6 +260,59 @@ hipError_t Launch<N, R>::diag(const Bufs &B, int buf, const Phys<R> &P, const Ta
                        (const R *)B.W[buf][0], (const R *)B.W[buf][1], (const R *)B.W[buf][2],
                        (const R *)B.b, (const R *)B.Rb[0], (const R *)B.Rb[1], (const R *)B.Rb[2], B.part);
     return hipGetLastError();
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::adjoint_stage(const Bufs &B, const AdjCall &c, const Phys<R> &P, const Tab<R> &t,
+                                       hipStream_t s, Ev ev)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        AdjArgs a;
+        a.m = mesh_view<double>(B);
+        a.P = P;
+        a.tab = t;
+        a.tg = (const Tab<double> *)B.tabg;
+        a.h = (const double *)c.W[0];
+        a.hu = (const double *)c.W[1];
+        a.hv = (const double *)c.W[2];
+        for (int k = 0; k < 3; ++k) {
+            a.a[k] = (const double *)c.a[k];
+            a.c[k] = (const double *)c.c[k];
+            a.ao[k] = (double *)c.ao[k];
+            a.co[k] = (double *)c.co[k];
+        }
+        a.gbx = c.gbx;
+        a.gby = c.gby;
+        a.gbn = c.gbn;
+        a.ca = c.ca;
+        a.cb = c.cb;
+        a.dt = c.dt;
+        a.ntiles = ntiles_of<N>(B.K);
+        hipExtLaunchKernelGGL((adjoint_stage_kernel<N>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, ev.a, ev.b,
+                              0, a);
+        return hipGetLastError();
+    } else {
+        (void)B; (void)c; (void)P; (void)t; (void)s; (void)ev;
+        return hipErrorNotSupported;
+    }
+}
+
+template <int N, typename R>
+hipError_t Launch<N, R>::bathymetry_adjoint(const Bufs &B, const Tab<double> &td, const double *gbx,
+                                            const double *gby, const double *gbn, double *gb, hipStream_t s)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        constexpr int np = (N + 1) * (N + 1);
+        const int64_t n = B.K * np;
+        const int bs = 256;
+        hipLaunchKernelGGL((bathymetry_adjoint_kernel<N>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s,
+                           B.K, (const double *)B.Ax, (const double *)B.Cx, (const double *)B.Ae,
+                           (const double *)B.Ce, gbx, gby, gbn, gb, td);
+        return hipGetLastError();
+    } else {
+        (void)B; (void)td; (void)gbx; (void)gby; (void)gbn; (void)gb; (void)s;
+        return hipErrorNotSupported;
+    }
 }
 
 template struct Launch<ESDG_N, double>;

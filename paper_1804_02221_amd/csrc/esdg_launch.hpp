@@ -58,6 +58,15 @@ struct StageCall {
     int variant;       // stage-kernel workgroup size: 0 default, 1 alternative
 };
 
+// One reverse stage of the discrete adjoint (float64 contexts only).
+struct AdjCall {
+    const void *W[3];          // stage input state W_{k-1}
+    const void *a[3], *c[3];   // dL/dW_k and A_{k+1} dL/dd_{k+1} (nullptr: zero)
+    void *ao[3], *co[3];       // dL/dW_{k-1} and A_k dL/dd_k (co nullptr: not written)
+    double *gbx, *gby, *gbn;   // bathymetry cotangents, accumulated
+    double ca, cb, dt;         // A_k, B_k and the step
+};
+
 template <int N, typename R>
 struct Launch {
     static hipError_t geometry(const Bufs &B, const Tab<double> &td, hipStream_t s);
@@ -71,6 +80,10 @@ struct Launch {
                             hipStream_t s, Ev ev);
     static hipError_t limit(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
     static hipError_t dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s);
+    static hipError_t adjoint_stage(const Bufs &B, const AdjCall &c, const Phys<R> &P, const Tab<R> &t,
+                                    hipStream_t s, Ev ev);
+    static hipError_t bathymetry_adjoint(const Bufs &B, const Tab<double> &td, const double *gbx,
+                                         const double *gby, const double *gbn, double *gb, hipStream_t s);
     static hipError_t diag(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, int64_t *nblocks,
                            hipStream_t s);
     static int threads();

@@ -159,6 +159,28 @@ struct esdg_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_stage, ev_av;
     size_t ev_next = 0;
     std::string err = "no error";
+    std::vector<int32_t> inv_h;   // caller's element -> internal element
+    uint64_t b_version = 0;       // bumped by every esdg_set_bathymetry
+    // discrete adjoint (gauges, checkpoints, cotangent fields)
+    struct Adjoint {
+        int ng = 0;
+        int32_t *gel = nullptr;    // [ng] internal element of each gauge
+        double *gw = nullptr;      // [ng][np] Lagrange weights of each gauge point
+        double *gH = nullptr;      // [ng] scratch for esdg_gauge_values
+        double *lam = nullptr;     // [4][3][n]: dL/dW (two buffers), dL/d(register) (two buffers)
+        double *gbf = nullptr;     // [4][n]: cotangents of b_x, b_y, face b; assembled dL/db
+        double *ckpt = nullptr;    // [ckpt_cap][3][n] states at the checkpoints
+        int64_t ckpt_cap = 0;
+        double *store = nullptr;   // [store_cap][3][n] stage inputs of one segment
+        int64_t store_cap = 0;
+        double *Hg = nullptr, *Tg = nullptr;   // [nsteps][ng] gauge values and target
+        int64_t h_cap = 0;
+        double *loss = nullptr;    // [1]
+        int nsteps = 0, every = 0;
+        double dt = 0.0;
+        bool ready = false;        // a forward sweep is recorded
+        uint64_t b_version = 0;
+    } adj;
 };
 
 namespace {
@@ -259,6 +281,13 @@ void free_bufs(esdg_ctx *c)
     for (void *p : B.Rb)
         if (p) (void)hipFree(p);
     B = Bufs{};
+    {
+        auto &A = c->adj;
+        void *qs[] = {A.gel, A.gw, A.gH, A.lam, A.gbf, A.ckpt, A.store, A.Hg, A.Tg, A.loss};
+        for (void *p : qs)
+            if (p) (void)hipFree(p);
+        A = esdg_ctx::Adjoint{};
+    }
     if (c->perm) (void)hipFree(c->perm);
     c->perm = nullptr;
     c->stage_d = nullptr;
@@ -507,7 +536,7 @@ int run_rhs(esdg_ctx *ctx, int buf)
 
 extern "C" {
 
-int esdg_abi_version(void) { return 101; }
+int esdg_abi_version(void) { return 102; }
 
 void esdg_default_params(esdg_params *p, int N)
 {
@@ -664,6 +693,7 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
             code2[e * 4 + s] = code[(int64_t)perm[e] * 4 + s];
         }
     free_bufs(ctx);
+    ctx->inv_h = inv;
     ctx->N = N;
     ctx->K = K;
     build_tables(N, ctx->ht);
@@ -816,6 +846,7 @@ int esdg_set_bathymetry(esdg_ctx *ctx, const double *b, int mem)
     CK(dispatch(ctx, [&](auto L, auto) { return decltype(L)::bathymetry(ctx->B, db, ctx->td, ctx->stream); }));
     CK(hipStreamSynchronize(ctx->stream));
     ctx->have_b = true;
+    ++ctx->b_version;
     return ESDG_OK;
 }
 
@@ -1392,6 +1423,385 @@ int esdg_ensemble_degrees(const esdg_ensemble *en, int *n, int *N)
 const char *esdg_ensemble_last_error(const esdg_ensemble *en)
 {
     return en ? en->err.c_str() : "null ensemble";
+}
+
+}  // extern "C"
+
+// ==========================================================================
+// Discrete adjoint: gauges, gauge-misfit loss, checkpointed reverse sweep
+// ==========================================================================
+namespace {
+
+__global__ void fill_double_kernel(double *p, double v, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+// Water surface H = h + b interpolated at every gauge point.
+__global__ void gauge_kernel(const double *__restrict__ h, const double *__restrict__ b,
+                             const int32_t *__restrict__ gel, const double *__restrict__ gw, int ng, int np,
+                             double *__restrict__ out)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int64_t o = (int64_t)gel[g] * np;
+    double s = 0.0;
+    for (int p = 0; p < np; ++p) s += gw[(int64_t)g * np + p] * (h[o + p] + b[o + p]);
+    out[g] = s;
+}
+
+// Cotangent of one step's gauge misfit, w (H_g - T_g) l_g, added to dL/dh and
+// to dL/db at the nodes of the gauge's element.  One workgroup; lane p owns
+// node p of every gauge element, gauges in sequence (gauges may share an
+// element).
+__global__ void gauge_adjoint_kernel(const double *__restrict__ H, const double *__restrict__ Tg, double w,
+                                     const int32_t *__restrict__ gel, const double *__restrict__ gw, int ng, int np,
+                                     double *ah, double *gbn)
+{
+    const int p = threadIdx.x;
+    if (p >= np) return;
+    for (int g = 0; g < ng; ++g) {
+        const double c = (H[g] - Tg[g]) * w * gw[(int64_t)g * np + p];
+        const int64_t q = (int64_t)gel[g] * np + p;
+        ah[q] += c;
+        gbn[q] += c;
+    }
+}
+
+// L = 1/2 dt sum (H - T)^2 over every step and gauge (one workgroup).
+__global__ void misfit_loss_kernel(const double *__restrict__ H, const double *__restrict__ Tg, int64_t n,
+                                   double dt, double *out)
+{
+    __shared__ double s[256];
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (int64_t k = t; k < n; k += 256) {
+        const double r = H[k] - Tg[k];
+        acc += r * r;
+    }
+    s[t] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) s[t] += s[t + st];
+        __syncthreads();
+    }
+    if (t == 0) out[0] = 0.5 * dt * s[0];
+}
+
+int fill(esdg_ctx *ctx, double *p, double v, int64_t n)
+{
+    const int64_t want = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_double_kernel, dim3((unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096)), dim3(256), 0,
+                       ctx->stream, p, v, n);
+    CK(hipGetLastError());
+    return ESDG_OK;
+}
+
+bool check_adjoint_ctx(esdg_ctx *ctx)
+{
+    if (!check_ctx(ctx, true)) return false;
+    if (ctx->prec != 64) return fail(ctx, ESDG_EINVAL, "the adjoint needs a float64 context"), false;
+    if (ctx->P.av_on) return fail(ctx, ESDG_EINVAL, "the adjoint covers the inviscid operator (av_on = 0)"), false;
+    if (n_inst(ctx) != 1) return fail(ctx, ESDG_EINVAL, "the adjoint runs on single-instance contexts"), false;
+    return true;
+}
+
+// Cotangent fields (allocated once per mesh).
+int adj_fields(esdg_ctx *ctx)
+{
+    auto &A = ctx->adj;
+    const int64_t n = nodes(ctx);
+    if (!A.lam) TRY(alloc(ctx, &A.lam, 12 * n * sizeof(double)));
+    if (!A.gbf) TRY(alloc(ctx, &A.gbf, 4 * n * sizeof(double)));
+    if (!A.loss) TRY(alloc(ctx, &A.loss, sizeof(double)));
+    return ESDG_OK;
+}
+
+// Grow a [slots][3][n] state array.
+int adj_slots(esdg_ctx *ctx, double **p, int64_t *cap, int64_t want)
+{
+    if (*cap >= want) return ESDG_OK;
+    if (*p) CK(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    TRY(alloc(ctx, p, (size_t)want * 3 * nodes(ctx) * sizeof(double)));
+    *cap = want;
+    return ESDG_OK;
+}
+
+int copy_state(esdg_ctx *ctx, double *dst, void *const src[3])
+{
+    const int64_t n = nodes(ctx);
+    for (int c = 0; c < 3; ++c)
+        CK(hipMemcpyAsync(dst + c * n, src[c], n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    return ESDG_OK;
+}
+
+// One forward LSRK stage from state slot `in` to `out` (the stage kernel of
+// esdg_step, writing the given buffers).
+int adj_forward_stage(esdg_ctx *ctx, double *in, double *out, int k)
+{
+    Bufs B2 = ctx->B;
+    const int64_t n = nodes(ctx);
+    for (int c = 0; c < 3; ++c) {
+        B2.W[0][c] = in + c * n;
+        B2.W[1][c] = out + c * n;
+    }
+    StageCall sc{kModeLsrk, false, 0, 1, 0, false, kLsrkA[k], kLsrkB[k], false, k < 4};
+    sc.variant = ctx->stage_variant;
+    CK(dispatch(ctx, [&](auto L, auto r) {
+        using R = decltype(r);
+        return decltype(L)::stage(B2, sc, phys<R>(ctx), tab<R>(ctx), ctx->stream, Ev{});
+    }));
+    return ESDG_OK;
+}
+
+int adj_stage(esdg_ctx *ctx, const AdjCall &c)
+{
+    CK(dispatch(ctx, [&](auto L, auto r) {
+        using R = decltype(r);
+        return decltype(L)::adjoint_stage(ctx->B, c, phys<R>(ctx), tab<R>(ctx), ctx->stream, Ev{});
+    }));
+    return ESDG_OK;
+}
+
+int adj_assemble_b(esdg_ctx *ctx)
+{
+    const int64_t n = nodes(ctx);
+    double *g = ctx->adj.gbf;
+    CK(dispatch(ctx, [&](auto L, auto) {
+        return decltype(L)::bathymetry_adjoint(ctx->B, ctx->td, g, g + n, g + 2 * n, g + 3 * n, ctx->stream);
+    }));
+    return ESDG_OK;
+}
+
+int gauge_values_into(esdg_ctx *ctx, int buf_or_neg, const double *state_h, double *out)
+{
+    auto &A = ctx->adj;
+    const int np = (ctx->N + 1) * (ctx->N + 1);
+    const double *h = state_h ? state_h : (const double *)ctx->B.W[buf_or_neg][0];
+    hipLaunchKernelGGL(gauge_kernel, dim3((unsigned)((A.ng + 63) / 64)), dim3(64), 0, ctx->stream, h,
+                       (const double *)ctx->B.b, A.gel, A.gw, A.ng, np, out);
+    CK(hipGetLastError());
+    return ESDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int esdg_set_gauges(esdg_ctx *ctx, int ng, const int32_t *elem, const double *xi, const double *eta)
+{
+    if (!ctx) return ESDG_EINVAL;
+    if (!ctx->have_mesh) return fail(ctx, ESDG_EINVAL, "upload_mesh first");
+    if (ng < 1 || !elem || !xi || !eta) return fail(ctx, ESDG_EINVAL, "gauges: need ng >= 1 and three arrays");
+    CK(hipSetDevice(ctx->device));
+    const int N = ctx->N, nf = N + 1, np = nf * nf;
+    std::vector<int32_t> gel(ng);
+    std::vector<double> gw((size_t)ng * np);
+    for (int g = 0; g < ng; ++g) {
+        if (elem[g] < 0 || elem[g] >= ctx->K) return fail(ctx, ESDG_EINVAL, "gauge %d: element out of range", g);
+        if (!(std::fabs(xi[g]) <= 1.0) || !(std::fabs(eta[g]) <= 1.0))
+            return fail(ctx, ESDG_EINVAL, "gauge %d: reference point outside [-1, 1]^2", g);
+        gel[g] = ctx->inv_h[elem[g]];
+        // Lagrange basis of the LGL nodes at xi and eta
+        long double lx[kMaxNF], le[kMaxNF];
+        for (int k = 0; k < nf; ++k) {
+            long double px = 1.0L, pe = 1.0L;
+            for (int m = 0; m < nf; ++m)
+                if (m != k) {
+                    const long double d = ctx->ht.x[k] - ctx->ht.x[m];
+                    px *= ((long double)xi[g] - ctx->ht.x[m]) / d;
+                    pe *= ((long double)eta[g] - ctx->ht.x[m]) / d;
+                }
+            lx[k] = px;
+            le[k] = pe;
+        }
+        for (int i = 0; i < nf; ++i)
+            for (int j = 0; j < nf; ++j) gw[(size_t)g * np + i * nf + j] = (double)(lx[i] * le[j]);
+    }
+    auto &A = ctx->adj;
+    if (A.gel) CK(hipFree(A.gel));
+    if (A.gw) CK(hipFree(A.gw));
+    if (A.gH) CK(hipFree(A.gH));
+    A.gel = nullptr; A.gw = nullptr; A.gH = nullptr; A.ng = 0; A.ready = false;
+    TRY(alloc(ctx, &A.gel, ng * sizeof(int32_t)));
+    TRY(alloc(ctx, &A.gw, gw.size() * sizeof(double)));
+    TRY(alloc(ctx, &A.gH, ng * sizeof(double)));
+    CK(hipMemcpyAsync(A.gel, gel.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(A.gw, gw.data(), gw.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    A.ng = ng;
+    return ESDG_OK;
+}
+
+int esdg_gauge_values(esdg_ctx *ctx, double *H, int mem)
+{
+    if (!H) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    if (ctx->prec != 64) return fail(ctx, ESDG_EINVAL, "gauges need a float64 context");
+    if (ctx->adj.ng < 1) return fail(ctx, ESDG_EINVAL, "esdg_set_gauges first");
+    TRY(gauge_values_into(ctx, ctx->cur, nullptr, ctx->adj.gH));
+    CK(hipMemcpyAsync(H, ctx->adj.gH, ctx->adj.ng * sizeof(double),
+                      mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int esdg_rhs_vjp(esdg_ctx *ctx, const double *lh, const double *lhu, const double *lhv, double *gh, double *ghu,
+                 double *ghv, double *gb, int mem)
+{
+    if (!lh || !lhu || !lhv || !gh || !ghu || !ghv || !gb)
+        return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_adjoint_ctx(ctx)) return ESDG_EINVAL;
+    TRY(adj_fields(ctx));
+    const int64_t n = nodes(ctx), per = n / ctx->K;
+    double *L = ctx->adj.lam;   // [0..2] result, [6..8] input cotangent
+    TRY(upload_field(ctx, L + 6 * n, lh, per, mem));
+    TRY(upload_field(ctx, L + 7 * n, lhu, per, mem));
+    TRY(upload_field(ctx, L + 8 * n, lhv, per, mem));
+    TRY(fill(ctx, ctx->adj.gbf, 0.0, 3 * n));
+    AdjCall c{};
+    for (int k = 0; k < 3; ++k) {
+        c.W[k] = ctx->B.W[ctx->cur][k];
+        c.a[k] = nullptr;
+        c.c[k] = L + (6 + k) * n;
+        c.ao[k] = L + k * n;
+        c.co[k] = nullptr;
+    }
+    c.gbx = ctx->adj.gbf;
+    c.gby = ctx->adj.gbf + n;
+    c.gbn = ctx->adj.gbf + 2 * n;
+    c.ca = 0.0;
+    c.cb = 0.0;
+    c.dt = 1.0;
+    TRY(adj_stage(ctx, c));
+    TRY(adj_assemble_b(ctx));
+    TRY(download_field(ctx, gh, L, per, mem));
+    TRY(download_field(ctx, ghu, L + n, per, mem));
+    TRY(download_field(ctx, ghv, L + 2 * n, per, mem));
+    TRY(download_field(ctx, gb, ctx->adj.gbf + 3 * n, per, mem));
+    if (mem) CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
+}
+
+int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const double *target, int mem,
+                         double *loss, double *H)
+{
+    if (!target) return ctx ? fail(ctx, ESDG_EINVAL, "null target") : ESDG_EINVAL;
+    if (!check_adjoint_ctx(ctx)) return ESDG_EINVAL;
+    auto &A = ctx->adj;
+    if (A.ng < 1) return fail(ctx, ESDG_EINVAL, "esdg_set_gauges first");
+    if (ctx->P.integrator != 0) return fail(ctx, ESDG_EINVAL, "the adjoint covers LSRK(5,4) (integrator 0)");
+    if (nsteps < 1 || every < 1 || !(dt > 0.0) || !std::isfinite(dt))
+        return fail(ctx, ESDG_EINVAL, "need nsteps >= 1, every >= 1 and a finite dt > 0");
+    A.ready = false;
+    TRY(adj_fields(ctx));
+    const int64_t nseg = (nsteps + every - 1) / every;
+    TRY(adj_slots(ctx, &A.ckpt, &A.ckpt_cap, nseg));
+    const int64_t nh = (int64_t)nsteps * A.ng;
+    if (A.h_cap < nh) {
+        if (A.Hg) CK(hipFree(A.Hg));
+        if (A.Tg) CK(hipFree(A.Tg));
+        A.Hg = A.Tg = nullptr;
+        A.h_cap = 0;
+        TRY(alloc(ctx, &A.Hg, nh * sizeof(double)));
+        TRY(alloc(ctx, &A.Tg, nh * sizeof(double)));
+        A.h_cap = nh;
+    }
+    CK(hipMemcpyAsync(A.Tg, target, nh * sizeof(double), mem ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                      ctx->stream));
+    const int64_t n = nodes(ctx);
+    TRY(reset_flags(ctx));
+    for (int it = 0; it < nsteps; ++it) {
+        if (it % every == 0) TRY(copy_state(ctx, A.ckpt + (it / every) * 3 * n, ctx->B.W[ctx->cur]));
+        TRY(launch_one_step(ctx, dt));
+        TRY(gauge_values_into(ctx, ctx->cur, nullptr, A.Hg + (int64_t)it * A.ng));
+    }
+    hipLaunchKernelGGL(misfit_loss_kernel, dim3(1), dim3(256), 0, ctx->stream, A.Hg, A.Tg, nh, dt, A.loss);
+    CK(hipGetLastError());
+    int flags[4];
+    TRY(read_flags(ctx, flags));
+    if (flags[0] || flags[1])
+        return fail(ctx, ESDG_EINVAL, "the limiter acted during the run: outside the adjoint's scope");
+    if (loss) CK(hipMemcpy(loss, A.loss, sizeof(double), hipMemcpyDeviceToHost));
+    if (H) {
+        CK(hipMemcpyAsync(H, A.Hg, nh * sizeof(double), mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+    }
+    A.nsteps = nsteps;
+    A.every = every;
+    A.dt = dt;
+    A.b_version = ctx->b_version;
+    A.ready = true;
+    return ESDG_OK;
+}
+
+int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, double *ghu0, double *ghv0, int mem)
+{
+    if (!gb) return ctx ? fail(ctx, ESDG_EINVAL, "null gb") : ESDG_EINVAL;
+    if (!check_adjoint_ctx(ctx)) return ESDG_EINVAL;
+    auto &A = ctx->adj;
+    if (!A.ready) return fail(ctx, ESDG_EINVAL, "esdg_adjoint_forward first");
+    if (A.b_version != ctx->b_version) return fail(ctx, ESDG_EINVAL, "the bathymetry changed since the forward sweep");
+    if (!std::isfinite(seed)) return fail(ctx, ESDG_EINVAL, "seed must be finite");
+    const int64_t n = nodes(ctx), per = n / ctx->K;
+    const int np = (ctx->N + 1) * (ctx->N + 1);
+    TRY(adj_slots(ctx, &A.store, &A.store_cap, (int64_t)std::min(A.every, A.nsteps) * 5 + 1));
+    double *lamA[2] = {A.lam, A.lam + 3 * n}, *lamC[2] = {A.lam + 6 * n, A.lam + 9 * n};
+    double *gbx = A.gbf, *gby = A.gbf + n, *gbn = A.gbf + 2 * n;
+    TRY(fill(ctx, A.gbf, 0.0, 3 * n));
+    TRY(fill(ctx, lamA[0], 0.0, 3 * n));
+    // the recomputed stages read the step from the scalar block
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.dscal, A.dt, 1);
+    CK(hipGetLastError());
+    int pa = 0;
+    const int nseg = (A.nsteps + A.every - 1) / A.every;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * A.every, s1 = std::min(A.nsteps, s0 + A.every);
+        // recompute the segment from its checkpoint, keeping every stage input
+        CK(hipMemcpyAsync(A.store, A.ckpt + (int64_t)seg * 3 * n, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+        for (int it = s0; it < s1; ++it)
+            for (int k = 0; k < 5; ++k) {
+                const int64_t sl = (int64_t)(it - s0) * 5 + k;
+                TRY(adj_forward_stage(ctx, A.store + sl * 3 * n, A.store + (sl + 1) * 3 * n, k));
+            }
+        // reverse the steps of the segment
+        for (int it = s1 - 1; it >= s0; --it) {
+            hipLaunchKernelGGL(gauge_adjoint_kernel, dim3(1), dim3(128), 0, ctx->stream, A.Hg + (int64_t)it * A.ng,
+                               A.Tg + (int64_t)it * A.ng, seed * A.dt, A.gel, A.gw, A.ng, np, lamA[pa], gbn);
+            CK(hipGetLastError());
+            for (int k = 4; k >= 0; --k) {
+                const int64_t sl = (int64_t)(it - s0) * 5 + k;
+                AdjCall c{};
+                for (int q = 0; q < 3; ++q) {
+                    c.W[q] = A.store + (sl * 3 + q) * n;
+                    c.a[q] = lamA[pa] + q * n;
+                    c.c[q] = k == 4 ? nullptr : lamC[pa] + q * n;
+                    c.ao[q] = lamA[1 - pa] + q * n;
+                    c.co[q] = k == 0 ? nullptr : lamC[1 - pa] + q * n;
+                }
+                c.gbx = gbx;
+                c.gby = gby;
+                c.gbn = gbn;
+                c.ca = kLsrkA[k];
+                c.cb = kLsrkB[k];
+                c.dt = A.dt;
+                TRY(adj_stage(ctx, c));
+                pa = 1 - pa;
+            }
+        }
+    }
+    TRY(adj_assemble_b(ctx));
+    TRY(download_field(ctx, gb, A.gbf + 3 * n, per, mem));
+    if (gh0) TRY(download_field(ctx, gh0, lamA[pa], per, mem));
+    if (ghu0) TRY(download_field(ctx, ghu0, lamA[pa] + n, per, mem));
+    if (ghv0) TRY(download_field(ctx, ghv0, lamA[pa] + 2 * n, per, mem));
+    CK(hipStreamSynchronize(ctx->stream));
+    return ESDG_OK;
 }
 
 }  // extern "C"

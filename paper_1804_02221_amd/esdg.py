@@ -47,6 +47,14 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_1804_02221_amd/build.py "
                               "(there is no fallback implementation)")
+        # torch ships its own HIP runtime; loaded first, it is the one runtime
+        # of the process and the library binds to it (loaded after the
+        # library, a second runtime would come up beside it and torch would
+        # see no GPU)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
         sig = {
@@ -86,6 +94,11 @@ def lib() -> C.CDLL:
             "esdg_ensemble_autotune": ([P, I, P], I),
             "esdg_autotune": ([P, I, P, P], I),
             "esdg_set_stage_variant": ([P, I], I),
+            "esdg_rhs_vjp": ([P, P, P, P, P, P, P, P, I], I),
+            "esdg_set_gauges": ([P, I, P, P, P], I),
+            "esdg_gauge_values": ([P, P, I], I),
+            "esdg_adjoint_forward": ([P, I, D, I, P, I, P, P], I),
+            "esdg_adjoint_backward": ([P, D, P, P, P, P, I], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -150,6 +163,7 @@ class Solver:
         self.precision = precision
         self.N = None
         self.K = None
+        self.n_gauges = 0
         if stream is not None:
             self.set_stream(stream)
 
@@ -217,6 +231,7 @@ class Solver:
         self._check(lib().esdg_upload_mesh(self._ctx, int(N), int(K), ax.ptr, ay.ptr, ne.ptr, ns.ptr,
                                            fl.ptr, ax.mem))
         self.N, self.K = int(N), int(K)
+        self.n_gauges = 0
 
     def set_bathymetry(self, b):
         a = _Arg(b, self.n_nodes)
@@ -315,6 +330,59 @@ class Solver:
         sm, sn, am, an = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
         self._check(lib().esdg_profile_read(self._ctx, C.byref(sm), C.byref(sn), C.byref(am), C.byref(an)))
         return dict(stage_ms=sm.value, stage_launches=sn.value, av_ms=am.value, av_launches=an.value)
+
+
+    # -- discrete adjoint -------------------------------------------------
+    def rhs_vjp(self, lh, lhu, lhv, device: bool | None = None):
+        """(dR/dW)^T lam and (dR/db)^T lam at the current state: returns
+        (gh, ghu, ghv, gb).  Outputs on the device when the inputs are CUDA
+        tensors (or device=True)."""
+        a = [_Arg(x, self.n_nodes) for x in (lh, lhu, lhv)]
+        if len({x.mem for x in a}) != 1:
+            raise ValueError("mix of host and device arrays")
+        dev = bool(a[0].mem) if device is None else device
+        if dev != bool(a[0].mem):
+            raise ValueError("inputs and outputs must both be host or both device arrays")
+        outs = self._outs(4, self.n_nodes, dev)
+        ps = [_Arg(o) for o in outs]
+        self._check(lib().esdg_rhs_vjp(self._ctx, *[x.ptr for x in a], *[p.ptr for p in ps], a[0].mem))
+        return self._shape(outs)
+
+    def set_gauges(self, elem, xi, eta):
+        e = np.ascontiguousarray(elem, dtype=np.int32)
+        x = np.ascontiguousarray(xi, dtype=np.float64)
+        y = np.ascontiguousarray(eta, dtype=np.float64)
+        if not (e.size == x.size == y.size):
+            raise ValueError("gauge arrays differ in length")
+        self._check(lib().esdg_set_gauges(self._ctx, int(e.size), e.ctypes.data_as(C.c_void_p),
+                                          x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p)))
+        self.n_gauges = int(e.size)
+
+    def gauge_values(self):
+        out = np.zeros(self.n_gauges)
+        self._check(lib().esdg_gauge_values(self._ctx, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def adjoint_forward(self, nsteps: int, dt: float, every: int, target, want_H: bool = False):
+        """Gauge-misfit loss over nsteps fixed steps (checkpoints every
+        `every` steps); target [nsteps, ng] host or device.  Returns the loss
+        (and the gauge values [nsteps, ng] with want_H)."""
+        t = _Arg(target, int(nsteps) * self.n_gauges)
+        loss = C.c_double(0.0)
+        H = np.zeros((int(nsteps), self.n_gauges)) if want_H else None
+        if want_H and t.mem:
+            raise ValueError("want_H needs a host target")
+        self._check(lib().esdg_adjoint_forward(self._ctx, int(nsteps), float(dt), int(every), t.ptr, t.mem,
+                                               C.byref(loss),
+                                               H.ctypes.data_as(C.c_void_p) if want_H else None))
+        return (loss.value, H) if want_H else loss.value
+
+    def adjoint_backward(self, seed: float = 1.0, device: bool = False):
+        """seed * (dL/db, dL/dh0, dL/dhu0, dL/dhv0) of the last forward sweep."""
+        outs = self._outs(4, self.n_nodes, device)
+        ps = [_Arg(o) for o in outs]
+        self._check(lib().esdg_adjoint_backward(self._ctx, float(seed), *[p.ptr for p in ps], ps[0].mem))
+        return self._shape(outs)
 
 
 class Ensemble:
