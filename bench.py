@@ -152,6 +152,68 @@ def ensemble_bench(esdg, dev, members, steps: int):
                 speedup=t_seq / t_ens, stage_variant={str(k): v for k, v in tuned.items()})
 
 
+def adjoint_bench(esdg, dev, stream, steps: int = 400, every: int = 20):
+    """Bathymetry-gradient workload (128 x 128 elements, N = 5, 32 gauges):
+    gauge-misfit loss over `steps` fixed LSRK(5,4) steps against a target run
+    over b + db, its gradient by the checkpointed reverse sweep, and the time
+    of both against the plain solver's steps."""
+    import torch
+    from paper_1804_02221_amd.inputs import bathymetry_gradient
+    w, x = bathymetry_gradient()
+    N = w.mesh.N
+    s = esdg.Solver(dev, 64, stream=stream)
+    s.upload_mesh(w.mesh)
+    s.set_params(esdg.default_params(N, **w.params))
+    s.set_bathymetry(w.b)
+    s.set_state(w.h, w.hu, w.hv)
+    s.set_gauges(x["gelem"], x["gxi"], x["geta"])
+    dt = float(s.compute_dt()[0])
+    ng = len(x["gelem"])
+    zero = np.zeros_like(w.h)
+    # target run over b + db
+    s.set_bathymetry(w.b + x["db"])
+    s.set_state(x["H0"] - w.b - x["db"], zero, zero)
+    _, tgt = s.adjoint_forward(steps, dt, every, np.zeros((steps, ng)), want_H=True)
+    s.set_bathymetry(w.b)
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    # warm-up of every path, then the timed runs
+    s.set_state(w.h, w.hu, w.hv)
+    s.step(2, dt)
+    s.set_state(w.h, w.hu, w.hv)
+    s.adjoint_forward(every, dt, every, tgt[:every])
+    s.adjoint_backward()
+    s.set_state(w.h, w.hu, w.hv)
+    _, t_plain = timed(lambda: s.step(steps, dt))
+    s.set_state(w.h, w.hu, w.hv)
+    loss, t_fwd = timed(lambda: s.adjoint_forward(steps, dt, every, tgt))
+    g, t_bwd = timed(lambda: s.adjoint_backward(device=True))
+    gb, gh0 = g[0].cpu().numpy(), g[1].cpu().numpy()
+    gtot = gb - gh0
+    # gradient on the continuous periodic nodes: sum over coincident DG nodes
+    lat = np.zeros((w.mesh.nx * N, w.mesh.ny * N))
+    np.add.at(lat, (w.mesh.ax, w.mesh.ay), gtot)
+    nodes = w.mesh.K * (N + 1) ** 2
+    n = nodes * 3 * 8
+    s.close()
+    return dict(workload=("wet Gaussian surface bump over an 8-Gaussian bed on 128x128 curvilinear periodic "
+                          "elements of [0,10]^2, N=5, AV off, limiter on (inactive), ES flux, 32 gauges, "
+                          "target run over b + db"),
+                nodes=nodes, steps=steps, checkpoint_every=every, gauges=ng, dt=dt, loss=loss,
+                plain_forward_ms=t_plain * 1e3, forward_ms=t_fwd * 1e3, backward_ms=t_bwd * 1e3,
+                adjoint_forward_ratio=t_bwd / t_plain, total_ratio=(t_fwd + t_bwd) / t_plain,
+                backward_value=nodes * 5 * steps / t_bwd,
+                gradient_values=int(gtot.size), continuous_nodes=int(lat.size),
+                gradient_norm=float(np.linalg.norm(gtot)), continuous_gradient_norm=float(np.linalg.norm(lat)),
+                checkpoint_bytes=((steps + every - 1) // every) * n, segment_bytes=(every * 5 + 1) * n)
+
+
 def cpu_baseline(N: int, n_patch: int):
     import oracle
     from paper_1804_02221_amd.inputs import smooth_sweep
@@ -186,6 +248,8 @@ def main():
     ap.add_argument("--ensemble", type=int, default=64,
                     help="instances of the batched-ensemble comparison (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=5)
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="time the bathymetry-gradient adjoint (128^2 elements, N=5, 400 steps)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick the stage-kernel workgroup size per run with the library's autotuner")
     args = ap.parse_args()
@@ -300,6 +364,12 @@ def main():
                          "Gaussian-sum bed, AV + limiter, LSRK(5,4), adaptive dt per instance")
         del members
 
+    adj = None
+    if args.adjoint:
+        log("bathymetry-gradient adjoint")
+        adj = adjoint_bench(esdg, dev, stream)
+        log(f"adjoint: backward / plain forward = {adj['adjoint_forward_ratio']:.2f}")
+
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         log(f"CPU oracle baseline on a {args.cpu_patch}^2 patch")
@@ -347,6 +417,8 @@ def main():
         out["sweep"] = sweep
     if ens:
         out["ensemble"] = ens
+    if adj:
+        out["adjoint"] = adj
     print(json.dumps(out), flush=True)
 
 
