@@ -216,11 +216,13 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
         s_fg[0][f] = gh; s_fg[1][f] = gu; s_fg[2][f] = gv; s_fg[3][f] = gb;
     }
 
-    // ---- volume: pairs along xi and eta; z = Dz_im mu_i + Dz_mi mu_m (D~ = 2 Dz) ----
+    // ---- volume: pairs along xi and eta; z = Dz_im mu_i + Dz_mi mu_m (D~ = 2 Dz).
+    // Unrolled by two only: a full unroll hoists every partner's LDS reads
+    // and needs more registers than one wave per SIMD leaves ----
     R P1 = 0, P2 = 0, Gh = 0, Tu = 0, Tv = 0;
     {
         const int base = el * np;
-#pragma unroll
+#pragma unroll 2
         for (int mm = 0; mm < nf; ++mm) {
             const int qq = base + mm * nf + j;
             const R da = a.tg->Dz[i * kMaxNF + mm], db = a.tg->Dz[mm * kMaxNF + i];
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
             Gh += s_h[qq] * (sA * z1 + sC * z2);
             Tu += sA * tt; Tv += sC * tt;
         }
-#pragma unroll
+#pragma unroll 2
         for (int mm = 0; mm < nf; ++mm) {
             const int qq = base + i * nf + mm;
             const R da = a.tg->Dz[j * kMaxNF + mm], db = a.tg->Dz[mm * kMaxNF + j];

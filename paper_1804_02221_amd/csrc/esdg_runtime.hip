@@ -166,6 +166,8 @@ struct esdg_ctx {
         int ng = 0;
         int32_t *gel = nullptr;    // [ng] internal element of each gauge
         double *gw = nullptr;      // [ng][np] Lagrange weights of each gauge point
+        int nu = 0;                // elements holding gauges
+        int32_t *ug = nullptr;     // [nu] those elements, [nu + 1] offsets, [ng] gauges sorted by element
         double *gH = nullptr;      // [ng] scratch for esdg_gauge_values
         double *lam = nullptr;     // [4][3][n]: dL/dW (two buffers), dL/d(register) (two buffers)
         double *gbf = nullptr;     // [4][n]: cotangents of b_x, b_y, face b; assembled dL/db
@@ -283,7 +285,7 @@ void free_bufs(esdg_ctx *c)
     B = Bufs{};
     {
         auto &A = c->adj;
-        void *qs[] = {A.gel, A.gw, A.gH, A.lam, A.gbf, A.ckpt, A.store, A.Hg, A.Tg, A.loss};
+        void *qs[] = {A.gel, A.gw, A.ug, A.gH, A.lam, A.gbf, A.ckpt, A.store, A.Hg, A.Tg, A.loss};
         for (void *p : qs)
             if (p) (void)hipFree(p);
         A = esdg_ctx::Adjoint{};
@@ -1438,35 +1440,47 @@ __global__ void fill_double_kernel(double *p, double v, int64_t n)
         p[k] = v;
 }
 
-// Water surface H = h + b interpolated at every gauge point.
-__global__ void gauge_kernel(const double *__restrict__ h, const double *__restrict__ b,
-                             const int32_t *__restrict__ gel, const double *__restrict__ gw, int ng, int np,
-                             double *__restrict__ out)
+constexpr int kGaugeThreads = 128;   // >= (N+1)^2 for every degree
+
+// Water surface H = h + b interpolated at every gauge point: workgroup g
+// reduces the weighted nodal values of gauge g.
+__global__ __launch_bounds__(kGaugeThreads) void gauge_kernel(const double *__restrict__ h,
+                                                              const double *__restrict__ b,
+                                                              const int32_t *__restrict__ gel,
+                                                              const double *__restrict__ gw, int np,
+                                                              double *__restrict__ out)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
+    __shared__ double s[kGaugeThreads];
+    const int g = blockIdx.x, p = threadIdx.x;
     const int64_t o = (int64_t)gel[g] * np;
-    double s = 0.0;
-    for (int p = 0; p < np; ++p) s += gw[(int64_t)g * np + p] * (h[o + p] + b[o + p]);
-    out[g] = s;
+    s[p] = p < np ? gw[(int64_t)g * np + p] * (h[o + p] + b[o + p]) : 0.0;
+    __syncthreads();
+    for (int st = kGaugeThreads / 2; st > 0; st >>= 1) {
+        if (p < st) s[p] += s[p + st];
+        __syncthreads();
+    }
+    if (p == 0) out[g] = s[0];
 }
 
 // Cotangent of one step's gauge misfit, w (H_g - T_g) l_g, added to dL/dh and
-// to dL/db at the nodes of the gauge's element.  One workgroup; lane p owns
-// node p of every gauge element, gauges in sequence (gauges may share an
-// element).
-__global__ void gauge_adjoint_kernel(const double *__restrict__ H, const double *__restrict__ Tg, double w,
-                                     const int32_t *__restrict__ gel, const double *__restrict__ gw, int ng, int np,
-                                     double *ah, double *gbn)
+// to dL/db at the nodes of the gauge's element.  Workgroup u takes the u-th
+// element holding gauges (gauges sorted by element: uorder[ustart[u] ..
+// ustart[u+1]) are its gauges, summed in that order), lane p its node p.
+__global__ __launch_bounds__(kGaugeThreads) void gauge_adjoint_kernel(
+    const double *__restrict__ H, const double *__restrict__ Tg, double w, const int32_t *__restrict__ uel,
+    const int32_t *__restrict__ ustart, const int32_t *__restrict__ uorder, const double *__restrict__ gw, int np,
+    double *ah, double *gbn)
 {
-    const int p = threadIdx.x;
+    const int u = blockIdx.x, p = threadIdx.x;
     if (p >= np) return;
-    for (int g = 0; g < ng; ++g) {
-        const double c = (H[g] - Tg[g]) * w * gw[(int64_t)g * np + p];
-        const int64_t q = (int64_t)gel[g] * np + p;
-        ah[q] += c;
-        gbn[q] += c;
+    double c = 0.0;
+    for (int k = ustart[u]; k < ustart[u + 1]; ++k) {
+        const int g = uorder[k];
+        c += (H[g] - Tg[g]) * w * gw[(int64_t)g * np + p];
     }
+    const int64_t q = (int64_t)uel[u] * np + p;
+    ah[q] += c;
+    gbn[q] += c;
 }
 
 // L = 1/2 dt sum (H - T)^2 over every step and gauge (one workgroup).
@@ -1581,8 +1595,8 @@ int gauge_values_into(esdg_ctx *ctx, int buf_or_neg, const double *state_h, doub
     auto &A = ctx->adj;
     const int np = (ctx->N + 1) * (ctx->N + 1);
     const double *h = state_h ? state_h : (const double *)ctx->B.W[buf_or_neg][0];
-    hipLaunchKernelGGL(gauge_kernel, dim3((unsigned)((A.ng + 63) / 64)), dim3(64), 0, ctx->stream, h,
-                       (const double *)ctx->B.b, A.gel, A.gw, A.ng, np, out);
+    hipLaunchKernelGGL(gauge_kernel, dim3((unsigned)A.ng), dim3(kGaugeThreads), 0, ctx->stream, h,
+                       (const double *)ctx->B.b, A.gel, A.gw, np, out);
     CK(hipGetLastError());
     return ESDG_OK;
 }
@@ -1621,18 +1635,35 @@ int esdg_set_gauges(esdg_ctx *ctx, int ng, const int32_t *elem, const double *xi
         for (int i = 0; i < nf; ++i)
             for (int j = 0; j < nf; ++j) gw[(size_t)g * np + i * nf + j] = (double)(lx[i] * le[j]);
     }
+    // gauges grouped by element (stable: gauge order inside an element)
+    std::vector<int32_t> order(ng);
+    for (int g = 0; g < ng; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return gel[a] < gel[c]; });
+    std::vector<int32_t> uel, ustart;
+    for (int k = 0; k < ng; ++k)
+        if (k == 0 || gel[order[k]] != gel[order[k - 1]]) {
+            uel.push_back(gel[order[k]]);
+            ustart.push_back(k);
+        }
+    ustart.push_back(ng);
+    const int nu = (int)uel.size();
+    std::vector<int32_t> ug(uel);
+    ug.insert(ug.end(), ustart.begin(), ustart.end());
+    ug.insert(ug.end(), order.begin(), order.end());
     auto &A = ctx->adj;
-    if (A.gel) CK(hipFree(A.gel));
-    if (A.gw) CK(hipFree(A.gw));
-    if (A.gH) CK(hipFree(A.gH));
-    A.gel = nullptr; A.gw = nullptr; A.gH = nullptr; A.ng = 0; A.ready = false;
+    for (void *p : {(void *)A.gel, (void *)A.gw, (void *)A.gH, (void *)A.ug})
+        if (p) CK(hipFree(p));
+    A.gel = nullptr; A.gw = nullptr; A.gH = nullptr; A.ug = nullptr; A.ng = 0; A.nu = 0; A.ready = false;
     TRY(alloc(ctx, &A.gel, ng * sizeof(int32_t)));
     TRY(alloc(ctx, &A.gw, gw.size() * sizeof(double)));
     TRY(alloc(ctx, &A.gH, ng * sizeof(double)));
+    TRY(alloc(ctx, &A.ug, ug.size() * sizeof(int32_t)));
     CK(hipMemcpyAsync(A.gel, gel.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     CK(hipMemcpyAsync(A.gw, gw.data(), gw.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(A.ug, ug.data(), ug.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     A.ng = ng;
+    A.nu = nu;
     return ESDG_OK;
 }
 
@@ -1771,8 +1802,9 @@ int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, d
             }
         // reverse the steps of the segment
         for (int it = s1 - 1; it >= s0; --it) {
-            hipLaunchKernelGGL(gauge_adjoint_kernel, dim3(1), dim3(128), 0, ctx->stream, A.Hg + (int64_t)it * A.ng,
-                               A.Tg + (int64_t)it * A.ng, seed * A.dt, A.gel, A.gw, A.ng, np, lamA[pa], gbn);
+            hipLaunchKernelGGL(gauge_adjoint_kernel, dim3((unsigned)A.nu), dim3(kGaugeThreads), 0, ctx->stream,
+                               A.Hg + (int64_t)it * A.ng, A.Tg + (int64_t)it * A.ng, seed * A.dt, A.ug,
+                               A.ug + A.nu, A.ug + 2 * A.nu + 1, A.gw, np, lamA[pa], gbn);
             CK(hipGetLastError());
             for (int k = 4; k >= 0; --k) {
                 const int64_t sl = (int64_t)(it - s0) * 5 + k;
