@@ -152,6 +152,18 @@ def ensemble_bench(esdg, dev, members, steps: int):
                 speedup=t_seq / t_ens, stage_variant={str(k): v for k, v in tuned.items()})
 
 
+def adjoint_stage_bytes(N: int, K: int) -> float:
+    """Algorithmic bytes of one reverse-stage launch, averaged over the five
+    stages of a step: per node reads W, dL/dW, the register cotangent (not on a
+    step's last stage), the metric directions, b_x, b_y and the three
+    bathymetry cotangents; writes dL/dW, the register cotangent (not on the
+    first stage) and the three bathymetry cotangents; per element the face
+    bathymetry."""
+    npn = (N + 1) ** 2
+    per_node = (3 + 3 + 0.8 * 3 + 4 + 2 + 3) + (3 + 0.8 * 3 + 3)
+    return 8.0 * (K * npn * per_node + K * 4 * (N + 1))
+
+
 def adjoint_bench(esdg, dev, stream, steps: int = 400, every: int = 20):
     """Bathymetry-gradient workload (128 x 128 elements, N = 5, 32 gauges):
     gauge-misfit loss over `steps` fixed LSRK(5,4) steps against a target run
@@ -194,6 +206,18 @@ def adjoint_bench(esdg, dev, stream, steps: int = 400, every: int = 20):
     s.set_state(w.h, w.hu, w.hv)
     loss, t_fwd = timed(lambda: s.adjoint_forward(steps, dt, every, tgt))
     g, t_bwd = timed(lambda: s.adjoint_backward(device=True))
+    # the reverse stage kernel alone, timed by events its dispatch records
+    s.set_state(w.h, w.hu, w.hv)
+    s.adjoint_forward(steps, dt, every, tgt)
+    s.profile(True)
+    s.profile_read_adjoint()
+    s.adjoint_backward(device=True)
+    kp = s.profile_read_adjoint()
+    s.profile(False)
+    K = w.mesh.K
+    adj_bytes = adjoint_stage_bytes(N, K)
+    adj_mean_ms = kp["ms"] / max(kp["launches"], 1)
+    adj_GBs = adj_bytes / (adj_mean_ms * 1e-3) / 1e9
     gb, gh0 = g[0].cpu().numpy(), g[1].cpu().numpy()
     gtot = gb - gh0
     # gradient on the continuous periodic nodes: sum over coincident DG nodes
@@ -211,7 +235,11 @@ def adjoint_bench(esdg, dev, stream, steps: int = 400, every: int = 20):
                 backward_value=nodes * 5 * steps / t_bwd,
                 gradient_values=int(gtot.size), continuous_nodes=int(lat.size),
                 gradient_norm=float(np.linalg.norm(gtot)), continuous_gradient_norm=float(np.linalg.norm(lat)),
-                checkpoint_bytes=((steps + every - 1) // every) * n, segment_bytes=(every * 5 + 1) * n)
+                checkpoint_bytes=((steps + every - 1) // every) * n, segment_bytes=(every * 5 + 1) * n,
+                roofline={"bound": "hbm", "kernel": "adjoint_stage_kernel", "achieved": adj_GBs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": adj_GBs / HBM_PEAK_GBS,
+                          "bytes_per_launch": adj_bytes, "mean_launch_ms": adj_mean_ms,
+                          "launches": kp["launches"], "traffic": None})
 
 
 def cpu_baseline(N: int, n_patch: int):

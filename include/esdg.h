@@ -187,6 +187,10 @@ int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, dou
 int esdg_profile(esdg_ctx *ctx, int enable);
 int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_launches,
                       double *av_ms, int64_t *av_launches);
+/* The same for the reverse stage kernel of esdg_rhs_vjp and
+ * esdg_adjoint_backward: summed milliseconds and launches since the last
+ * read, then reset. */
+int esdg_profile_read_adjoint(esdg_ctx *ctx, double *ms, int64_t *launches);
 
 /*
  * Autotuner of the stage kernel's tile (elements per workgroup): every

@@ -156,8 +156,10 @@ struct esdg_ctx {
     int32_t *perm = nullptr;     // [K] caller's element of each internal element
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_stage, ev_av;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_stage, ev_av, ev_adj;
     size_t ev_next = 0;
+    double acc_ms[3] = {0, 0, 0};   // drained event times: stage, viscosity, adjoint stage
+    int64_t acc_n[3] = {0, 0, 0};
     std::string err = "no error";
     std::vector<int32_t> inv_h;   // caller's element -> internal element
     uint64_t b_version = 0;       // bumped by every esdg_set_bathymetry
@@ -1113,29 +1115,57 @@ int esdg_profile(esdg_ctx *ctx, int enable)
     return ESDG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Sum the recorded event pairs of every log into the accumulators; the
+// events return to the pool.
+int drain_events(esdg_ctx *ctx)
+{
+    CK(hipSetDevice(ctx->device));
+    CK(hipStreamSynchronize(ctx->stream));
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *logs[3] = {&ctx->ev_stage, &ctx->ev_av, &ctx->ev_adj};
+    for (int k = 0; k < 3; ++k) {
+        for (auto &pr : *logs[k]) {
+            float ms = 0;
+            CK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            ctx->acc_ms[k] += ms;
+        }
+        ctx->acc_n[k] += (int64_t)logs[k]->size();
+        logs[k]->clear();
+    }
+    ctx->ev_next = 0;
+    return ESDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_n, double *av_ms, int64_t *av_n)
 {
     if (!ctx) return ESDG_EINVAL;
-    CK(hipSetDevice(ctx->device));
-    CK(hipStreamSynchronize(ctx->stream));
-    double s = 0, a = 0;
-    for (auto &pr : ctx->ev_stage) {
-        float ms = 0;
-        CK(hipEventElapsedTime(&ms, pr.first, pr.second));
-        s += ms;
+    TRY(drain_events(ctx));
+    if (stage_ms) *stage_ms = ctx->acc_ms[0];
+    if (stage_n) *stage_n = ctx->acc_n[0];
+    if (av_ms) *av_ms = ctx->acc_ms[1];
+    if (av_n) *av_n = ctx->acc_n[1];
+    for (int k = 0; k < 2; ++k) {
+        ctx->acc_ms[k] = 0;
+        ctx->acc_n[k] = 0;
     }
-    for (auto &pr : ctx->ev_av) {
-        float ms = 0;
-        CK(hipEventElapsedTime(&ms, pr.first, pr.second));
-        a += ms;
-    }
-    if (stage_ms) *stage_ms = s;
-    if (stage_n) *stage_n = (int64_t)ctx->ev_stage.size();
-    if (av_ms) *av_ms = a;
-    if (av_n) *av_n = (int64_t)ctx->ev_av.size();
-    ctx->ev_stage.clear();
-    ctx->ev_av.clear();
-    ctx->ev_next = 0;
+    return ESDG_OK;
+}
+
+int esdg_profile_read_adjoint(esdg_ctx *ctx, double *ms, int64_t *n)
+{
+    if (!ctx) return ESDG_EINVAL;
+    TRY(drain_events(ctx));
+    if (ms) *ms = ctx->acc_ms[2];
+    if (n) *n = ctx->acc_n[2];
+    ctx->acc_ms[2] = 0;
+    ctx->acc_n[2] = 0;
     return ESDG_OK;
 }
 
@@ -1573,11 +1603,12 @@ int adj_forward_stage(esdg_ctx *ctx, double *in, double *out, int k)
 
 int adj_stage(esdg_ctx *ctx, const AdjCall &c)
 {
-    CK(dispatch(ctx, [&](auto L, auto r) {
-        using R = decltype(r);
-        return decltype(L)::adjoint_stage(ctx->B, c, phys<R>(ctx), tab<R>(ctx), ctx->stream, Ev{});
-    }));
-    return ESDG_OK;
+    return timed(ctx, ctx->ev_adj, [&](Ev ev) {
+        return dispatch(ctx, [&](auto L, auto r) {
+            using R = decltype(r);
+            return decltype(L)::adjoint_stage(ctx->B, c, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
+        });
+    });
 }
 
 int adj_assemble_b(esdg_ctx *ctx)

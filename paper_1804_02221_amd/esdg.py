@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
             "esdg_gauge_values": ([P, P, I], I),
             "esdg_adjoint_forward": ([P, I, D, I, P, I, P, P], I),
             "esdg_adjoint_backward": ([P, D, P, P, P, P, I], I),
+            "esdg_profile_read_adjoint": ([P, P, P], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -330,6 +331,11 @@ class Solver:
         sm, sn, am, an = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
         self._check(lib().esdg_profile_read(self._ctx, C.byref(sm), C.byref(sn), C.byref(am), C.byref(an)))
         return dict(stage_ms=sm.value, stage_launches=sn.value, av_ms=am.value, av_launches=an.value)
+
+    def profile_read_adjoint(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(lib().esdg_profile_read_adjoint(self._ctx, C.byref(ms), C.byref(n)))
+        return dict(ms=ms.value, launches=n.value)
 
 
     # -- discrete adjoint -------------------------------------------------
