@@ -59,15 +59,18 @@ def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_v
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic_N7_512x512_fp64.txt")
 
 
+# the sources that define the stage kernel and its launch
+STAGE_SOURCES = ("esdg_inst.hip", "esdg_kernels.hpp", "esdg_launch.hpp", "esdg_tables.hpp")
+
+
 def kernel_source_hash() -> str:
     import hashlib
     src = os.path.join(ROOT, "paper_1804_02221_amd", "csrc")
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(src)):
-        if fn.endswith((".hpp", ".hip")):
-            h.update(fn.encode())
-            with open(os.path.join(src, fn), "rb") as f:
-                h.update(f.read())
+    for fn in STAGE_SOURCES:
+        h.update(fn.encode())
+        with open(os.path.join(src, fn), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
