@@ -17,7 +17,8 @@
  * j <-> eta.  Local sides 0..3 are the paper's s=1..4: eta=-1, xi=+1,
  * eta=+1, xi=-1.  Face node k runs along increasing xi (sides 0,2) or eta
  * (sides 1,3).  nbr_elem/nbr_side/flip give the element and side sharing
- * each side; flip=1 reverses the neighbour's face-node order.
+ * each side; flip=1 reverses the neighbour's face-node order; nbr_elem = -1
+ * marks a solid wall.
  *
  * Parity status of each part is listed in the test suite; functions whose
  * result no property of the paper fixes say so below ("parity unpinned").
@@ -299,10 +300,23 @@ static void scaled_normal(const orc_geom *G, int s, int64_t q, double *nx, doubl
     }
 }
 
-/* The neighbour node matched to face node k of side s of element e. */
+/* Is side s of element e a solid wall (no neighbour)? */
+static int is_wall(const orc_mesh *m, int64_t e, int s)
+{
+    return m->nbr_elem[e * 4 + s] < 0;
+}
+
+/* The neighbour node matched to face node k of side s of element e; at a
+ * wall, the element's own face node (its trace is then mirrored where the
+ * flux needs the outside state). */
 static int64_t nbr_node(const orc_mesh *m, int64_t e, int s, int k)
 {
     int N = m->N, n1 = N + 1, np = n1 * n1;
+    if (is_wall(m, e, s)) {
+        int i, j;
+        side_node(N, s, k, &i, &j);
+        return e * np + i * n1 + j;
+    }
     int64_t en = m->nbr_elem[e * 4 + s];
     int sn = m->nbr_side[e * 4 + s];
     int kk = m->flip[e * 4 + s] ? N - k : k;
@@ -318,6 +332,18 @@ static int64_t nbr_node(const orc_mesh *m, int64_t e, int s, int k)
 static double velocity(double hq, double h, double h_tol)
 {
     return (h > h_tol) ? hq / h : 0.0;
+}
+
+/* Outside state of a solid wall with unit outward normal n: the same water
+ * height and the discharge with its normal component reversed (reading: the
+ * usual reflecting wall; the interface flux then carries no mass through the
+ * wall and, for the EC flux, no entropy). */
+static void wall_state(const double *wm, double nx, double ny, double *wp)
+{
+    double dn = wm[1] * nx + wm[2] * ny;
+    wp[0] = wm[0];
+    wp[1] = wm[1] - 2.0 * dn * nx;
+    wp[2] = wm[2] - 2.0 * dn * ny;
 }
 
 /* Entropy-conservative two-point volume fluxes F#, G# (eq. volumeFluxes). */
@@ -496,7 +522,8 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
         for (int64_t e = 0; e < K; ++e) {
             if (need && !need[e]) continue;
             needv[e] = 1;
-            for (int s = 0; s < 4; ++s) needv[m->nbr_elem[e * 4 + s]] = 1;
+            for (int s = 0; s < 4; ++s)
+                if (!is_wall(m, e, s)) needv[m->nbr_elem[e * 4 + s]] = 1;
         }
         /* viscosity per element from the stage state (appendix A) */
         for (int64_t e = 0; e < K; ++e)
@@ -608,6 +635,7 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
                 scaled_normal(G, s, q, &snx, &sny);
                 double Js = sqrt(snx * snx + sny * sny);   /* eq. SurfJac */
                 double wm[3] = {h[q], hu[q], hv[q]}, wp[3] = {h[qn], hu[qn], hv[qn]};
+                if (is_wall(m, e, s)) wall_state(wm, snx / Js, sny / Js, wp);
                 double Fn[3];
                 orc_surface_flux(P, wm, b[q], wp, b[qn], snx / Js, sny / Js, Fn);
                 for (int c = 0; c < 3; ++c) {
@@ -717,7 +745,8 @@ static int check_mesh(const orc_mesh *m)
         for (int s = 0; s < 4; ++s) {
             int32_t en = m->nbr_elem[e * 4 + s];
             int sn = m->nbr_side[e * 4 + s];
-            if (en < 0 || en >= m->K || sn < 0 || sn > 3) return ORC_EINVAL;
+            if (en < 0) continue;                               /* solid wall */
+            if (en >= m->K || sn < 0 || sn > 3) return ORC_EINVAL;
         }
     return ORC_OK;
 }
@@ -860,6 +889,7 @@ static void dt_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
                 double hm = h[q], hp = h[qn];
                 double utm = nx * velocity(hu[q], hm, htol) + ny * velocity(hv[q], hm, htol);
                 double utp = nx * velocity(hu[qn], hp, htol) + ny * velocity(hv[qn], hp, htol);
+                if (is_wall(m, e, s)) utp = -utm;        /* the wall's mirror state */
                 double cm = sqrt(g * fmax(hm, 0.0)), cp = sqrt(g * fmax(hp, 0.0));
                 double au = 0.5 * (utm + utp), ac = 0.5 * (cm + cp);
                 double A = fabs(au + ac) + fabs(au - ac);
@@ -1298,13 +1328,21 @@ static int rhs_vjp_acc(const orc_params *P, const orc_ops *op, const orc_mesh *m
 }
 
 /* (dR/dW)^T lam and (dR/db)^T lam of the inviscid right-hand side at (W, b). */
+/* The adjoint covers closed periodic meshes (no walls). */
+static int has_walls(const orc_mesh *m)
+{
+    for (int64_t f = 0; f < 4 * m->K; ++f)
+        if (m->nbr_elem[f] < 0) return 1;
+    return 0;
+}
+
 int orc_rhs_vjp(const orc_params *P, const orc_mesh *m, const double *b, const double *h,
                 const double *hu, const double *hv, const double *lh, const double *lhu,
                 const double *lhv, double *gh, double *ghu, double *ghv, double *gb)
 {
     int st = check_mesh(m);
     if (st) return st;
-    if (P->av_on) return ORC_EINVAL;
+    if (P->av_on || has_walls(m)) return ORC_EINVAL;
     orc_ops op;
     build_ops(m->N, &op);
     orc_geom G;
@@ -1340,7 +1378,8 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
 {
     int st = check_mesh(m);
     if (st) return st;
-    if (P->av_on || P->integrator != 0 || nsteps < 1 || ng < 0 || !(dt > 0.0)) return ORC_EINVAL;
+    if (P->av_on || P->integrator != 0 || nsteps < 1 || ng < 0 || !(dt > 0.0) || has_walls(m))
+        return ORC_EINVAL;
     const int N = m->N, n1 = N + 1, np = n1 * n1;
     for (int gg = 0; gg < ng; ++gg)
         if (gelem[gg] < 0 || gelem[gg] >= m->K) return ORC_EINVAL;

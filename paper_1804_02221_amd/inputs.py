@@ -210,6 +210,34 @@ def make_periodic_mesh(N: int, nx: int, ny: int, Lx: float, Ly: float,
                         lat_x=lat_x, lat_y=lat_y)
 
 
+def make_box_mesh(N: int, nx: int, ny: int, x0: float, y0: float, Lx: float, Ly: float,
+                  amp: float = 0.0, walls_x: bool = True, walls_y: bool = True,
+                  rotate_seed: int | None = None) -> PeriodicMesh:
+    """Mesh of [x0, x0+Lx] x [y0, y0+Ly] with solid walls (nbr_elem = -1) on the
+    sides x = const (walls_x) and/or y = const (walls_y), periodic in the
+    other direction: the periodic mesh with the faces across the seams cut.
+    The sin perturbation vanishes on the boundary, so walls are straight.
+    Fields on such a mesh are evaluated at the nodal coordinates (x, y), not
+    through the periodic lattice."""
+    if nx < 3 or ny < 3:
+        raise ValueError("box mesh needs nx, ny >= 3")
+    m = make_periodic_mesh(N, nx, ny, Lx, Ly, amp=amp, rotate_seed=rotate_seed)
+    cx, cy = m.element_centroid_ref()
+    ne = m.nbr_elem.copy()
+    for s in range(4):
+        nb = ne[:, s]
+        cut = np.zeros(m.K, dtype=bool)
+        if walls_x:
+            cut |= np.abs(cx[nb] - cx) > 0.5 * Lx
+        if walls_y:
+            cut |= np.abs(cy[nb] - cy) > 0.5 * Ly
+        ne[cut, s] = -1
+    m.nbr_elem = np.ascontiguousarray(ne)
+    m.x = np.ascontiguousarray(m.x + x0)
+    m.y = np.ascontiguousarray(m.y + y0)
+    return m
+
+
 # --------------------------------------------------------------------------
 # Fields
 # --------------------------------------------------------------------------
@@ -374,6 +402,35 @@ def bathymetry_gradient(n: int = 128, N: int = 5, seed: int = 4, target_seed: in
     w = Workload(f"bathymetry_gradient_{n}x{n}_N{N}", mesh, _c(b), _c(h), _c(z), _c(z.copy()),
                  dict(g=9.81, surface_flux=0, av_on=0, limiter_on=1, cfl=0.5))
     return w, dict(H0=_c(H0), db=_c(db), gelem=gelem, gxi=_c(gxi), geta=_c(geta))
+
+
+def oscillating_lake(n: int = 200, N: int = 3, t: float = 0.0, h0: float = 0.1, a: float = 1.0,
+                     sigma: float = 0.5, g: float = 9.81) -> Workload:
+    """The paper's oscillating lake: [-2,2]^2 with solid walls, n x n Cartesian
+    elements, parabolic bowl b = h0 (x^2+y^2)/a^2 and the planar oscillation
+    of its closed form at time t (omega = sqrt(2 g h0)/a): h = max(0, sigma
+    h0/a^2 (2x cos wt + 2y sin wt - sigma) + h0 - b), u = -sigma w sin wt,
+    v = sigma w cos wt (zero where dry); eps0 = 0.01, AV and limiter on."""
+    mesh = make_box_mesh(N, n, n, -2.0, -2.0, 4.0, 4.0)
+    x, y = mesh.x, mesh.y
+    w = np.sqrt(2.0 * g * h0) / a
+    b = h0 * (x * x + y * y) / (a * a)
+    h = np.maximum(0.0, sigma * h0 / (a * a) * (2 * x * np.cos(w * t) + 2 * y * np.sin(w * t) - sigma) + h0 - b)
+    u = np.where(h > 0, -sigma * w * np.sin(w * t), 0.0)
+    v = np.where(h > 0, sigma * w * np.cos(w * t), 0.0)
+    return Workload(f"oscillating_lake_{n}x{n}_N{N}", mesh, _c(b), _c(h), _c(h * u), _c(h * v),
+                    dict(g=g, surface_flux=0, av_on=1, limiter_on=1, eps0=0.01, cfl=0.5))
+
+
+def dry_dam_break(n: int = 50, N: int = 3) -> Workload:
+    """The paper's dry dam break: [-20,20]^2, n x n Cartesian elements, solid
+    walls at x = -20 and 20, periodic in y; h = 10 where x < 0, else dry;
+    at rest; flat bed; eps0 = 0.1, AV and limiter on."""
+    mesh = make_box_mesh(N, n, n, -20.0, -20.0, 40.0, 40.0, walls_x=True, walls_y=False)
+    h = np.where(mesh.x < 0.0, 10.0, 0.0)
+    z = np.zeros_like(h)
+    return Workload(f"dry_dam_break_{n}x{n}_N{N}", mesh, _c(z.copy()), _c(h), _c(z.copy()), _c(z.copy()),
+                    dict(g=9.81, surface_flux=0, av_on=1, limiter_on=1, eps0=0.1, cfl=0.5))
 
 
 def random_states(rng: np.random.Generator, n: int, dry_fraction: float = 0.0,
