@@ -29,7 +29,11 @@
  *  - Face map: nbr_elem[e*4+s], nbr_side[e*4+s] name the element and local
  *    side sharing side s of element e; flip[e*4+s] = 1 when the neighbour's
  *    face-node order is reversed (its node N-k meets node k).  The mesh must
- *    be conforming and closed (periodic); every side has a neighbour.
+ *    be conforming.  nbr_elem[e*4+s] = -1 makes side s a solid (reflecting)
+ *    wall: the interface flux takes as outside state the element's own trace
+ *    with the normal velocity reversed (the same height and bathymetry), the
+ *    artificial viscosity sees no jump there (U* = u, F^{v,*} = F^v), and the
+ *    Lemma 2 bound uses the same mirror state (nbr_side/flip are ignored).
  *  - mem = 0: the pointer is host memory; mem = 1: device memory of the
  *    context's GPU (e.g. a torch tensor's data_ptr()).  The library copies
  *    in and out and never keeps a caller pointer.  Device-pointer transfers
@@ -263,7 +267,8 @@ const char *esdg_ensemble_last_error(const esdg_ensemble *en);
  * eqs. fluxDiffFormF, Fmij and volumeFluxes, interface flux of appendix B,
  * source of eq. SourceDisc) and of LSRK(5,4) steps, for gradients with
  * respect to the nodal bathymetry.  The artificial viscosity is frozen at
- * zero (av_on must be 0: ESDG_EINVAL otherwise).  The limiter must not act:
+ * zero (av_on must be 0: ESDG_EINVAL otherwise) and the mesh has no walls
+ * (ESDG_EINVAL otherwise).  The limiter must not act:
  * on a wet state (h >= h_tol everywhere, so theta = 1 and no velocity is cut
  * off) it is the identity and so is its derivative.  |x| is differentiated
  * as sign(x) with sign(0) = 0.

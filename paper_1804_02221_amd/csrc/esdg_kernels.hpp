@@ -121,7 +121,7 @@ struct Mesh {
     const R *bx, *by;   // split-form bathymetry derivatives (eq. SourceDisc)
     const R *bface;     // bathymetry on the faces [K][4][nf]
     const int32_t *nbr; // [K][4] neighbour element
-    const int8_t *code; // [K][4] neighbour side | flip << 2
+    const int8_t *code; // [K][4] neighbour side | flip << 2 | wall << 3 (a wall names the element itself)
 };
 
 template <typename R>
@@ -133,7 +133,9 @@ struct Phys {
     int ec, limiter_on;
 };
 
-// Neighbour node of face node (s, k) of element e.
+// Neighbour node of face node (s, k) of element e.  At a solid wall the face
+// map names the element's own side (the node itself): the interface flux then
+// mirrors the velocity (is_wall), the viscous terms see no jump.
 template <int N, typename R>
 __device__ __forceinline__ int64_t nbr_node(const Mesh<R> &m, int64_t e, int s, int k,
                                            int64_t &en, int &ns, int &kk)
@@ -142,10 +144,26 @@ __device__ __forceinline__ int64_t nbr_node(const Mesh<R> &m, int64_t e, int s, 
     en = m.nbr[e * 4 + s];
     const int c = m.code[e * 4 + s];
     ns = c & 3;
-    kk = (c >> 2) ? N - k : k;
+    kk = ((c >> 2) & 1) ? N - k : k;
     int i, j;
     side_node<N>(ns, kk, i, j);
     return en * np + i * nf + j;
+}
+
+template <typename R>
+__device__ __forceinline__ bool is_wall(const Mesh<R> &m, int64_t e, int s)
+{
+    return (m.code[e * 4 + s] >> 3) & 1;
+}
+
+// Reflecting-wall outside state: the velocity with its normal component
+// reversed about the unit normal (nx, ny); height and bathymetry unchanged.
+template <typename R>
+__device__ __forceinline__ void wall_mirror(R nx, R ny, R &u, R &v)
+{
+    const R dn = u * nx + v * ny;
+    u -= R(2) * dn * nx;
+    v -= R(2) * dn * ny;
 }
 
 // 1/x from the hardware reciprocal estimate refined by two Newton-Raphson
@@ -922,6 +940,7 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             }
             const R bo = a.m.bface[(fe * 4 + s) * nf + k];
             const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
+            if (is_wall(a.m, fe, s)) wall_mirror(snx * ijs, sny * ijs, un, vn);
             R F0, F1, F2;
             const V2 wl = s_w[lp];
             interface_flux<R>(s_h[lp], wl.x, wl.y, bo, hn, un, vn, bn, snx * ijs, sny * ijs, P, F0,
@@ -1253,7 +1272,7 @@ __device__ __forceinline__ R lemma2_bound(const DtArgs<R> &a, int64_t f)
     const R hm = a.h[qo], hp = a.h[qn];
     const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
     const R utm = nx * (a.hu[qo] * im) + ny * (a.hv[qo] * im);
-    const R utp = nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
+    const R utp = is_wall(a.m, fe, s) ? -utm : nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
     const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
     const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
     const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);

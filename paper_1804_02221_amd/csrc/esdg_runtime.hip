@@ -162,6 +162,7 @@ struct esdg_ctx {
     int64_t acc_n[3] = {0, 0, 0};
     std::string err = "no error";
     std::vector<int32_t> inv_h;   // caller's element -> internal element
+    bool has_walls = false;       // some side is a solid wall
     uint64_t b_version = 0;       // bumped by every esdg_set_bathymetry
     // discrete adjoint (gauges, checkpoints, cotangent fields)
     struct Adjoint {
@@ -647,6 +648,11 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         for (int s = 0; s < 4; ++s) {
             const int64_t f = e * 4 + s;
             const int32_t en = ne[f];
+            if (en == -1) {
+                // solid wall: internally the side names itself, flagged
+                code[f] = (int8_t)(s | (1 << 3));
+                continue;
+            }
             const int sn = ns[f], fv = fl[f];
             if (en < 0 || en >= K || sn < 0 || sn > 3 || (fv != 0 && fv != 1))
                 return fail(ctx, ESDG_EMESH, "face map entry (%lld,%d) out of range", (long long)e, s);
@@ -682,7 +688,7 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         for (int64_t e = off[k]; e < off[k + 1]; ++e) inst_of[e] = k;
     }
     for (int64_t f = 0; f < 4 * K; ++f)
-        if (inst_of[ne[f]] != inst_of[f / 4])
+        if (ne[f] >= 0 && inst_of[ne[f]] != inst_of[f / 4])
             return fail(ctx, ESDG_EMESH, "face map connects two instances at element %lld", (long long)(f / 4));
     // locality order inside each instance (instances stay contiguous)
     std::vector<int32_t> perm(K), inv(K);
@@ -693,11 +699,15 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     std::vector<int8_t> code2(4 * K);
     for (int64_t e = 0; e < K; ++e)
         for (int s = 0; s < 4; ++s) {
-            ne2[e * 4 + s] = inv[ne[(int64_t)perm[e] * 4 + s]];
+            const int32_t en = ne[(int64_t)perm[e] * 4 + s];
+            ne2[e * 4 + s] = en >= 0 ? inv[en] : (int32_t)e;
             code2[e * 4 + s] = code[(int64_t)perm[e] * 4 + s];
         }
+    bool walls = false;
+    for (int64_t f = 0; f < 4 * K; ++f) walls = walls || ne[f] < 0;
     free_bufs(ctx);
     ctx->inv_h = inv;
+    ctx->has_walls = walls;
     ctx->N = N;
     ctx->K = K;
     build_tables(N, ctx->ht);
@@ -1268,7 +1278,7 @@ int ensemble_build(esdg_ensemble *en)
             std::copy(I.hu.begin(), I.hu.end(), hu.begin() + o * npn);
             std::copy(I.hv.begin(), I.hv.end(), hv.begin() + o * npn);
             for (int64_t f = 0; f < 4 * I.K; ++f) {
-                ne[4 * o + f] = (int32_t)(I.ne[f] + o);
+                ne[4 * o + f] = I.ne[f] >= 0 ? (int32_t)(I.ne[f] + o) : -1;   // walls stay walls
                 ns[4 * o + f] = I.ns[f];
                 fl[4 * o + f] = I.fl[f];
             }
@@ -1336,7 +1346,7 @@ int esdg_ensemble_add(esdg_ensemble *en, const esdg_params *p, int N, int64_t K,
     if (N < 2 || N > kMaxN || K < 1) return efail(en, ESDG_EINVAL, "N or K out of range");
     if (p->max_dt_retries > 0) return efail(en, ESDG_EINVAL, "dt retries need a single instance");
     for (int64_t f = 0; f < 4 * K; ++f)
-        if (nbr_elem[f] < 0 || nbr_elem[f] >= K) return efail(en, ESDG_EMESH, "face map entry out of range");
+        if (nbr_elem[f] < -1 || nbr_elem[f] >= K) return efail(en, ESDG_EMESH, "face map entry out of range");
     esdg_ensemble::Inst I;
     I.P = *p;
     I.N = N;
@@ -1548,6 +1558,7 @@ bool check_adjoint_ctx(esdg_ctx *ctx)
     if (ctx->prec != 64) return fail(ctx, ESDG_EINVAL, "the adjoint needs a float64 context"), false;
     if (ctx->P.av_on) return fail(ctx, ESDG_EINVAL, "the adjoint covers the inviscid operator (av_on = 0)"), false;
     if (n_inst(ctx) != 1) return fail(ctx, ESDG_EINVAL, "the adjoint runs on single-instance contexts"), false;
+    if (ctx->has_walls) return fail(ctx, ESDG_EINVAL, "the adjoint covers meshes without walls"), false;
     return true;
 }
 
