@@ -28,6 +28,7 @@ static Mesh<R> mesh_view(const Bufs &B)
     m.bface = (const R *)B.bface;
     m.nbr = B.nbr;
     m.code = B.code;
+    m.walls = B.walls;
     return m;
 }
 

@@ -122,6 +122,7 @@ struct Mesh {
     const R *bface;     // bathymetry on the faces [K][4][nf]
     const int32_t *nbr; // [K][4] neighbour element
     const int8_t *code; // [K][4] neighbour side | flip << 2 | wall << 3 (a wall names the element itself)
+    int walls;          // some side is a wall (else the wall bit is never looked at)
 };
 
 template <typename R>
@@ -153,7 +154,7 @@ __device__ __forceinline__ int64_t nbr_node(const Mesh<R> &m, int64_t e, int s, 
 template <typename R>
 __device__ __forceinline__ bool is_wall(const Mesh<R> &m, int64_t e, int s)
 {
-    return (m.code[e * 4 + s] >> 3) & 1;
+    return m.walls && ((m.code[e * 4 + s] >> 3) & 1);
 }
 
 // Reflecting-wall outside state: the velocity with its normal component

@@ -18,6 +18,7 @@ struct Bufs {
     void *bx = nullptr, *by = nullptr, *bface = nullptr, *b = nullptr;
     int32_t *nbr = nullptr;
     int8_t *code = nullptr;
+    int walls = 0;           // some side of the mesh is a solid wall
     void *W[3][3] = {};      // state buffers [buffer][h, hu, hv]: W^n and the two stage outputs
     void *dU[3] = {};        // LSRK register
     void *Rb[3] = {};        // right-hand side output scratch

@@ -708,6 +708,7 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     free_bufs(ctx);
     ctx->inv_h = inv;
     ctx->has_walls = walls;
+    ctx->B.walls = walls ? 1 : 0;
     ctx->N = N;
     ctx->K = K;
     build_tables(N, ctx->ht);
