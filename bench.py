@@ -245,6 +245,51 @@ def adjoint_bench(esdg, dev, stream, steps: int = 400, every: int = 20):
                           "launches": kp["launches"], "traffic": None})
 
 
+def paper_cases_bench(esdg, dev, stream):
+    """The paper's walled test cases at their own resolutions, SSPRK(3,3) with
+    the adaptive step: the oscillating lake (200x200, N=3) to T/6 with its
+    error against the closed form, and the dry dam break (50x50, N=3) to t=1
+    with its mass drift and entropy change."""
+    import torch
+    from paper_1804_02221_amd.inputs import dry_dam_break, oscillating_lake
+    out = {}
+    g = 9.81
+    for name, w, t_end in (("oscillating_lake", oscillating_lake(200, 3), 2 * np.pi / np.sqrt(2 * g * 0.1) / 6),
+                           ("dry_dam_break", dry_dam_break(50, 3), 1.0)):
+        s = esdg.Solver(dev, 64, stream=stream)
+        s.upload_mesh(w.mesh)
+        s.set_params(esdg.default_params(3, **w.params))
+        s.set_bathymetry(w.b)
+        s.set_state(w.h, w.hu, w.hv)
+        d0 = s.diagnostics()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, n = 0.0, 0
+        while t < t_end - 1e-12:
+            dt = min(s.compute_dt()[0], t_end - t)
+            t, _ = s.step(1, dt)
+            n += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d = s.diagnostics()
+        nodes = w.mesh.K * 16
+        r = dict(elements=w.mesh.K, nodes=nodes, t_end=t_end, steps=n, ms_per_step=el * 1e3 / n,
+                 value=nodes * 3 * n / el, mass_drift=(d[0] - d0[0]) / d0[0], entropy_change=(d[3] - d0[3]) / d0[3],
+                 min_h=d[5])
+        if name == "oscillating_lake":
+            h = s.get_state()[0]
+            ex = oscillating_lake(200, 3, t=t_end)
+            geo = s.get_geometry()
+            w1 = np.array([1 / 6, 5 / 6, 5 / 6, 1 / 6])   # LGL weights, N = 3
+            wq = geo["J"] * np.outer(w1, w1).reshape(-1)[None, :]
+            r["relative_L1_error"] = float(np.sum(wq * np.abs(h - ex.h)) / np.sum(wq * ex.h))
+        s.close()
+        out[name] = r
+    out["note"] = ("wall-clock per step includes the host loop (one esdg_step and one esdg_compute_dt per step, "
+                   "the step clipped to reach t_end); value = nodes x 3 stages x steps / elapsed")
+    return out
+
+
 def cpu_baseline(N: int, n_patch: int):
     import oracle
     from paper_1804_02221_amd.inputs import smooth_sweep
@@ -281,6 +326,8 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=5)
     ap.add_argument("--adjoint", type=int, default=1,
                     help="time the bathymetry-gradient adjoint (128^2 elements, N=5, 400 steps)")
+    ap.add_argument("--paper-cases", type=int, default=1,
+                    help="run the walled test cases (oscillating lake, dry dam break) at their resolutions")
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick the stage-kernel workgroup size per run with the library's autotuner")
     args = ap.parse_args()
@@ -401,6 +448,11 @@ def main():
         adj = adjoint_bench(esdg, dev, stream)
         log(f"adjoint: backward / plain forward = {adj['adjoint_forward_ratio']:.2f}")
 
+    cases = None
+    if args.paper_cases:
+        log("walled test cases")
+        cases = paper_cases_bench(esdg, dev, stream)
+
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         log(f"CPU oracle baseline on a {args.cpu_patch}^2 patch")
@@ -450,6 +502,8 @@ def main():
         out["ensemble"] = ens
     if adj:
         out["adjoint"] = adj
+    if cases:
+        out["paper_cases"] = cases
     print(json.dumps(out), flush=True)
 
 
