@@ -23,9 +23,10 @@
 //    equals that of node a's row with respect to its first argument; node a
 //    contracts that derivative with D~_ab mu_a + D~_ba mu_b (mu = -l/J);
 //  * interface: a face node takes the derivative of its own face term with
-//    respect to its own ('-') trace and of the neighbour's face term (the
-//    neighbour's normal, surface Jacobian and cotangent) with respect to the
-//    neighbour's '+' trace, which is this node.
+//    respect to its own ('-') trace and of the neighbour's face term with
+//    respect to the neighbour's '+' trace, which is this node; since the
+//    interface flux is conservative, F*(W+, W-, -n) = -F*(W-, W+, n), both
+//    are one reverse evaluation of the own term's flux.
 // The derivative of |x| is taken as sign(x) with sign(0) = 0; velocities
 // below the dry cut-off are constants (zero derivative).
 #pragma once
@@ -187,31 +188,30 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
             const R snx = sg * dir.x, sny = sg * dir.y;
             const R js = sqrt(snx * snx + sny * sny);
-            // neighbour's trace, outward normal, surface Jacobian and cotangent
+            // neighbour's trace and cotangent mu_n = -l_n / J_n
             const R hn = a.h[qn];
             const R inn = rcp_wet(hn, P.h_tol);
             const R un = a.hu[qn] * inn, vn = a.hv[qn] * inn;
-            const R nAx = a.m.Ax[qn], nCx = a.m.Cx[qn], nAe = a.m.Ae[qn], nCe = a.m.Ce[qn];
-            const R nsg = (ns == 0 || ns == 3) ? R(-1) : R(1);
-            const R nnx = nsg * ((ns & 1) ? nAx : nAe), nny = nsg * ((ns & 1) ? nCx : nCe);
-            const R jsn = sqrt(nnx * nnx + nny * nny);
-            const R nJ = nCe * nAx - nCx * nAe;
+            const R nJ = a.m.Ce[qn] * a.m.Ax[qn] - a.m.Cx[qn] * a.m.Ae[qn];
             R nl0 = 0, nl1 = 0, nl2 = 0;
             if (a.c[0]) { nl0 = a.c[0][qn]; nl1 = a.c[1][qn]; nl2 = a.c[2][qn]; }
             if (a.a[0]) { nl0 += a.cb * a.a[0][qn]; nl1 += a.cb * a.a[1][qn]; nl2 += a.cb * a.a[2][qn]; }
+            const R inJ = R(1) / nJ;
             const R bo = a.m.bface[(fe * 4 + s) * nf + k];
             const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
             const R ho = s_h[lp];
             const double2 wo = s_w[lp];
-            // L_p += (J^surf / w_0) F*(own, nbr, n): cotangent (J^surf / w_0) mu
+            // Own term (J^surf / w_0) mu . F*(own, nbr, n) and the neighbour's
+            // (J^surf / w_0) mu_n . F*(nbr, own, -n) = -(J^surf / w_0) mu_n . F*(own, nbr, n)
+            // (the flux is conservative; on a conforming mesh both sides share
+            // the face's normal up to sign and its surface Jacobian): one
+            // reverse evaluation with the cotangent (J^surf / w_0)(mu - mu_n).
             const R so = js * a.tab.iw0;
-            FluxBar<R> g1, g2, unused;
+            FluxBar<R> g1, unused;
             interface_flux_vjp<R>(ho, wo.x, wo.y, bo, hn, un, vn, bn, snx / js, sny / js, P,
-                                  so * s_m[0][lp], so * s_m[1][lp], so * s_m[2][lp], g1, unused);
-            const R sn = -jsn * a.tab.iw0 / nJ;
-            interface_flux_vjp<R>(hn, un, vn, bn, ho, wo.x, wo.y, bo, nnx / jsn, nny / jsn, P, sn * nl0,
-                                  sn * nl1, sn * nl2, unused, g2);
-            gh = g1.h + g2.h; gu = g1.u + g2.u; gv = g1.v + g2.v; gb = g1.b + g2.b;
+                                  so * (s_m[0][lp] + nl0 * inJ), so * (s_m[1][lp] + nl1 * inJ),
+                                  so * (s_m[2][lp] + nl2 * inJ), g1, unused);
+            gh = g1.h; gu = g1.u; gv = g1.v; gb = g1.b;
         }
         s_fg[0][f] = gh; s_fg[1][f] = gu; s_fg[2][f] = gv; s_fg[3][f] = gb;
     }
