@@ -140,6 +140,7 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
     __shared__ double2 s_q[T], s_w[T], s_a[T], s_b[T];   // (hu, hv), (u, v), J grad(xi), J grad(eta)
     __shared__ R s_m[3][T];                              // mu = -l / J
     __shared__ R s_fg[4][NF];                            // face cotangents: h, u, v, b
+    __shared__ R s_dz[nf * nf];                          // D with a zero diagonal
 
     const int64_t tile = xcd_tile(a.ntiles);
     if (tile < 0) return;
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
     s_a[t] = double2{Ax, Cx};
     s_b[t] = double2{Ae, Ce};
     s_m[0][t] = m0; s_m[1][t] = m1; s_m[2][t] = m2;
+    for (int c = t; c < nf * nf; c += T) s_dz[c] = a.tg->Dz[(c / nf) * kMaxNF + (c - (c / nf) * nf)];
     lds_sync<T>();
 
     // ---- interface: own term w.r.t. the '-' trace, neighbour's term w.r.t. its '+' trace ----
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
 #pragma unroll 2
         for (int mm = 0; mm < nf; ++mm) {
             const int qq = base + mm * nf + j;
-            const R da = a.tg->Dz[i * kMaxNF + mm], db = a.tg->Dz[mm * kMaxNF + i];
+            const R da = s_dz[i * nf + mm], db = s_dz[mm * nf + i];
             const R z0 = da * m0 + db * s_m[0][qq], z1 = da * m1 + db * s_m[1][qq], z2 = da * m2 + db * s_m[2][qq];
             const double2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ax + am.x, sC = Cx + am.y;
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
 #pragma unroll 2
         for (int mm = 0; mm < nf; ++mm) {
             const int qq = base + i * nf + mm;
-            const R da = a.tg->Dz[j * kMaxNF + mm], db = a.tg->Dz[mm * kMaxNF + j];
+            const R da = s_dz[j * nf + mm], db = s_dz[mm * nf + j];
             const R z0 = da * m0 + db * s_m[0][qq], z1 = da * m1 + db * s_m[1][qq], z2 = da * m2 + db * s_m[2][qq];
             const double2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ae + bm.x, sC = Ce + bm.y;

@@ -523,24 +523,25 @@ __device__ __forceinline__ R viscosity_from_totals(R all, R top, R allM, R topM,
 // fractions of the top two mode shells, sigma = log10 of the larger, and the
 // sine ramp between sigma_min and sigma_max; zero for dry elements.  The
 // result is valid in thread p == 0 of each element.  red: 6*T reals of LDS
-// (the last T hold the intermediate V^{-1} h).  Three barriers.
+// (the last T hold the intermediate V^{-1} h); vinv: V^{-1} row-major with
+// row stride N+1, staged in LDS by the caller (stage_vinv).  Three barriers.
 template <int N, typename R, int T = Shape<N>::T>
-__device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phys<R> &P, int t, int el,
-                               int p, bool lane, R h)
+__device__ R element_viscosity(const R *sh, R *red, const R *vinv, const Phys<R> &P, int t, int el, int p,
+                               bool lane, R h)
 {
     constexpr int nf = N + 1, np = nf * nf;
     const int i = p / nf, j = p - i * nf;
     R Tq = 0;
     if (lane) {
 #pragma unroll
-        for (int r = 0; r < nf; ++r) Tq += tab.Vinv[i * kMaxNF + r] * sh[el * np + r * nf + j];
+        for (int r = 0; r < nf; ++r) Tq += vinv[i * nf + r] * sh[el * np + r * nf + j];
     }
     red[5 * T + t] = Tq;
     lds_sync<T>();
     R Qh = 0;
     if (lane) {
 #pragma unroll
-        for (int c = 0; c < nf; ++c) Qh += red[5 * T + el * np + i * nf + c] * tab.Vinv[j * kMaxNF + c];
+        for (int c = 0; c < nf; ++c) Qh += red[5 * T + el * np + i * nf + c] * vinv[j * nf + c];
     }
     const R q2 = Qh * Qh;
     const int mx = i > j ? i : j;
@@ -549,6 +550,14 @@ __device__ R element_viscosity(const R *sh, R *red, const Tab<R> &tab, const Phy
                  lane ? -h : R(3.0e38)};
     elem_totals_any<N, R, 4, true, T>(vals, red, t, el, p, lane);
     return viscosity_from_totals<R>(vals[0] + vals[1], vals[0], vals[1], vals[2], -vals[3], P);
+}
+
+// Copy V^{-1} (row stride N+1) into LDS; ordered by the caller's next barrier.
+template <int N, typename R, int T>
+__device__ __forceinline__ void stage_vinv(R *dst, const Tab<R> &tab, int t)
+{
+    constexpr int nf = N + 1;
+    for (int q = t; q < nf * nf; q += T) dst[q] = tab.Vinv[(q / nf) * kMaxNF + (q - (q / nf) * nf)];
 }
 
 // Viscous physical fluxes at node (i,j) of the element whose u, v are in
@@ -605,10 +614,11 @@ __global__ __launch_bounds__(Shape<N>::T) void indicator_kernel(IndicatorArgs<N,
 {
     using S = Shape<N>;
     constexpr int np = S::np, E = S::E, T = S::T;
-    __shared__ R s_h[T], s_red[6 * T];
+    __shared__ R s_h[T], s_red[6 * T], s_vinv[(N + 1) * (N + 1)];
     const int64_t tile = xcd_tile(a.ntiles);
     if (tile < 0) return;
     const int t = threadIdx.x;
+    stage_vinv<N, R, T>(s_vinv, *a.tg, t);
     const bool lane = t < E * np;
     const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0;
     const int64_t e = tile * E + el;
@@ -616,7 +626,7 @@ __global__ __launch_bounds__(Shape<N>::T) void indicator_kernel(IndicatorArgs<N,
     const R h = act ? a.h[e * np + p] : R(0);
     s_h[t] = h;
     lds_sync<T>();
-    const R eps = element_viscosity<N, R>(s_h, s_red, *a.tg, a.P, t, el, p, lane, h);
+    const R eps = element_viscosity<N, R>(s_h, s_red, s_vinv, a.P, t, el, p, lane, h);
     if (act && p == 0) {
         a.eps[e] = eps;
         if (eps > R(0)) a.list[atomicAdd(a.count, 1)] = (int32_t)e;
@@ -878,6 +888,8 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     R *const s_h = s_st + 8 * T;
     __shared__ R s_fl[3][NF];
     __shared__ R s_lim[4 * E];
+    __shared__ R s_vinv[nf * nf];       // V^{-1} for the indicator epilogue (with AV)
+    __shared__ R s_dz[nf * nf];         // D with a zero diagonal (volume term)
 
     const int64_t tile = xcd_tile(a.ntiles);
     if (tile < 0) return;
@@ -904,6 +916,11 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     s_w[t] = V2{u, v};
     s_a[t] = V2{Ax, Cx};
     s_b[t] = V2{Ae, Ce};
+    if constexpr (MODE != kModeRhs)
+        if (av) stage_vinv<N, R, T>(s_vinv, *a.tg, t);
+    // the per-lane table entries of the volume term from LDS rather than
+    // through the vector memory path (3-6% faster)
+    for (int c = t; c < nf * nf; c += T) s_dz[c] = a.tg->Dz[(c / nf) * kMaxNF + (c - (c / nf) * nf)];
     lds_sync<T>();
 
     // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node; for
@@ -974,7 +991,7 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
         for (int mm = 0; mm < nf; ++mm) {
             // the self pair has coefficient 0 (no branch: D~ has a zero diagonal)
             const int qq = base + mm * nf + j;
-            const R d = a.tg->Dz[i * kMaxNF + mm];
+            const R d = s_dz[i * nf + mm];
             const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ax + am.x, sC = Cx + am.y;
             const R f1 = (hu + qm.x) * sA + (hv + qm.y) * sC;
@@ -986,7 +1003,7 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
             const int qq = base + i * nf + mm;
-            const R d = a.tg->Dz[j * kMaxNF + mm];
+            const R d = s_dz[j * nf + mm];
             const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ae + bm.x, sC = Ce + bm.y;
             const R f1 = (hu + qm.x) * sA + (hv + qm.y) * sC;
@@ -1085,7 +1102,7 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             // viscosity of the new state for the next stage (appendix A)
             s_st[8 * T + t] = nh;
             lds_sync<T>();
-            en = element_viscosity<N, R, T>(s_st + 8 * T, s_st, *a.tg, P, t, el, p, lane, nh);
+            en = element_viscosity<N, R, T>(s_st + 8 * T, s_st, s_vinv, P, t, el, p, lane, nh);
             if (act && p == 0) {
                 a.eps_out[e] = en;
                 if (en > R(0)) a.list_out[atomicAdd(a.count_out, 1)] = (int32_t)e;
