@@ -871,6 +871,33 @@ struct StageArgs {
     int variant;                 // workgroup size: 0 the default, 1 the alternative (launch side)
 };
 
+// Face slot data loaded ahead of the LDS staging (slot = lane).
+template <typename R>
+struct FacePrefetch {
+    int64_t qn = 0, en = 0;
+    int ns = 0, kk = 0;
+    R h = 0, hu = 0, hv = 0, bo = 0, bn = 0;
+};
+
+template <int N, typename R, int E, int NF>
+__device__ __forceinline__ void prefetch_face(const StageArgs<R> &a, int t, int64_t e0, FacePrefetch<R> &pf)
+{
+    constexpr int nf = N + 1, np = nf * nf;
+    if (t >= NF) return;
+    const int fel = t / (4 * nf), s = (t / nf) & 3, k = t - (t / nf) * nf;
+    const int64_t fe = e0 + fel;
+    if (fe >= a.m.K) return;
+    pf.qn = nbr_node<N>(a.m, fe, s, k, pf.en, pf.ns, pf.kk);
+    const int64_t ql = pf.qn - e0 * np;
+    if (!(ql >= 0 && ql < E * np)) {
+        pf.h = a.h[pf.qn];
+        pf.hu = a.hu[pf.qn];
+        pf.hv = a.hv[pf.qn];
+    }
+    pf.bo = a.m.bface[(fe * 4 + s) * nf + k];
+    pf.bn = a.m.bface[(pf.en * 4 + pf.ns) * nf + pf.kk];
+}
+
 template <int N, typename R, int MODE, int TT>
 __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage_kernel(StageArgs<R> a)
 {
@@ -909,6 +936,11 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
         h = a.h[q]; hu = a.hu[q]; hv = a.hv[q];
         Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
     }
+    // When every face slot has a lane of its own, the slot's neighbour trace
+    // and face bathymetry are loaded here, with the element's own data, so
+    // that their latency is not paid a second time after the LDS staging.
+    FacePrefetch<R> pf;
+    if constexpr (NF <= T) prefetch_face<N, R, E, NF>(a, t, e0, pf);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
     s_h[t] = h;
@@ -935,7 +967,12 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             int64_t en;
             side_node<N>(s, k, fi, fj);
             const int lp = fel * np + fi * nf + fj;
-            const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+            int64_t qn;
+            if constexpr (NF <= T) {
+                qn = pf.qn; en = pf.en; ns = pf.ns; kk = pf.kk;
+            } else {
+                qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+            }
             // outward scaled normal: +-J grad(xi) on xi = +-1, +-J grad(eta) on eta = +-1
             const V2 dir = (s & 1) ? s_a[lp] : s_b[lp];
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
@@ -944,20 +981,29 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             const R ijs = rcp_nr(js);
             // neighbour trace: from LDS when the neighbour is in this workgroup
             const int64_t ql = qn - e0 * np;
-            R hn, un, vn;
+            R hn, un, vn, bo, bn;
             if (ql >= 0 && ql < E * np) {
                 hn = s_h[ql];
                 const V2 w = s_w[ql];
                 un = w.x;
                 vn = w.y;
             } else {
-                hn = a.h[qn];
+                R hun, hvn;
+                if constexpr (NF <= T) {
+                    hn = pf.h; hun = pf.hu; hvn = pf.hv;
+                } else {
+                    hn = a.h[qn]; hun = a.hu[qn]; hvn = a.hv[qn];
+                }
                 const R in = rcp_wet(hn, P.h_tol);
-                un = a.hu[qn] * in;
-                vn = a.hv[qn] * in;
+                un = hun * in;
+                vn = hvn * in;
             }
-            const R bo = a.m.bface[(fe * 4 + s) * nf + k];
-            const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
+            if constexpr (NF <= T) {
+                bo = pf.bo; bn = pf.bn;
+            } else {
+                bo = a.m.bface[(fe * 4 + s) * nf + k];
+                bn = a.m.bface[(en * 4 + ns) * nf + kk];
+            }
             if (is_wall(a.m, fe, s)) wall_mirror(snx * ijs, sny * ijs, un, vn);
             R F0, F1, F2;
             const V2 wl = s_w[lp];
