@@ -56,6 +56,22 @@ def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_v
     return (per_node * n + per_elem * K + visc) * real_bytes
 
 
+def stage_flops(N: int, av: bool) -> float:
+    """Algorithmic FP64 FLOPs per node of one stage (operation count of the
+    method, not of this implementation): the volume term 2(N+1) partner pairs
+    of 22 FLOP (pairwise sums of the conserved and primitive variables and of
+    two metric terms, the contravariant discharge, the two momentum fluxes,
+    the D-weighted accumulation), the interface flux (~80 FLOP per face-node
+    evaluation, 2(N+1) per element side pair, plus ~36 for the lift, spread
+    over the nodes), velocities, source and scaling (~18) and the update
+    (~12); with AV the indicator (~20(N+1) + 25); the limiter's test (~15)."""
+    nf = N + 1
+    f = 44 * nf + 196 / nf + 30 + 15
+    if av:
+        f += 20 * nf + 25
+    return float(f)
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic_N7_512x512_fp64.txt")
 
 
@@ -389,7 +405,10 @@ def main():
         stage_launch = prof["stage_launches"]
         stage_mean_ms = prof["stage_ms"] / max(stage_launch, 1)
         achieved = stage_total / (prof["stage_ms"] * 1e-3) / 1e9
+        flops_node = stage_flops(N, av)
         res = dict(N=N, precision=precision, K=K, nodes=nodes, elapsed=el, t_sim=t_sim, n_visc=n_visc,
+                   stage_TFLOPs=flops_node * nodes / (stage_mean_ms * 1e-3) / 1e12,
+                   flops_per_node=flops_node,
                    stage_variant=choice,
                    value=nodes * 5 * steps / el,
                    ms_per_step=el * 1e3 / steps,
@@ -424,9 +443,15 @@ def main():
     main_res = run(args.N)
     log("memcopy probe")
     mc = memcopy_probe(main_res["stage_bytes_per_launch"])
+    log("LDS probe")
+    lds_bw = esdg.lds_bandwidth(dev)
+    # LDS bytes the volume term reads per node: 2(N+1) partners x (metric pair, discharge
+    # pair, velocity pair: 16 B each; h and the D entry: 8 B each)
+    lds_node = 2 * (args.N + 1) * 64.0
+    lds_achieved = lds_node * main_res["nodes"] / (main_res["stage_mean_ms"] * 1e-3)
     sweep = []
     keys = ("N", "precision", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs", "roofline_frac",
-            "stage_variant")
+            "stage_TFLOPs", "stage_variant")
     for tok in [t for t in args.sweep.split(",") if t.strip()]:
         r = run(int(tok), steps=args.sweep_steps, warmup=2)
         sweep.append({k: r[k] for k in keys})
@@ -489,12 +514,20 @@ def main():
             "bytes_per_launch": main_res["stage_bytes_per_launch"],
             "viscous_elements": main_res["n_visc"],
             "mean_launch_ms": main_res["stage_mean_ms"],
+            "fp64_vector": {"achieved_TFLOPs": main_res["stage_TFLOPs"],
+                            "peak_TFLOPs": 78.6 if args.precision == 64 else 157.3,
+                            "flops_per_node": main_res["flops_per_node"],
+                            "note": "algorithmic FLOPs of the method (bench.stage_flops); the rocprofv3 FP64 "
+                                    "instruction counts per degree are in "
+                                    "profiles/stage_kernel_roofline_by_degree_512x512_fp64.md"},
         },
         "cpu_baseline": cpu,
         "viscosity_kernels": {"ms_per_stage": main_res["av_ms_per_stage"],
                               "launches": main_res["av_launches"]},
         "memcopy_roofline": {"GBs": mc["GBs"], "bytes": mc["bytes"],
                              "stage_frac": main_res["stage_GBs"] / mc["GBs"]},
+        "lds_roofline": {"probe_GBs": lds_bw / 1e9, "volume_bytes_per_node": lds_node,
+                         "stage_volume_GBs": lds_achieved / 1e9, "frac": lds_achieved / lds_bw},
     }
     if sweep:
         out["sweep"] = sweep

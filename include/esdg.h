@@ -211,6 +211,12 @@ int esdg_profile_read_adjoint(esdg_ctx *ctx, double *ms, int64_t *launches);
 int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2]);
 int esdg_set_stage_variant(esdg_ctx *ctx, int variant);
 
+/* Empirical LDS roofline (the paper's shared-memory roofline): 16-byte LDS
+ * reads per second on device `device` in the volume term's access pattern
+ * (one 8 x 8 element per 64-lane wave read along its lines), measured with
+ * HIP events over a dedicated kernel.  Allocates and frees a small buffer. */
+int esdg_lds_bandwidth(int device, double *bytes_per_s);
+
 /* Last error message of ctx (never NULL). */
 const char *esdg_last_error(const esdg_ctx *ctx);
 

@@ -1880,3 +1880,71 @@ int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, d
 }
 
 }  // extern "C"
+
+// ==========================================================================
+// Empirical LDS roofline (the paper's shared-memory roofline): 16-byte LDS
+// reads in the volume term's pattern, an 8 x 8 element per wave read along
+// its lines (row reads are shared by the 8 lanes of a row, column reads are
+// 8 different addresses), with one FMA per read so the ALUs stay idle.
+// ==========================================================================
+namespace {
+
+constexpr int kLdsProbeThreads = 256;
+
+__global__ __launch_bounds__(kLdsProbeThreads) void lds_probe_kernel(int iters, double *out)
+{
+    __shared__ double2 s[kLdsProbeThreads];
+    const int t = threadIdx.x;
+    s[t] = double2{(double)t, 1.0 + t};
+    __syncthreads();
+    const int base = t & ~63, row = (t & 63) >> 3, col = t & 7;
+    double ax = 0.0, ay = 0.0;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int mm = (m + it) & 7;   // the addresses change every iteration: nothing to hoist
+            const double2 a = s[base + row * 8 + mm];
+            const double2 b = s[base + mm * 8 + col];
+            ax = fma(a.x, b.y, ax);
+            ay = fma(a.y, b.x, ay);
+        }
+    }
+    out[(int64_t)blockIdx.x * kLdsProbeThreads + t] = ax + ay;
+}
+
+}  // namespace
+
+extern "C" {
+
+int esdg_lds_bandwidth(int device, double *bytes_per_s)
+{
+    if (!bytes_per_s) return ESDG_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return ESDG_EHIP;
+    const int blocks = 256 * 16, iters = 256;
+    double *out = nullptr;
+    if (hipMalloc((void **)&out, (size_t)blocks * kLdsProbeThreads * sizeof(double)) != hipSuccess)
+        return ESDG_ENOMEM;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = ESDG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = ESDG_EHIP;
+    float best = 0.0f;
+    for (int rep = 0; rep < 4 && st == ESDG_OK; ++rep) {
+        hipEventRecord(e0, nullptr);
+        hipLaunchKernelGGL(lds_probe_kernel, dim3(blocks), dim3(kLdsProbeThreads), 0, nullptr, iters, out);
+        hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) != hipSuccess) { st = ESDG_EHIP; break; }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && (best == 0.0f || ms < best)) best = ms;   // the first launch warms up
+    }
+    if (st == ESDG_OK) {
+        const double bytes = (double)blocks * kLdsProbeThreads * iters * 8 * 2 * 16;
+        *bytes_per_s = bytes / (best * 1e-3);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    return st;
+}
+
+}  // extern "C"

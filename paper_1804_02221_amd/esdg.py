@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
             "esdg_adjoint_forward": ([P, I, D, I, P, I, P, P], I),
             "esdg_adjoint_backward": ([P, D, P, P, P, P, I], I),
             "esdg_profile_read_adjoint": ([P, P, P], I),
+            "esdg_lds_bandwidth": ([I, P], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -123,6 +124,15 @@ def default_params(N: int = 3, **kw) -> Params:
             raise KeyError(k)
         setattr(p, k, v)
     return p
+
+
+def lds_bandwidth(device: int = 0) -> float:
+    """Measured LDS read bandwidth (bytes/s) in the volume term's pattern."""
+    out = C.c_double(0.0)
+    st = lib().esdg_lds_bandwidth(int(device), C.byref(out))
+    if st != OK:
+        raise EsdgError(st, "esdg_lds_bandwidth failed")
+    return out.value
 
 
 def _is_torch(a):
