@@ -877,6 +877,7 @@ struct FacePrefetch {
     int64_t qn = 0, en = 0;
     int ns = 0, kk = 0;
     R h = 0, hu = 0, hv = 0, bo = 0, bn = 0;
+    bool visc_nbr = false;   // with AV: the element has no viscosity, its neighbour has
 };
 
 template <int N, typename R, int E, int NF>
@@ -896,6 +897,7 @@ __device__ __forceinline__ void prefetch_face(const StageArgs<R> &a, int t, int6
     }
     pf.bo = a.m.bface[(fe * 4 + s) * nf + k];
     pf.bn = a.m.bface[(pf.en * 4 + pf.ns) * nf + pf.kk];
+    if (a.eps) pf.visc_nbr = !(a.eps[fe] > R(0)) && a.eps[pf.en] > R(0);
 }
 
 template <int N, typename R, int MODE, int TT>
@@ -941,6 +943,7 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     // that their latency is not paid a second time after the LDS staging.
     FacePrefetch<R> pf;
     if constexpr (NF <= T) prefetch_face<N, R, E, NF>(a, t, e0, pf);
+    const R eps_e = (av && act) ? a.eps[e] : R(0);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
     s_h[t] = h;
@@ -1011,7 +1014,10 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
                               F1, F2);
             const R sc = js * a.tab.iw0;
             c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
-            if (av && !(a.eps[fe] > R(0)) && a.eps[en] > R(0)) {
+            bool visc_nbr;
+            if constexpr (NF <= T) visc_nbr = av && pf.visc_nbr;
+            else visc_nbr = av && !(a.eps[fe] > R(0)) && a.eps[en] > R(0);
+            if (visc_nbr) {
                 const R *vn = a.vtr + ((en * 4 + ns) * nf + kk) * 4;
                 const R hw = R(0.5) * a.tab.iw0;
                 c1 -= hw * (snx * vn[0] + sny * vn[2]);
@@ -1075,7 +1081,7 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     R bxv = 0, byv = 0, Lv2 = 0, Lv3 = 0;
     if (act) {
         bxv = a.m.bx[q]; byv = a.m.by[q];
-        if (av && a.eps[e] > R(0)) { Lv2 = a.lv2[q]; Lv3 = a.lv3[q]; }
+        if (av && eps_e > R(0)) { Lv2 = a.lv2[q]; Lv3 = a.lv3[q]; }
     }
     const R iJ = act ? rcp_nr(J) : R(0);
     const R hg = R(0.5) * P.g * h;
