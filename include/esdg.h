@@ -273,8 +273,9 @@ const char *esdg_ensemble_last_error(const esdg_ensemble *en);
  * eqs. fluxDiffFormF, Fmij and volumeFluxes, interface flux of appendix B,
  * source of eq. SourceDisc) and of LSRK(5,4) steps, for gradients with
  * respect to the nodal bathymetry.  The artificial viscosity is frozen at
- * zero (av_on must be 0: ESDG_EINVAL otherwise) and the mesh has no walls
- * (ESDG_EINVAL otherwise).  The limiter must not act:
+ * zero (av_on must be 0: ESDG_EINVAL otherwise).  Solid walls are covered:
+ * their outside state is a linear mirror of the own trace, and the reverse
+ * mode runs through it.  The limiter must not act:
  * on a wet state (h >= h_tol everywhere, so theta = 1 and no velocity is cut
  * off) it is the identity and so is its derivative.  |x| is differentiated
  * as sign(x) with sign(0) = 0.

@@ -1276,8 +1276,20 @@ static int rhs_vjp_acc(const orc_params *P, const orc_ops *op, const orc_mesh *m
                 double Js = sqrt(snx * snx + sny * sny);
                 dn wm[3] = {dn_var(h[q], 0), dn_var(hu[q], 1), dn_var(hv[q], 2)};
                 dn wp[3] = {dn_var(h[qn], 4), dn_var(hu[qn], 5), dn_var(hv[qn], 6)};
+                dn bm = dn_var(b[q], 3), bp = dn_var(b[qn], 7);
+                if (is_wall(m, e, s)) {
+                    /* the outside state is the own trace with its normal
+                     * discharge reversed, b unchanged: the chain rule runs
+                     * through the mirror, and nothing reaches a neighbour */
+                    double ux = snx / Js, uy = sny / Js;
+                    dn dnrm = dn_add(dn_scl(ux, wm[1]), dn_scl(uy, wm[2]));
+                    wp[0] = wm[0];
+                    wp[1] = dn_sub(wm[1], dn_scl(2.0 * ux, dnrm));
+                    wp[2] = dn_sub(wm[2], dn_scl(2.0 * uy, dnrm));
+                    bp = bm;
+                }
                 dn Fn[3];
-                surface_flux_dn(P, wm, dn_var(b[q], 3), wp, dn_var(b[qn], 7), snx / Js, sny / Js, Fn);
+                surface_flux_dn(P, wm, bm, wp, bp, snx / Js, sny / Js, Fn);
                 double contra = (s == 1 || s == 2) ? Js : -Js;       /* F~* = +-J^surf F*_n */
                 double fac = (s == 1 || s == 2) ? contra / op->w[N] : -contra / op->w[0];
                 for (int c = 0; c < 3; ++c) {
@@ -1328,21 +1340,13 @@ static int rhs_vjp_acc(const orc_params *P, const orc_ops *op, const orc_mesh *m
 }
 
 /* (dR/dW)^T lam and (dR/db)^T lam of the inviscid right-hand side at (W, b). */
-/* The adjoint covers closed periodic meshes (no walls). */
-static int has_walls(const orc_mesh *m)
-{
-    for (int64_t f = 0; f < 4 * m->K; ++f)
-        if (m->nbr_elem[f] < 0) return 1;
-    return 0;
-}
-
 int orc_rhs_vjp(const orc_params *P, const orc_mesh *m, const double *b, const double *h,
                 const double *hu, const double *hv, const double *lh, const double *lhu,
                 const double *lhv, double *gh, double *ghu, double *ghv, double *gb)
 {
     int st = check_mesh(m);
     if (st) return st;
-    if (P->av_on || has_walls(m)) return ORC_EINVAL;
+    if (P->av_on) return ORC_EINVAL;
     orc_ops op;
     build_ops(m->N, &op);
     orc_geom G;
@@ -1378,7 +1382,7 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
 {
     int st = check_mesh(m);
     if (st) return st;
-    if (P->av_on || P->integrator != 0 || nsteps < 1 || ng < 0 || !(dt > 0.0) || has_walls(m))
+    if (P->av_on || P->integrator != 0 || nsteps < 1 || ng < 0 || !(dt > 0.0))
         return ORC_EINVAL;
     const int N = m->N, n1 = N + 1, np = n1 * n1;
     for (int gg = 0; gg < ng; ++gg)

@@ -26,7 +26,10 @@
 //    respect to its own ('-') trace and of the neighbour's face term with
 //    respect to the neighbour's '+' trace, which is this node; since the
 //    interface flux is conservative, F*(W+, W-, -n) = -F*(W-, W+, n), both
-//    are one reverse evaluation of the own term's flux.
+//    are one reverse evaluation of the own term's flux.  At a solid wall the
+//    outside trace is the own trace with the normal velocity reversed: the
+//    outside cotangent returns to this node through that (symmetric) mirror,
+//    and there is no neighbour term.
 // The derivative of |x| is taken as sign(x) with sign(0) = 0; velocities
 // below the dry cut-off are constants (zero derivative).
 #pragma once
@@ -190,15 +193,24 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
             const R snx = sg * dir.x, sny = sg * dir.y;
             const R js = sqrt(snx * snx + sny * sny);
-            // neighbour's trace and cotangent mu_n = -l_n / J_n
+            const R nx = snx / js, ny = sny / js;
+            const bool wall = is_wall(a.m, fe, s);
+            // neighbour's trace and cotangent mu_n = -l_n / J_n (a wall: the
+            // own trace, mirrored, and no neighbour term)
             const R hn = a.h[qn];
             const R inn = rcp_wet(hn, P.h_tol);
-            const R un = a.hu[qn] * inn, vn = a.hv[qn] * inn;
-            const R nJ = a.m.Ce[qn] * a.m.Ax[qn] - a.m.Cx[qn] * a.m.Ae[qn];
-            R nl0 = 0, nl1 = 0, nl2 = 0;
-            if (a.c[0]) { nl0 = a.c[0][qn]; nl1 = a.c[1][qn]; nl2 = a.c[2][qn]; }
-            if (a.a[0]) { nl0 += a.cb * a.a[0][qn]; nl1 += a.cb * a.a[1][qn]; nl2 += a.cb * a.a[2][qn]; }
-            const R inJ = R(1) / nJ;
+            R un = a.hu[qn] * inn, vn = a.hv[qn] * inn;
+            R nm0 = 0, nm1 = 0, nm2 = 0;
+            if (wall) {
+                wall_mirror(nx, ny, un, vn);
+            } else {
+                const R nJ = a.m.Ce[qn] * a.m.Ax[qn] - a.m.Cx[qn] * a.m.Ae[qn];
+                R nl0 = 0, nl1 = 0, nl2 = 0;
+                if (a.c[0]) { nl0 = a.c[0][qn]; nl1 = a.c[1][qn]; nl2 = a.c[2][qn]; }
+                if (a.a[0]) { nl0 += a.cb * a.a[0][qn]; nl1 += a.cb * a.a[1][qn]; nl2 += a.cb * a.a[2][qn]; }
+                const R inJ = R(1) / nJ;
+                nm0 = nl0 * inJ; nm1 = nl1 * inJ; nm2 = nl2 * inJ;
+            }
             const R bo = a.m.bface[(fe * 4 + s) * nf + k];
             const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
             const R ho = s_h[lp];
@@ -209,11 +221,16 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
             // the face's normal up to sign and its surface Jacobian): one
             // reverse evaluation with the cotangent (J^surf / w_0)(mu - mu_n).
             const R so = js * a.tab.iw0;
-            FluxBar<R> g1, unused;
-            interface_flux_vjp<R>(ho, wo.x, wo.y, bo, hn, un, vn, bn, snx / js, sny / js, P,
-                                  so * (s_m[0][lp] + nl0 * inJ), so * (s_m[1][lp] + nl1 * inJ),
-                                  so * (s_m[2][lp] + nl2 * inJ), g1, unused);
+            FluxBar<R> g1, g2;
+            interface_flux_vjp<R>(ho, wo.x, wo.y, bo, hn, un, vn, bn, nx, ny, P, so * (s_m[0][lp] + nm0),
+                                  so * (s_m[1][lp] + nm1), so * (s_m[2][lp] + nm2), g1, g2);
             gh = g1.h; gu = g1.u; gv = g1.v; gb = g1.b;
+            if (wall) {
+                // the outside trace is (h, M(u, v), b), M = I - 2 n n^T = M^T:
+                // its cotangent returns through the mirror
+                wall_mirror(nx, ny, g2.u, g2.v);
+                gh += g2.h; gu += g2.u; gv += g2.v; gb += g2.b;
+            }
         }
         s_fg[0][f] = gh; s_fg[1][f] = gu; s_fg[2][f] = gv; s_fg[3][f] = gb;
     }

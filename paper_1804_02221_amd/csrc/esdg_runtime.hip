@@ -162,7 +162,6 @@ struct esdg_ctx {
     int64_t acc_n[3] = {0, 0, 0};
     std::string err = "no error";
     std::vector<int32_t> inv_h;   // caller's element -> internal element
-    bool has_walls = false;       // some side is a solid wall
     uint64_t b_version = 0;       // bumped by every esdg_set_bathymetry
     // discrete adjoint (gauges, checkpoints, cotangent fields)
     struct Adjoint {
@@ -707,7 +706,6 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     for (int64_t f = 0; f < 4 * K; ++f) walls = walls || ne[f] < 0;
     free_bufs(ctx);
     ctx->inv_h = inv;
-    ctx->has_walls = walls;
     ctx->B.walls = walls ? 1 : 0;
     ctx->N = N;
     ctx->K = K;
@@ -1559,7 +1557,6 @@ bool check_adjoint_ctx(esdg_ctx *ctx)
     if (ctx->prec != 64) return fail(ctx, ESDG_EINVAL, "the adjoint needs a float64 context"), false;
     if (ctx->P.av_on) return fail(ctx, ESDG_EINVAL, "the adjoint covers the inviscid operator (av_on = 0)"), false;
     if (n_inst(ctx) != 1) return fail(ctx, ESDG_EINVAL, "the adjoint runs on single-instance contexts"), false;
-    if (ctx->has_walls) return fail(ctx, ESDG_EINVAL, "the adjoint covers meshes without walls"), false;
     return true;
 }
 

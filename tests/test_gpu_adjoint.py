@@ -13,7 +13,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-from paper_1804_02221_amd.inputs import bathymetry_gradient, make_periodic_mesh, periodic_gaussians, smooth_sweep
+from paper_1804_02221_amd.inputs import (bathymetry_gradient, make_box_mesh, make_periodic_mesh, periodic_gaussians,
+                                         smooth_sweep)
 
 TOL_VJP = 1e-12
 TOL_GRAD = 1e-10
@@ -72,6 +73,31 @@ def test_rhs_vjp_parity(esdg, orc, N, n, ec, rot):
     s.close()
 
 
+def box_state(N, nx, ny, wx, wy, rot, seed):
+    """A wet state in a walled box with flow through the walls' normals."""
+    mesh = make_box_mesh(N, nx, ny, -2.0, -2.0, 4.0, 4.0, amp=0.1, walls_x=wx, walls_y=wy, rotate_seed=rot)
+    rng = np.random.default_rng(seed)
+    x, y = mesh.x, mesh.y
+    c = rng.uniform(0.3, 0.7, 6)
+    b = 0.3 * np.exp(-((x - c[0] * 4 + 2) ** 2 + (y - c[1] * 4 + 2) ** 2))
+    h = 1.0 + 0.2 * np.sin(1.3 * x + c[2]) * np.cos(0.9 * y + c[3]) - b
+    return mesh, b, h, h * (0.3 * np.cos(0.7 * x + c[4]) + 0.2), h * (0.2 * np.sin(0.8 * y + c[5]) - 0.15)
+
+
+@pytest.mark.parametrize("N,wx,wy,ec,rot", [(2, 1, 1, 0, 2), (3, 1, 0, 0, None), (4, 0, 1, 1, 4),
+                                            (5, 1, 1, 0, 5), (7, 1, 1, 1, 7), (8, 1, 0, 0, 8)])
+def test_rhs_vjp_parity_with_walls(esdg, orc, N, wx, wy, ec, rot):
+    mesh, b, h, hu, hv = box_state(N, 5, 4, bool(wx), bool(wy), rot, N)
+    s, P = make_solver(esdg, mesh, b, h, hu, hv, N, surface_flux=ec, limiter_on=1)
+    rng = np.random.default_rng(100 + N)
+    lam = [rng.standard_normal(h.shape) for _ in range(3)]
+    print(f"rhs_vjp walls N={N} x={wx} y={wy} ec={ec} rot={rot}", flush=True)
+    got = s.rhs_vjp(*lam)
+    want = orc.rhs_vjp(oparams(orc, P), mesh, b, h, hu, hv, *lam)
+    check(got, want, TOL_VJP, f"walls N={N}")
+    s.close()
+
+
 def test_rhs_vjp_device_arrays(esdg, orc):
     import torch
     w = smooth_sweep(4, 3, seed=7)
@@ -124,6 +150,38 @@ def test_gauge_gradient_parity(esdg, orc, N, ec, every):
     h1 = s.get_state()[0]
     ref1 = orc.step(op, mesh, b, H0 - b, z, z, steps, dt_fixed=dt)[0]
     assert np.abs(h1 - ref1).max() <= 1e-13 * np.abs(ref1).max()
+    s.close()
+
+
+@pytest.mark.parametrize("N,ec,every", [(3, 0, 4), (7, 1, 5)])
+def test_gauge_gradient_parity_with_walls(esdg, orc, N, ec, every):
+    """A closed basin (walls on both axes): waves from the initial surface
+    bump reflect off the walls within the run."""
+    mesh = make_box_mesh(N, 5, 5, -2.0, -2.0, 4.0, 4.0, amp=0.1, rotate_seed=N)
+    rng = np.random.default_rng(N)
+    x, y = mesh.x, mesh.y
+    b = 0.25 * np.exp(-((x - 0.6) ** 2 + (y + 0.4) ** 2) / 0.5) + 0.05 * x
+    H0 = 1.0 + 0.05 * np.exp(-((x + 1.2) ** 2 + (y - 1.0) ** 2) / 0.3)
+    db = 0.03 * np.exp(-((x + 0.3) ** 2 + (y + 1.1) ** 2) / 0.4)
+    ng, steps = 6, 30
+    gelem = rng.integers(0, mesh.K, ng).astype(np.int32)
+    gxi, geta = rng.uniform(-1, 1, ng), rng.uniform(-1, 1, ng)
+    z = np.zeros_like(b)
+    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, N, surface_flux=ec, limiter_on=1)
+    op = oparams(orc, P)
+    dt = 0.8 * orc.dt(op, mesh, b, H0 - b, z, z)[1]
+    tgt = orc.gauge_adjoint(op, mesh, b + db, H0 - b - db, z, z, steps, dt, gelem, gxi, geta,
+                            np.zeros((steps, ng)), gradient=False)["H"]
+    tgt = tgt + 1e-3 * rng.standard_normal(tgt.shape)
+    ref = orc.gauge_adjoint(op, mesh, b, H0 - b, z, z, steps, dt, gelem, gxi, geta, tgt)
+    print(f"gauge gradient with walls N={N} ec={ec} every={every} steps={steps}", flush=True)
+    s.set_gauges(gelem, gxi, geta)
+    loss, H = s.adjoint_forward(steps, dt, every, tgt, want_H=True)
+    assert np.abs(H - ref["H"]).max() <= 1e-13 * np.abs(ref["H"]).max()
+    assert abs(loss - ref["loss"]) <= 1e-9 * ref["loss"]
+    gb, gh0, ghu0, ghv0 = s.adjoint_backward()
+    check([gb, gh0, ghu0, ghv0], [ref["gb"], ref["gh0"], ref["ghu0"], ref["ghv0"]], TOL_GRAD,
+          f"walls grad N={N}")
     s.close()
 
 

@@ -152,12 +152,3 @@ def test_dry_dam_break_paper_resolution(esdg):
     assert d[3] < E0
     assert rises <= 0.02 * steps and worst <= 1e-3
     s.close()
-
-
-def test_adjoint_refuses_walls(esdg):
-    w = oscillating_lake(10, 3)
-    s, P = make_solver(esdg, w.mesh, w.b, w.h, w.hu, w.hv, 3, **dict(w.params, av_on=0))
-    z = np.zeros_like(w.h)
-    with pytest.raises(esdg.EsdgError):
-        s.rhs_vjp(z, z, z)
-    s.close()

@@ -10,12 +10,14 @@ mathematics, not against itself:
 * the gauge-misfit loss and its gradient through LSRK(5,4) steps against a
   loss assembled independently here (one oracle step at a time, gauges
   interpolated with a Lagrange basis built from numpy's Legendre roots) and
-  its central differences along random directions in b and in W(0).
+  its central differences along random directions in b and in W(0);
+* all of the above also on basins with solid walls, whose outside state is
+  the mirror of the own trace (the reverse mode runs through the mirror).
 """
 import numpy as np
 import pytest
 
-from paper_1804_02221_amd.inputs import lgl_positions, make_periodic_mesh, periodic_gaussians, smooth_sweep
+from paper_1804_02221_amd.inputs import lgl_positions, make_box_mesh, make_periodic_mesh, periodic_gaussians, smooth_sweep
 
 
 def _dot(a, b):
@@ -25,6 +27,18 @@ def _dot(a, b):
 def _state(rot=None, N=3, n=4):
     w = smooth_sweep(n, N, seed=21, rotate_seed=rot)
     return w.mesh, w.b, w.h, w.hu, w.hv
+
+
+def _box_state(N, wx, wy, rot, seed=0):
+    """A wet state in a walled box with a flow through the walls' normals
+    (so the mirror matters) on a curved mesh."""
+    mesh = make_box_mesh(N, 4, 5, -2.0, -2.0, 4.0, 4.0, amp=0.1, walls_x=wx, walls_y=wy, rotate_seed=rot)
+    rng = np.random.default_rng(seed)
+    x, y = mesh.x, mesh.y
+    c = rng.uniform(0.3, 0.7, 6)
+    b = 0.3 * np.exp(-((x - c[0] * 4 + 2) ** 2 + (y - c[1] * 4 + 2) ** 2))
+    h = 1.0 + 0.2 * np.sin(1.3 * x + c[2]) * np.cos(0.9 * y + c[3]) - b
+    return mesh, b, h, h * (0.3 * np.cos(0.7 * x + c[4]) + 0.2), h * (0.2 * np.sin(0.8 * y + c[5]) - 0.15)
 
 
 @pytest.mark.parametrize("flux", [0, 1])
@@ -51,11 +65,72 @@ def test_rhs_vjp_against_central_differences(orc, flux, N, rot, kind):
     assert abs(fd - ad) <= 2e-7 * abs(ad) + 1e-9 * np.abs(grad).max() * np.abs(d).sum() / d.size, (fd, ad)
 
 
+@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("N,wx,wy,rot", [(3, True, True, None), (4, True, False, 7), (2, False, True, 3)])
+@pytest.mark.parametrize("kind", ["h", "hu", "hv", "b"])
+def test_rhs_vjp_with_walls_against_central_differences(orc, flux, N, wx, wy, rot, kind):
+    mesh, b, h, hu, hv = _box_state(N, wx, wy, rot, seed=N)
+    assert (mesh.nbr_elem < 0).any()
+    P = orc.params(N, surface_flux=flux)
+    rng = np.random.default_rng(50 + N + 10 * flux)
+    lam = [rng.standard_normal(h.shape) for _ in range(3)]
+    gh, ghu, ghv, gb = orc.rhs_vjp(P, mesh, b, h, hu, hv, *lam)
+    d = rng.standard_normal(h.shape)
+    args = dict(h=h, hu=hu, hv=hv, b=b)
+    grad = dict(h=gh, hu=ghu, hv=ghv, b=gb)[kind]
+    eps = 1e-5 * np.abs(args[kind]).max()
+
+    def R(sign):
+        a = dict(args)
+        a[kind] = args[kind] + sign * eps * d
+        return orc.rhs(P, mesh, a["b"], a["h"], a["hu"], a["hv"])[:3]
+
+    fd = (_dot(lam, R(1)) - _dot(lam, R(-1))) / (2 * eps)
+    ad = float(np.sum(grad * d))
+    assert abs(fd - ad) <= 2e-7 * abs(ad) + 1e-9 * np.abs(grad).max() * np.abs(d).sum() / d.size, (fd, ad)
+
+
+def test_rhs_vjp_at_walls_only_through_the_mirror(orc):
+    """Cotangents placed on the wall face nodes only: the VJP there equals
+    central differences of R restricted to those nodes' own traces, and a
+    wall face node's gradient does not leak to the far side of the box (the
+    periodic image it would have had without the wall)."""
+    N = 3
+    mesh, b, h, hu, hv = _box_state(N, True, False, None, seed=9)
+    P = orc.params(N)
+    n1 = N + 1
+    walls = np.argwhere(mesh.nbr_elem < 0)
+    lam = [np.zeros_like(h) for _ in range(3)]
+    rng = np.random.default_rng(3)
+    for e, s in walls:
+        for k in range(n1):
+            i, j = {0: (k, 0), 1: (N, k), 2: (k, N), 3: (0, k)}[int(s)]
+            for c in range(3):
+                lam[c][e, i * n1 + j] = rng.standard_normal()
+    g = orc.rhs_vjp(P, mesh, b, h, hu, hv, *lam)
+    # the two inner columns of the 4-column box (no wall side) receive nothing
+    cx = mesh.x.mean(axis=1)
+    far = np.abs(cx) < 1.0
+    assert far.any()
+    for a in g:
+        assert np.abs(a[far]).max() == 0.0
+    d = rng.standard_normal(h.shape)
+    eps = 1e-6
+
+    def R(sign):
+        return orc.rhs(P, mesh, b, h, hu + sign * eps * d, hv)[:3]
+
+    fd = (_dot(lam, R(1)) - _dot(lam, R(-1))) / (2 * eps)
+    ad = float(np.sum(g[1] * d))
+    assert abs(fd - ad) <= 1e-7 * abs(ad), (fd, ad)
+
+
+@pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("rot", [None, 13])
-def test_total_mass_rate_has_zero_gradient(orc, rot):
-    """sum J w_i w_j R_h = 0 for every state (Lemma 1, conservation), so its
-    gradient with respect to W and b vanishes."""
-    mesh, b, h, hu, hv = _state(rot, 3)
+def test_total_mass_rate_has_zero_gradient(orc, rot, walls):
+    """sum J w_i w_j R_h = 0 for every state (Lemma 1, conservation; no mass
+    crosses a wall), so its gradient with respect to W and b vanishes."""
+    mesh, b, h, hu, hv = _box_state(3, True, True, rot) if walls else _state(rot, 3)
     P = orc.params(3)
     op = orc.operators(3)
     J = orc.geometry(mesh)["J"]
@@ -104,6 +179,25 @@ def _small_case(N=3, n=4, steps=6, ng=5, seed=3):
     return mesh, b, H0, db, gelem, gxi, geta, steps
 
 
+def _small_box_case(N=3, steps=6, ng=5, seed=3):
+    """_small_case in the walled box [-2, 2]^2 (walls on both axes), fields
+    evaluated at the nodal coordinates."""
+    mesh = make_box_mesh(N, 4, 4, -2.0, -2.0, 4.0, 4.0, amp=0.1, rotate_seed=seed)
+    rng = np.random.default_rng(seed)
+    x, y = mesh.x, mesh.y
+
+    def bumps(k, lo, hi, amps, width):
+        c = rng.uniform(lo, hi, (k, 2))
+        return sum(a * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / width ** 2) for (cx, cy), a in zip(c, amps))
+
+    b = bumps(3, -1.5, 1.5, rng.uniform(0.1, 0.3, 3), 0.8)
+    H0 = 1.0 + bumps(1, -1.0, 1.0, [0.05], 0.8)
+    db = bumps(1, -1.5, 1.5, [0.02], 0.8)
+    gelem = rng.integers(0, mesh.x.shape[0], ng).astype(np.int32)
+    gxi, geta = rng.uniform(-1, 1, ng), rng.uniform(-1, 1, ng)
+    return mesh, b, H0, db, gelem, gxi, geta, steps
+
+
 def _loss_by_steps(orc, P, mesh, b, h0, hu0, hv0, steps, dt, gelem, gxi, geta, target):
     N = mesh.N
     Wg = [_lagrange_weights(N, a, c) for a, c in zip(gxi, geta)]
@@ -118,9 +212,10 @@ def _loss_by_steps(orc, P, mesh, b, h0, hu0, hv0, steps, dt, gelem, gxi, geta, t
     return L, np.array(Hs)
 
 
+@pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("flux", [0, 1])
-def test_gauge_loss_and_gradient(orc, flux):
-    mesh, b, H0, db, gelem, gxi, geta, steps = _small_case()
+def test_gauge_loss_and_gradient(orc, flux, walls):
+    mesh, b, H0, db, gelem, gxi, geta, steps = _small_box_case() if walls else _small_case()
     N = mesh.N
     P = orc.params(N, surface_flux=flux, limiter_on=1)
     z = np.zeros_like(b)
