@@ -249,9 +249,10 @@ def rhs_vjp(P: Params, mesh, b, h, hu, hv, lh, lhu, lhv):
 def gauge_adjoint(P: Params, mesh, b, h0, hu0, hv0, nsteps: int, dt: float, gelem, gxi, geta,
                   target, gradient: bool = True) -> dict:
     """Gauge-misfit loss L = 1/2 sum_n sum_g (H_g(t_n) - target[n-1, g])^2 dt over
-    nsteps fixed LSRK(5,4) steps, the surface H = h + b at the gauges (element
-    gelem[g], reference point (gxi[g], geta[g])).  Returns loss, H [nsteps, ng]
-    and, with gradient, gb = dL/db (initial state fixed) and gW0 = dL/dW(0)."""
+    nsteps fixed LSRK(5,4) or SSPRK(3,3) steps (P.integrator), the surface
+    H = h + b at the gauges (element gelem[g], reference point (gxi[g],
+    geta[g])).  Returns loss, H [nsteps, ng] and, with gradient, gb = dL/db
+    (initial state fixed) and gW0 = dL/dW(0)."""
     M = _MeshRef(mesh)
     b, h0, hu0, hv0 = _f64(b), _f64(h0), _f64(hu0), _f64(hv0)
     gelem = np.ascontiguousarray(gelem, dtype=np.int32)

@@ -1364,8 +1364,8 @@ int orc_rhs_vjp(const orc_params *P, const orc_mesh *m, const double *b, const d
     return st;
 }
 
-/* Gauge-misfit loss over nsteps fixed LSRK(5,4) steps of size dt from
- * (h0, hu0, hv0):
+/* Gauge-misfit loss over nsteps fixed steps of size dt from (h0, hu0, hv0),
+ * LSRK(5,4) or SSPRK(3,3) as P->integrator selects:
  *     L = 1/2 sum_{n=1..nsteps} sum_g (H_g(t_n) - target[n-1][g])^2 dt,
  * H_g the water surface h + b interpolated at reference point (xi_g, eta_g)
  * of element gelem[g] with the LGL Lagrange basis.  H_out [nsteps][ng]
@@ -1382,9 +1382,13 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
 {
     int st = check_mesh(m);
     if (st) return st;
-    if (P->av_on || P->integrator != 0 || nsteps < 1 || ng < 0 || !(dt > 0.0))
+    if (P->av_on || P->integrator < 0 || P->integrator > 1 || nsteps < 1 || ng < 0 || !(dt > 0.0))
         return ORC_EINVAL;
     const int N = m->N, n1 = N + 1, np = n1 * n1;
+    /* stages per step: LSRK(5,4) or SSPRK(3,3) (eq. RKSSP) */
+    const int ssp = P->integrator == 1, S = ssp ? 3 : 5;
+    static const double SSP_ALPHA[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double SSP_BETA[3] = {1.0, 0.25, 2.0 / 3.0};
     for (int gg = 0; gg < ng; ++gg)
         if (gelem[gg] < 0 || gelem[gg] >= m->K) return ORC_EINVAL;
     orc_ops op;
@@ -1396,7 +1400,7 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
     /* gauge weights l_i(xi_g) l_j(eta_g) */
     double *gw = malloc(sizeof(double) * (size_t)(ng > 0 ? ng : 1) * np);
     /* every stage input of every step, plus the final state */
-    const int64_t nslot = (int64_t)nsteps * 5 + 1;
+    const int64_t nslot = (int64_t)nsteps * S + 1;
     double *Ws = malloc(sizeof(double) * 3 * n * nslot);
     double *R = malloc(sizeof(double) * 3 * n), *d = malloc(sizeof(double) * 3 * n);
     double *Hg = malloc(sizeof(double) * (size_t)nsteps * (ng > 0 ? ng : 1));
@@ -1418,16 +1422,22 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
         if (!(h0[q] >= P->h_tol)) st = ORC_EINVAL;   /* the initial state must be wet too */
     for (int it = 0; it < nsteps && st == ORC_OK; ++it) {
         memset(d, 0, sizeof(double) * 3 * n);
-        for (int k = 0; k < 5 && st == ORC_OK; ++k) {
-            const int64_t s = (int64_t)it * 5 + k;
+        for (int k = 0; k < S && st == ORC_OK; ++k) {
+            const int64_t s = (int64_t)it * S + k;
             const double *W = Ws + s * 3 * n;
+            const double *Wstep = Ws + (int64_t)it * S * 3 * n;   /* W^n */
             double *Wn = Ws + (s + 1) * 3 * n;
             st = rhs_impl(P, &op, m, &G, b, W, W + n, W + 2 * n, R, R + n, R + 2 * n, NULL, NULL,
                           NULL);
             if (st) break;
-            for (int64_t q = 0; q < 3 * n; ++q) {
-                d[q] = LSRK_A[k] * d[q] + dt * R[q];
-                Wn[q] = W[q] + LSRK_B[k] * d[q];
+            if (ssp) {
+                for (int64_t q = 0; q < 3 * n; ++q)
+                    Wn[q] = SSP_ALPHA[k] * Wstep[q] + SSP_BETA[k] * (W[q] + dt * R[q]);
+            } else {
+                for (int64_t q = 0; q < 3 * n; ++q) {
+                    d[q] = LSRK_A[k] * d[q] + dt * R[q];
+                    Wn[q] = W[q] + LSRK_B[k] * d[q];
+                }
             }
             if (P->limiter_on) {
                 int64_t nl = 0;
@@ -1441,7 +1451,7 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
             }
         }
         if (st) break;
-        const double *W = Ws + ((int64_t)it * 5 + 5) * 3 * n;
+        const double *W = Ws + ((int64_t)it * S + S) * 3 * n;
         for (int gg = 0; gg < ng; ++gg) {
             double H = 0.0;
             for (int p = 0; p < np; ++p) {
@@ -1458,10 +1468,13 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
         if (H_out) memcpy(H_out, Hg, sizeof(double) * (size_t)nsteps * ng);
     }
     if (st == ORC_OK && gb) {
-        /* reverse sweep: a = dL/dW (running), c = dL/d(register) */
+        /* reverse sweep: a = dL/dW (running), c = dL/d(register) for LSRK;
+         * for SSPRK c holds the stage's cotangent and z collects dL/dW^n
+         * from the alpha_k W^n terms */
         double *a = calloc((size_t)(3 * n), sizeof(double));
         double *c = calloc((size_t)(3 * n), sizeof(double));
-        if (!a || !c) st = ORC_ENOMEM;
+        double *z = calloc((size_t)(3 * n), sizeof(double));
+        if (!a || !c || !z) st = ORC_ENOMEM;
         memset(gb, 0, sizeof(double) * n);
         for (int it = nsteps - 1; it >= 0 && st == ORC_OK; --it) {
             /* the loss reads W(t_{it+1}) = h + b at the gauges */
@@ -1473,6 +1486,24 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
                     gb[q] += r * gw[gg * np + p];
                 }
             }
+            const double *lam[3] = {c, c + n, c + 2 * n};
+            double *ga[3] = {a, a + n, a + 2 * n};
+            if (ssp) {
+                /* W_k = alpha_k W^n + beta_k (W_{k-1} + dt R(W_{k-1})):
+                 * dL/dW_{k-1} = beta_k (a + dt (dR/dW)^T a), dL/dW^n += alpha_k a */
+                memset(z, 0, sizeof(double) * 3 * n);
+                for (int k = 2; k >= 0 && st == ORC_OK; --k) {
+                    const double *W = Ws + ((int64_t)it * S + k) * 3 * n;
+                    for (int64_t q = 0; q < 3 * n; ++q) {
+                        z[q] += SSP_ALPHA[k] * a[q];
+                        c[q] = SSP_BETA[k] * a[q];
+                        a[q] = c[q];
+                    }
+                    st = rhs_vjp_acc(P, &op, m, &G, b, W, W + n, W + 2 * n, lam, dt, ga, gb);
+                }
+                for (int64_t q = 0; q < 3 * n; ++q) a[q] += z[q];
+                continue;
+            }
             /* W_k = W_{k-1} + B_k d_k,  d_k = A_k d_{k-1} + dt R(W_{k-1}),
              * with d_{-1} = 0 at the start of the step */
             memset(c, 0, sizeof(double) * 3 * n);
@@ -1480,8 +1511,6 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
                 const int64_t s = (int64_t)it * 5 + k;
                 const double *W = Ws + s * 3 * n;
                 for (int64_t q = 0; q < 3 * n; ++q) c[q] += LSRK_B[k] * a[q];
-                const double *lam[3] = {c, c + n, c + 2 * n};
-                double *ga[3] = {a, a + n, a + 2 * n};
                 st = rhs_vjp_acc(P, &op, m, &G, b, W, W + n, W + 2 * n, lam, dt, ga, gb);
                 for (int64_t q = 0; q < 3 * n; ++q) c[q] *= LSRK_A[k];
             }
@@ -1491,7 +1520,7 @@ int orc_gauge_adjoint(const orc_params *P, const orc_mesh *m, const double *b,
             if (ghu0) memcpy(ghu0, a + n, sizeof(double) * n);
             if (ghv0) memcpy(ghv0, a + 2 * n, sizeof(double) * n);
         }
-        free(a); free(c);
+        free(a); free(c); free(z);
     }
     free(gw); free(Ws); free(R); free(d); free(Hg);
     geom_free(&G);

@@ -7,10 +7,11 @@ mathematics, not against itself:
   in any part fails;
 * the gradient of the total mass rate, which vanishes identically by the
   discrete conservation of Lemma 1, is zero;
-* the gauge-misfit loss and its gradient through LSRK(5,4) steps against a
-  loss assembled independently here (one oracle step at a time, gauges
-  interpolated with a Lagrange basis built from numpy's Legendre roots) and
-  its central differences along random directions in b and in W(0);
+* the gauge-misfit loss and its gradient through LSRK(5,4) and SSPRK(3,3)
+  steps against a loss assembled independently here (one oracle step at a
+  time, gauges interpolated with a Lagrange basis built from numpy's
+  Legendre roots) and its central differences along random directions in b
+  and in W(0);
 * all of the above also on basins with solid walls, whose outside state is
   the mirror of the own trace (the reverse mode runs through the mirror).
 """
@@ -212,12 +213,13 @@ def _loss_by_steps(orc, P, mesh, b, h0, hu0, hv0, steps, dt, gelem, gxi, geta, t
     return L, np.array(Hs)
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
 @pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("flux", [0, 1])
-def test_gauge_loss_and_gradient(orc, flux, walls):
+def test_gauge_loss_and_gradient(orc, flux, walls, integrator):
     mesh, b, H0, db, gelem, gxi, geta, steps = _small_box_case() if walls else _small_case()
     N = mesh.N
-    P = orc.params(N, surface_flux=flux, limiter_on=1)
+    P = orc.params(N, surface_flux=flux, limiter_on=1, integrator=integrator)
     z = np.zeros_like(b)
     dt = 0.5 * orc.dt(P, mesh, b, H0 - b, z, z)[1]
     # target: the same run over the perturbed bed b + db, plus gauge noise
