@@ -271,14 +271,14 @@ const char *esdg_ensemble_last_error(const esdg_ensemble *en);
  * ------------------------------------------------------------------------
  * Reverse mode of the semi-discrete operator R of esdg_rhs (volume term of
  * eqs. fluxDiffFormF, Fmij and volumeFluxes, interface flux of appendix B,
- * source of eq. SourceDisc) and of LSRK(5,4) steps, for gradients with
- * respect to the nodal bathymetry.  The artificial viscosity is frozen at
- * zero (av_on must be 0: ESDG_EINVAL otherwise).  Solid walls are covered:
- * their outside state is a linear mirror of the own trace, and the reverse
- * mode runs through it.  The limiter must not act:
- * on a wet state (h >= h_tol everywhere, so theta = 1 and no velocity is cut
- * off) it is the identity and so is its derivative.  |x| is differentiated
- * as sign(x) with sign(0) = 0.
+ * source of eq. SourceDisc) and of LSRK(5,4) and SSPRK(3,3) steps (eq.
+ * RKSSP), for gradients with respect to the nodal bathymetry.  The
+ * artificial viscosity is frozen at zero (av_on must be 0: ESDG_EINVAL
+ * otherwise).  Solid walls are covered: their outside state is a linear
+ * mirror of the own trace, and the reverse mode runs through it.  The
+ * limiter must not act: on a wet state (h >= h_tol everywhere, so theta = 1
+ * and no velocity is cut off) it is the identity and so is its derivative.
+ * |x| is differentiated as sign(x) with sign(0) = 0.
  */
 
 /* gh, ghu, ghv = (dR/dW)^T lam and gb = (dR/db)^T lam at the current state
@@ -298,13 +298,15 @@ int esdg_gauge_values(esdg_ctx *ctx, double *H, int mem);
 /*
  * Forward sweep of the gauge-misfit loss
  *     L = 1/2 sum_{n=1..nsteps} sum_g (H_g(t_n) - target[n-1][g])^2 dt
- * over nsteps LSRK(5,4) steps of fixed size dt from the current state
- * (integrator must be 0).  target is [nsteps][ng] (mem: 0 host, 1 device);
+ * over nsteps steps of fixed size dt from the current state, LSRK(5,4) or
+ * SSPRK(3,3) as the parameters' integrator selects.  target is [nsteps][ng]
+ * (mem: 0 host, 1 device);
  * *loss (may be NULL) receives L and H (may be NULL) the gauge values
  * [nsteps][ng].  The state is advanced as by esdg_step; the states at steps
  * 0, every, 2 every, ... are kept on the device for esdg_adjoint_backward
- * (ceil(nsteps/every) states, plus 5 every + 1 stage states during the
- * backward sweep).  ESDG_EINVAL if the limiter acted in any stage.
+ * (ceil(nsteps/every) states, plus S every + 1 stage states during the
+ * backward sweep, S = 5 stages per LSRK step, 3 per SSPRK step).
+ * ESDG_EINVAL if the limiter acted in any stage.
  */
 int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const double *target, int mem,
                          double *loss, double *H);

@@ -1,6 +1,6 @@
-// Discrete adjoint (reverse mode) of one inviscid LSRK(5,4) stage, float64.
+// Discrete adjoint (reverse mode) of one inviscid Runge-Kutta stage, float64.
 //
-// The stage computes, per node, d_k = A_k d_{k-1} + dt R(W_{k-1}) and
+// An LSRK(5,4) stage computes, per node, d_k = A_k d_{k-1} + dt R(W_{k-1}) and
 // W_k = W_{k-1} + B_k d_k with R = -(1/J)(L_xi + L_eta - S) (Lemma 1): the
 // split-form volume term with the two-point fluxes of eq. volumeFluxes and
 // the contravariant metric averages of eq. Fmij, the rotated interface flux
@@ -10,7 +10,13 @@
 //     l = c + B_k a                      (dL/dd_k)
 //     a' = a + dt (dR/dW)^T l            (dL/dW_{k-1})
 //     c' = A_k l
-// plus the bathymetry cotangents dt (dR/db)^T l, accumulated in three node
+// The same kernel reverses an SSPRK(3,3) stage (eq. RKSSP),
+// W_k = alpha_k W^n + beta_k (W_{k-1} + dt R(W_{k-1})): with c = 0 and
+// B_k = beta_k, l = beta_k a and dL/dW_{k-1} = beta_k a + dt (dR/dW)^T l (a
+// scaled by sa = beta_k), while co collects the alpha_k a terms of dL/dW^n
+// (A_k = alpha_k / beta_k, added to the running sum y) and the first stage
+// adds that sum to its output (x).  In both schemes the reverse stage adds
+// the bathymetry cotangents dt (dR/db)^T l, accumulated in three node
 // fields: of the split derivatives b_x, b_y (the source is linear in them)
 // and of the face traces of b (the interface flux reads b through the jump
 // of the entropy variables).  bathymetry_adjoint_kernel maps the first two
@@ -128,8 +134,11 @@ struct AdjArgs {
     const double *c[3];            // A_{k+1} dL/dd_{k+1} (nullptr: zero)
     double *ao[3];                 // dL/dW_{k-1}
     double *co[3];                 // A_k dL/dd_k (nullptr: not written)
+    const double *x[3];            // added to ao (nullptr: zero)
+    const double *y[3];            // added to co (nullptr: zero; may alias co)
     double *gbx, *gby, *gbn;       // bathymetry cotangents (accumulated)
     double ca, cb, dt;             // A_k, B_k, step
+    double sa;                     // scale of a in ao (1 for LSRK)
     int64_t ntiles;
 };
 
@@ -289,13 +298,17 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
     const R ghu = R(0.5) * Tu + R(0.25) * P1 * ih + fu * ih;
     const R ghv = R(0.5) * Tv + R(0.25) * P2 * ih + fv * ih;
     const R dt = a.dt;
-    a.ao[0][q] = A0 + dt * gh;
-    a.ao[1][q] = A1 + dt * ghu;
-    a.ao[2][q] = A2 + dt * ghv;
+    R x0 = 0, x1 = 0, x2 = 0;
+    if (a.x[0]) { x0 = a.x[0][q]; x1 = a.x[1][q]; x2 = a.x[2][q]; }
+    a.ao[0][q] = a.sa * A0 + dt * gh + x0;
+    a.ao[1][q] = a.sa * A1 + dt * ghu + x1;
+    a.ao[2][q] = a.sa * A2 + dt * ghv + x2;
     if (a.co[0]) {
-        a.co[0][q] = a.ca * l0;
-        a.co[1][q] = a.ca * l1;
-        a.co[2][q] = a.ca * l2;
+        R y0 = 0, y1 = 0, y2 = 0;
+        if (a.y[0]) { y0 = a.y[0][q]; y1 = a.y[1][q]; y2 = a.y[2][q]; }
+        a.co[0][q] = a.ca * l0 + y0;
+        a.co[1][q] = a.ca * l1 + y1;
+        a.co[2][q] = a.ca * l2 + y2;
     }
     const R hs = R(0.5) * g * h * dt;
     a.gbx[q] += hs * m1;

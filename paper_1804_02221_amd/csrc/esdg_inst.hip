@@ -281,6 +281,8 @@ hipError_t Launch<N, R>::adjoint_stage(const Bufs &B, const AdjCall &c, const Ph
             a.c[k] = (const double *)c.c[k];
             a.ao[k] = (double *)c.ao[k];
             a.co[k] = (double *)c.co[k];
+            a.x[k] = (const double *)c.x[k];
+            a.y[k] = (const double *)c.y[k];
         }
         a.gbx = c.gbx;
         a.gby = c.gby;
@@ -288,6 +290,7 @@ hipError_t Launch<N, R>::adjoint_stage(const Bufs &B, const AdjCall &c, const Ph
         a.ca = c.ca;
         a.cb = c.cb;
         a.dt = c.dt;
+        a.sa = c.sa;
         a.ntiles = ntiles_of<N>(B.K);
         hipExtLaunchKernelGGL((adjoint_stage_kernel<N>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, ev.a, ev.b,
                               0, a);

@@ -64,8 +64,10 @@ struct AdjCall {
     const void *W[3];          // stage input state W_{k-1}
     const void *a[3], *c[3];   // dL/dW_k and A_{k+1} dL/dd_{k+1} (nullptr: zero)
     void *ao[3], *co[3];       // dL/dW_{k-1} and A_k dL/dd_k (co nullptr: not written)
+    const void *x[3], *y[3];   // added to ao and to co (nullptr: zero; y may alias co)
     double *gbx, *gby, *gbn;   // bathymetry cotangents, accumulated
     double ca, cb, dt;         // A_k, B_k and the step
+    double sa = 1.0;           // scale of a in ao (SSPRK: beta_k)
 };
 
 template <int N, typename R>

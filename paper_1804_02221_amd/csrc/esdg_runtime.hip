@@ -189,6 +189,11 @@ struct esdg_ctx {
 
 namespace {
 
+// SSPRK(3,3) in the Shu-Osher form of eq. RKSSP:
+// W_k = alpha_k W^n + beta_k (W_{k-1} + dt R(W_{k-1}))
+constexpr double kSspAlpha[3] = {0.0, 0.75, 1.0 / 3.0};
+constexpr double kSspBeta[3] = {1.0, 0.25, 2.0 / 3.0};
+
 int fail(esdg_ctx *c, int code, const char *fmt, ...)
 {
     if (c) {
@@ -506,7 +511,6 @@ int launch_one_step(esdg_ctx *ctx, double dt, bool with_dt = true)
     const bool av = ctx->P.av_on != 0;
     const bool ssp = ctx->P.integrator == 1;
     const int nst = ssp ? 3 : 5;
-    const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
     // W^n stays untouched in its buffer for the whole step: the stages
     // alternate between the other two (the last one ends in o1), so a retry
     // restarts from it without a copy
@@ -518,7 +522,7 @@ int launch_one_step(esdg_ctx *ctx, double dt, bool with_dt = true)
         const int out = (k % 2 == 0) ? o1 : o2;
         if (av) TRY(launch_viscous(ctx, in, out));
         const bool last = k == nst - 1;
-        StageCall sc = ssp ? StageCall{kModeSsp, av, in, out, base, false, al[k], be[k], last}
+        StageCall sc = ssp ? StageCall{kModeSsp, av, in, out, base, false, kSspAlpha[k], kSspBeta[k], last}
                            : StageCall{kModeLsrk, av, in, out, base, false, kLsrkA[k], kLsrkB[k], last, !last};
         TRY(launch_stage(ctx, sc));
         ctx->eps_valid[out] = av;   // written by the stage epilogue
@@ -1591,17 +1595,21 @@ int copy_state(esdg_ctx *ctx, double *dst, void *const src[3])
     return ESDG_OK;
 }
 
-// One forward LSRK stage from state slot `in` to `out` (the stage kernel of
-// esdg_step, writing the given buffers).
-int adj_forward_stage(esdg_ctx *ctx, double *in, double *out, int k)
+// One forward stage k from state `in` to `out` (the stage kernel of
+// esdg_step, writing the given buffers): LSRK(5,4), or SSPRK(3,3) with the
+// step's start state `base`.
+int adj_forward_stage(esdg_ctx *ctx, double *in, double *out, double *base, int k)
 {
     Bufs B2 = ctx->B;
     const int64_t n = nodes(ctx);
     for (int c = 0; c < 3; ++c) {
         B2.W[0][c] = in + c * n;
         B2.W[1][c] = out + c * n;
+        B2.W[2][c] = base + c * n;
     }
-    StageCall sc{kModeLsrk, false, 0, 1, 0, false, kLsrkA[k], kLsrkB[k], false, k < 4};
+    StageCall sc = ctx->P.integrator == 1
+                       ? StageCall{kModeSsp, false, 0, 1, 2, false, kSspAlpha[k], kSspBeta[k], false, false}
+                       : StageCall{kModeLsrk, false, 0, 1, 0, false, kLsrkA[k], kLsrkB[k], false, k < 4};
     sc.variant = ctx->stage_variant;
     CK(dispatch(ctx, [&](auto L, auto r) {
         using R = decltype(r);
@@ -1764,7 +1772,6 @@ int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const 
     if (!check_adjoint_ctx(ctx)) return ESDG_EINVAL;
     auto &A = ctx->adj;
     if (A.ng < 1) return fail(ctx, ESDG_EINVAL, "esdg_set_gauges first");
-    if (ctx->P.integrator != 0) return fail(ctx, ESDG_EINVAL, "the adjoint covers LSRK(5,4) (integrator 0)");
     if (nsteps < 1 || every < 1 || !(dt > 0.0) || !std::isfinite(dt))
         return fail(ctx, ESDG_EINVAL, "need nsteps >= 1, every >= 1 and a finite dt > 0");
     A.ready = false;
@@ -1820,7 +1827,9 @@ int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, d
     if (!std::isfinite(seed)) return fail(ctx, ESDG_EINVAL, "seed must be finite");
     const int64_t n = nodes(ctx), per = n / ctx->K;
     const int np = (ctx->N + 1) * (ctx->N + 1);
-    TRY(adj_slots(ctx, &A.store, &A.store_cap, (int64_t)std::min(A.every, A.nsteps) * 5 + 1));
+    const bool ssp = ctx->P.integrator == 1;
+    const int S = ssp ? 3 : 5;   // stages per step
+    TRY(adj_slots(ctx, &A.store, &A.store_cap, (int64_t)std::min(A.every, A.nsteps) * S + 1));
     double *lamA[2] = {A.lam, A.lam + 3 * n}, *lamC[2] = {A.lam + 6 * n, A.lam + 9 * n};
     double *gbx = A.gbf, *gby = A.gbf + n, *gbn = A.gbf + 2 * n;
     TRY(fill(ctx, A.gbf, 0.0, 3 * n));
@@ -1836,9 +1845,10 @@ int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, d
         CK(hipMemcpyAsync(A.store, A.ckpt + (int64_t)seg * 3 * n, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
                           ctx->stream));
         for (int it = s0; it < s1; ++it)
-            for (int k = 0; k < 5; ++k) {
-                const int64_t sl = (int64_t)(it - s0) * 5 + k;
-                TRY(adj_forward_stage(ctx, A.store + sl * 3 * n, A.store + (sl + 1) * 3 * n, k));
+            for (int k = 0; k < S; ++k) {
+                const int64_t s = (int64_t)(it - s0) * S, sl = s + k;
+                TRY(adj_forward_stage(ctx, A.store + sl * 3 * n, A.store + (sl + 1) * 3 * n, A.store + s * 3 * n,
+                                      k));
             }
         // reverse the steps of the segment
         for (int it = s1 - 1; it >= s0; --it) {
@@ -1846,6 +1856,34 @@ int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, d
                                A.Hg + (int64_t)it * A.ng, A.Tg + (int64_t)it * A.ng, seed * A.dt, A.ug,
                                A.ug + A.nu, A.ug + 2 * A.nu + 1, A.gw, np, lamA[pa], gbn);
             CK(hipGetLastError());
+            if (ssp) {
+                // dL/dW_{k-1} = beta_k (a + dt (dR/dW)^T a); the alpha_k a
+                // terms of dL/dW^n are summed in lamC[0] and added by stage 0
+                double *z = lamC[0];
+                for (int k = 2; k >= 0; --k) {
+                    const int64_t sl = (int64_t)(it - s0) * 3 + k;
+                    AdjCall c{};
+                    for (int q = 0; q < 3; ++q) {
+                        c.W[q] = A.store + (sl * 3 + q) * n;
+                        c.a[q] = lamA[pa] + q * n;
+                        c.c[q] = nullptr;
+                        c.ao[q] = lamA[1 - pa] + q * n;
+                        c.co[q] = k == 0 ? nullptr : z + q * n;
+                        c.y[q] = k == 1 ? z + q * n : nullptr;
+                        c.x[q] = k == 0 ? z + q * n : nullptr;
+                    }
+                    c.gbx = gbx;
+                    c.gby = gby;
+                    c.gbn = gbn;
+                    c.ca = kSspAlpha[k] / kSspBeta[k];
+                    c.cb = kSspBeta[k];
+                    c.sa = kSspBeta[k];
+                    c.dt = A.dt;
+                    TRY(adj_stage(ctx, c));
+                    pa = 1 - pa;
+                }
+                continue;
+            }
             for (int k = 4; k >= 0; --k) {
                 const int64_t sl = (int64_t)(it - s0) * 5 + k;
                 AdjCall c{};

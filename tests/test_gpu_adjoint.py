@@ -124,11 +124,13 @@ def small_case(N=3, n=5, steps=13, ng=7, seed=3, rot=3):
     return mesh, b, H0, db, gelem, gxi, geta, steps
 
 
-@pytest.mark.parametrize("N,ec,every", [(3, 0, 4), (5, 1, 5), (7, 0, 13)])
-def test_gauge_gradient_parity(esdg, orc, N, ec, every):
+@pytest.mark.parametrize("N,ec,every,integ", [(3, 0, 4, 0), (5, 1, 5, 0), (7, 0, 13, 0), (3, 1, 4, 1),
+                                               (5, 0, 13, 1), (8, 1, 5, 1)])
+def test_gauge_gradient_parity(esdg, orc, N, ec, every, integ):
+    """integ 0: LSRK(5,4), 1: SSPRK(3,3)."""
     mesh, b, H0, db, gelem, gxi, geta, steps = small_case(N=N)
     z = np.zeros_like(b)
-    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, N, surface_flux=ec, limiter_on=1)
+    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, N, surface_flux=ec, limiter_on=1, integrator=integ)
     op = oparams(orc, P)
     dt = 0.5 * orc.dt(op, mesh, b, H0 - b, z, z)[1]
     # target from the oracle's run over b + db (no oracle input from the GPU)
@@ -138,7 +140,7 @@ def test_gauge_gradient_parity(esdg, orc, N, ec, every):
                             np.zeros((steps, len(gelem))), gradient=False)["H"]
     tgt = tgt + 1e-3 * np.random.default_rng(N).standard_normal(tgt.shape)
     ref = orc.gauge_adjoint(op, mesh, b, H0 - b, z, z, steps, dt, gelem, gxi, geta, tgt)
-    print(f"gauge gradient N={N} ec={ec} every={every} steps={steps}", flush=True)
+    print(f"gauge gradient N={N} ec={ec} every={every} steps={steps} integrator={integ}", flush=True)
     s.set_gauges(gelem, gxi, geta)
     loss, H = s.adjoint_forward(steps, dt, every, tgt, want_H=True)
     assert np.abs(H - ref["H"]).max() <= 1e-13 * np.abs(ref["H"]).max()
@@ -153,8 +155,8 @@ def test_gauge_gradient_parity(esdg, orc, N, ec, every):
     s.close()
 
 
-@pytest.mark.parametrize("N,ec,every", [(3, 0, 4), (7, 1, 5)])
-def test_gauge_gradient_parity_with_walls(esdg, orc, N, ec, every):
+@pytest.mark.parametrize("N,ec,every,integ", [(3, 0, 4, 0), (7, 1, 5, 0), (5, 0, 4, 1)])
+def test_gauge_gradient_parity_with_walls(esdg, orc, N, ec, every, integ):
     """A closed basin (walls on both axes): waves from the initial surface
     bump reflect off the walls within the run."""
     mesh = make_box_mesh(N, 5, 5, -2.0, -2.0, 4.0, 4.0, amp=0.1, rotate_seed=N)
@@ -167,7 +169,7 @@ def test_gauge_gradient_parity_with_walls(esdg, orc, N, ec, every):
     gelem = rng.integers(0, mesh.K, ng).astype(np.int32)
     gxi, geta = rng.uniform(-1, 1, ng), rng.uniform(-1, 1, ng)
     z = np.zeros_like(b)
-    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, N, surface_flux=ec, limiter_on=1)
+    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, N, surface_flux=ec, limiter_on=1, integrator=integ)
     op = oparams(orc, P)
     dt = 0.8 * orc.dt(op, mesh, b, H0 - b, z, z)[1]
     tgt = orc.gauge_adjoint(op, mesh, b + db, H0 - b - db, z, z, steps, dt, gelem, gxi, geta,
@@ -185,10 +187,11 @@ def test_gauge_gradient_parity_with_walls(esdg, orc, N, ec, every):
     s.close()
 
 
-def test_checkpoint_interval_is_invisible(esdg):
+@pytest.mark.parametrize("integ", [0, 1])
+def test_checkpoint_interval_is_invisible(esdg, integ):
     mesh, b, H0, db, gelem, gxi, geta, steps = small_case(N=4, steps=11)
     z = np.zeros_like(b)
-    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, 4, limiter_on=1)
+    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, 4, limiter_on=1, integrator=integ)
     s.set_gauges(gelem, gxi, geta)
     dt = 0.5 * s.compute_dt()[1]
     tgt = np.full((steps, len(gelem)), 1.01)
@@ -358,4 +361,57 @@ def test_full_size_gradient(esdg, orc):
     print(f"full size: discharge direction rel err {abs(fd - ad) / abs(ad):.2e}, "
           f"step change {abs(D1 - D2) / abs(ad):.2e}", flush=True)
     assert abs(fd - ad) <= FD_TOL * abs(ad) + abs(D1 - D2), (fd, ad, D1, D2)
+    s.close()
+
+
+def test_ssprk_gradient_in_a_walled_basin_against_differences(esdg):
+    """SSPRK(3,3) steps in a closed basin (walls on both axes, 24 x 24
+    elements, N = 4, 120 steps, checkpoints every 10): the gradient of the
+    gauge misfit against Richardson-extrapolated central differences of the
+    GPU loss along continuous random directions in b, after the waves from
+    the initial surface bump have reached the walls."""
+    N, steps, every = 4, 120, 10
+    mesh = make_box_mesh(N, 24, 24, -2.0, -2.0, 4.0, 4.0, amp=0.1, rotate_seed=4)
+    rng = np.random.default_rng(21)
+    x, y = mesh.x, mesh.y
+    b = 0.25 * np.exp(-((x - 0.6) ** 2 + (y + 0.4) ** 2) / 0.5) + 0.05 * x
+    H0 = 1.0 + 0.05 * np.exp(-((x + 1.2) ** 2 + (y - 1.0) ** 2) / 0.3)
+    db = 0.03 * np.exp(-((x + 0.3) ** 2 + (y + 1.1) ** 2) / 0.4)
+    ng = 12
+    gelem = rng.integers(0, mesh.K, ng).astype(np.int32)
+    gxi, geta = rng.uniform(-1, 1, ng), rng.uniform(-1, 1, ng)
+    z = np.zeros_like(b)
+    s, P = make_solver(esdg, mesh, b, H0 - b, z, z, N, limiter_on=1, integrator=1)
+    s.set_gauges(gelem, gxi, geta)
+    dt = 0.8 * s.compute_dt()[1]
+    s.set_bathymetry(b + db)
+    s.set_state(H0 - b - db, z, z)
+    _, tgt = s.adjoint_forward(steps, dt, every, np.zeros((steps, ng)), want_H=True)
+
+    def loss(bb):
+        s.set_bathymetry(bb)
+        s.set_state(H0 - bb, z, z)
+        return s.adjoint_forward(steps, dt, every, tgt)
+
+    print(f"SSPRK walled basin: {steps} steps to t = {steps * dt:.3f}", flush=True)
+    L0 = loss(b)
+    gb, gh0, _, _ = s.adjoint_backward()
+    gtot = gb - gh0
+    assert L0 > 0
+    # the waves reached the walls: the surface moved at the wall nodes
+    h_end = s.get_state()[0]
+    wall = (np.abs(np.abs(x) - 2.0) < 1e-9) | (np.abs(np.abs(y) - 2.0) < 1e-9)
+    assert np.abs((h_end + b - H0)[wall]).max() > 1e-3
+
+    def richardson(f, eps=1e-4):
+        d1 = (f(eps) - f(-eps)) / (2 * eps)
+        d2 = (f(eps / 2) - f(-eps / 2)) / eps
+        return (4 * d2 - d1) / 3
+
+    for k in range(5):
+        d = mesh.gather(rng.standard_normal((mesh.nx * N, mesh.ny * N)))
+        fd = richardson(lambda e: loss(b + e * d))
+        ad = float(np.sum(gtot * d))
+        print(f"direction {k}: fd {fd:.12e} adjoint {ad:.12e} rel {abs(fd - ad) / abs(ad):.2e}", flush=True)
+        assert abs(fd - ad) <= FD_TOL * abs(ad), (k, fd, ad)
     s.close()
