@@ -59,12 +59,13 @@ struct TileShape {
 };
 
 // Waves per SIMD the stage kernel is compiled for (its register budget) in
-// the FP64 update modes with the default shape: five (N = 7 reaches six by
-// its partner-loop unroll); a few spilled bytes at N = 2, 6 cost less than the
-// occupancy they buy (measured).  No constraint otherwise.
+// the FP64 update modes with the default shape: six at N = 6, five otherwise
+// (N = 7 reaches six by its partner-loop unroll); the few spilled bytes at
+// N = 2, 6 cost less than the occupancy they buy (measured).  No constraint
+// otherwise.
 template <int N, typename R, int MODE, int TT = Shape<N>::T>
 struct StageWaves {
-    static constexpr int value = (sizeof(R) == 8 && MODE != 0 && TT == Shape<N>::T) ? 5 : 1;
+    static constexpr int value = (sizeof(R) == 8 && MODE != 0 && TT == Shape<N>::T) ? (N == 6 ? 6 : 5) : 1;
 };
 
 // Workgroup barrier for exchanges through LDS only: orders LDS accesses
@@ -1037,9 +1038,11 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
         const int base = el * np;
         // partner loops unrolled fully, except at N = 7 (one element per
         // wave), where unrolling by two keeps the kernel at 79 VGPRs and six
-        // waves per SIMD instead of five (5% faster; slower at N <= 6), and
-        // at N = 8, where unrolling by three fits five waves (96 VGPRs, 8%)
-        constexpr int VU = (N == 7 && T == 64) ? 2 : (N == 8 ? 3 : nf);
+        // waves per SIMD instead of five (5% faster; slower at N <= 5), at
+        // N = 6, where it brings six waves within reach of a few spilled
+        // registers (2.5% faster), and at N = 8, where unrolling by three
+        // fits five waves (96 VGPRs, 8%)
+        constexpr int VU = (N == 7 && T == 64) ? 2 : (N == 8 ? 3 : (N == 6 ? 2 : nf));
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
             // the self pair has coefficient 0 (no branch: D~ has a zero diagonal)

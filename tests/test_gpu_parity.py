@@ -287,4 +287,14 @@ def test_error_paths(esdg):
     with pytest.raises(esdg.EsdgError) as ei:
         s.upload_mesh(3, mesh.K, x, mesh.y, mesh.nbr_elem, mesh.nbr_side, mesh.flip)
     assert ei.value.code == esdg.EMESH
+    # an empty mesh and degrees outside 2..8 are refused
+    e0 = np.zeros((0, 16))
+    with pytest.raises(esdg.EsdgError) as ei:
+        s.upload_mesh(3, 0, e0, e0, np.zeros((0, 4), np.int32), np.zeros((0, 4), np.int8), np.zeros((0, 4), np.int8))
+    assert ei.value.code == esdg.EINVAL
+    for N in (1, 9):
+        z = np.zeros((mesh.K, (N + 1) ** 2))
+        with pytest.raises(esdg.EsdgError) as ei:
+            s.upload_mesh(N, mesh.K, z, z, mesh.nbr_elem, mesh.nbr_side, mesh.flip)
+        assert ei.value.code == esdg.EINVAL
     s.close()
