@@ -316,7 +316,8 @@ int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const 
  * initial state held fixed) and, when not NULL, g{h,hu,hv}0 = seed * dL/dW(0).
  * Each segment between checkpoints is recomputed from its checkpoint, then
  * its stages are reversed.  Leaves the current state alone.  ESDG_EINVAL if
- * no forward sweep is recorded or the bathymetry changed since.  (For an
+ * no forward sweep is recorded or the bathymetry or the parameters changed
+ * since.  (For an
  * initial state set through the surface, h(0) = H0 - b, the total gradient
  * is gb - gh0.)
  */

@@ -5,8 +5,9 @@ marshalling only: the forward and reverse sweeps run in the HIP library).
   and bathymetry; its backward is the library's reverse mode of R
   (``esdg_rhs_vjp``).
 * ``GaugeMisfit``: (b, H0, hu0, hv0) -> gauge-misfit loss after nsteps fixed
-  LSRK(5,4) steps from h(0) = H0 - b, hu(0) = hu0, hv(0) = hv0; its backward
-  is the checkpointed reverse sweep (``esdg_adjoint_backward``).
+  steps (LSRK(5,4) or SSPRK(3,3), the solver's integrator) from
+  h(0) = H0 - b, hu(0) = hu0, hv(0) = hv0; its backward is the checkpointed
+  reverse sweep (``esdg_adjoint_backward``).
 
 Both set the solver's bathymetry and state (the solver is an argument, not a
 differentiable input).  Inputs are contiguous float64 CUDA tensors of shape

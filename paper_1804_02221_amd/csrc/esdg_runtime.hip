@@ -184,6 +184,7 @@ struct esdg_ctx {
         double dt = 0.0;
         bool ready = false;        // a forward sweep is recorded
         uint64_t b_version = 0;
+        esdg_params P{};           // the parameters of the recorded sweep
     } adj;
 };
 
@@ -1813,6 +1814,7 @@ int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const 
     A.every = every;
     A.dt = dt;
     A.b_version = ctx->b_version;
+    A.P = ctx->P;
     A.ready = true;
     return ESDG_OK;
 }
@@ -1824,6 +1826,7 @@ int esdg_adjoint_backward(esdg_ctx *ctx, double seed, double *gb, double *gh0, d
     auto &A = ctx->adj;
     if (!A.ready) return fail(ctx, ESDG_EINVAL, "esdg_adjoint_forward first");
     if (A.b_version != ctx->b_version) return fail(ctx, ESDG_EINVAL, "the bathymetry changed since the forward sweep");
+    if (!same_params(A.P, ctx->P)) return fail(ctx, ESDG_EINVAL, "the parameters changed since the forward sweep");
     if (!std::isfinite(seed)) return fail(ctx, ESDG_EINVAL, "seed must be finite");
     const int64_t n = nodes(ctx), per = n / ctx->K;
     const int np = (ctx->N + 1) * (ctx->N + 1);

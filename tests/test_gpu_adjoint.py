@@ -224,6 +224,12 @@ def test_adjoint_argument_errors(esdg):
     s.set_bathymetry(b)                                      # invalidates the sweep
     with pytest.raises(esdg.EsdgError):
         s.adjoint_backward()
+    s.adjoint_forward(2, 1e-3, 1, np.zeros((2, len(gelem))))
+    s.set_params(s.get_params(), integrator=1)               # so does another scheme
+    with pytest.raises(esdg.EsdgError):
+        s.adjoint_backward()
+    s.set_params(s.get_params(), integrator=0)               # the recorded one again
+    s.adjoint_backward()
     s.set_params(s.get_params(), av_on=1, eps0=0.05)
     with pytest.raises(esdg.EsdgError):
         s.rhs_vjp(z, z, z)
