@@ -1031,9 +1031,11 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     // ---- volume: sum_m 2 D_im F~(i,m) + sum_m 2 D_jm G~(j,m) (D~ has a zero
     // diagonal).  Per pair with contravariant direction (A, C):
     //   F1' = s_hu sA + s_hv sC,  F2' = s_u F1' + 2g h h_m sA,  F3' = s_v F1' + 2g h h_m sC
-    // and 2 D F~ = D (F1'/2, F2'/4, F3'/4).
-    R a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0;
-    const R h2g = R(2) * P.g * h;
+    // and 2 D F~ = D (F1'/2, F2'/4, F3'/4).  With s_u = u + u_m the sums split
+    // into the own factors times partner sums, accumulated over both
+    // directions at once:
+    //   sum D F2' = u sum D F1' + sum D F1' u_m + 2g h sum D h_m sA   (F3' alike)
+    R A1 = 0, A2 = 0, A3 = 0, C2 = 0, C3 = 0;
     {
         const int base = el * np;
         // partner loops unrolled fully, except at N = 7 (one element per
@@ -1050,11 +1052,13 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             const R d = s_dz[i * nf + mm];
             const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ax + am.x, sC = Cx + am.y;
-            const R f1 = (hu + qm.x) * sA + (hv + qm.y) * sC;
-            const R pp = h2g * s_h[qq];
-            a1 += d * f1;
-            a2 += d * ((u + wm.x) * f1 + pp * sA);
-            a3 += d * ((v + wm.y) * f1 + pp * sC);
+            const R df = d * ((hu + qm.x) * sA + (hv + qm.y) * sC);
+            const R dh = d * s_h[qq];
+            A1 += df;
+            A2 += df * wm.x;
+            A3 += df * wm.y;
+            C2 += dh * sA;
+            C3 += dh * sC;
         }
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
@@ -1062,14 +1066,17 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             const R d = s_dz[j * nf + mm];
             const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ae + bm.x, sC = Ce + bm.y;
-            const R f1 = (hu + qm.x) * sA + (hv + qm.y) * sC;
-            const R pp = h2g * s_h[qq];
-            b1 += d * f1;
-            b2 += d * ((u + wm.x) * f1 + pp * sA);
-            b3 += d * ((v + wm.y) * f1 + pp * sC);
+            const R df = d * ((hu + qm.x) * sA + (hv + qm.y) * sC);
+            const R dh = d * s_h[qq];
+            A1 += df;
+            A2 += df * wm.x;
+            A3 += df * wm.y;
+            C2 += dh * sA;
+            C3 += dh * sC;
         }
     }
-    R L1 = R(0.5) * (a1 + b1), L2 = R(0.25) * (a2 + b2), L3 = R(0.25) * (a3 + b3);
+    const R h2g = R(2) * P.g * h;
+    R L1 = R(0.5) * A1, L2 = R(0.25) * (u * A1 + A2 + h2g * C2), L3 = R(0.25) * (v * A1 + A3 + h2g * C3);
     lds_sync<T>();   // face slots complete; staging region free from here on
     {
         const int fb = el * 4 * nf;
