@@ -503,6 +503,11 @@ template <typename R>
 __device__ __forceinline__ R viscosity_from_totals(R all, R top, R allM, R topM, R hmax, const Phys<R> &P)
 {
     if (!(hmax > P.h_tol)) return R(0);
+    // smooth elements (both fractions clearly below 10^sigma_min) leave
+    // before the divisions; the margin keeps the decision that of the
+    // quotients below
+    const R pre = R(0.999999) * P.ratio_min;
+    if (!(top > pre * all) && !(topM > pre * allM)) return R(0);
     const R r1 = all > R(0) ? top / all : R(0);
     const R r2 = allM > R(0) ? topM / allM : R(0);
     const R rm = r1 > r2 ? r1 : r2;
