@@ -498,11 +498,12 @@ __device__ __forceinline__ void elem_totals_any(R (&v)[NQ], R *red, int t, int e
 // Artificial viscosity (appendix A, Theorem 1)
 // ------------------------------------------------------------------------
 // Viscosity from the indicator's element totals: modal energy of all modes,
-// of the top shell, of the modes up to N-1 and of shell N-1, and max h.
+// of the top shell, of the modes up to N-1 and of shell N-1; zero for a dry
+// element (no node above h_tol).
 template <typename R>
-__device__ __forceinline__ R viscosity_from_totals(R all, R top, R allM, R topM, R hmax, const Phys<R> &P)
+__device__ __forceinline__ R viscosity_from_totals(R all, R top, R allM, R topM, bool wet, const Phys<R> &P)
 {
-    if (!(hmax > P.h_tol)) return R(0);
+    if (!wet) return R(0);
     // smooth elements (both fractions clearly below 10^sigma_min) leave
     // before the divisions; the margin keeps the decision that of the
     // quotients below
@@ -552,10 +553,20 @@ __device__ R element_viscosity(const R *sh, R *red, const R *vinv, const Phys<R>
     const R q2 = Qh * Qh;
     const int mx = i > j ? i : j;
     // the energy of all modes is the top shell's plus that of the modes up to N-1
-    R vals[4] = {mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0),
-                 lane ? -h : R(3.0e38)};
-    elem_totals_any<N, R, 4, true, T>(vals, red, t, el, p, lane);
-    return viscosity_from_totals<R>(vals[0] + vals[1], vals[0], vals[1], vals[2], -vals[3], P);
+    if constexpr ((np == 64 || np == 16) && T % 64 == 0) {
+        // the element's lanes lie in one wave: its wetness by a ballot
+        // instead of a max reduction of h
+        const uint64_t wm = __ballot(lane && h > P.h_tol);
+        const uint64_t mine = np == 64 ? ~0ull : (0xFFFFull << ((t & 63) - p));
+        R vals[3] = {mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0)};
+        elem_totals_any<N, R, 3, false, T>(vals, red, t, el, p, lane);
+        return viscosity_from_totals<R>(vals[0] + vals[1], vals[0], vals[1], vals[2], (wm & mine) != 0ull, P);
+    } else {
+        R vals[4] = {mx == N ? q2 : R(0), mx <= N - 1 ? q2 : R(0), mx == N - 1 ? q2 : R(0),
+                     lane ? -h : R(3.0e38)};
+        elem_totals_any<N, R, 4, true, T>(vals, red, t, el, p, lane);
+        return viscosity_from_totals<R>(vals[0] + vals[1], vals[0], vals[1], vals[2], -vals[3] > P.h_tol, P);
+    }
 }
 
 // Copy V^{-1} (row stride N+1) into LDS; ordered by the caller's next barrier.
