@@ -380,6 +380,24 @@ def main():
         s.set_state(w.h, w.hu, w.hv)
         K = w.mesh.K
         nodes = K * (N + 1) ** 2
+        err32 = None
+        if precision == 32:
+            # the FP32 right-hand side against the FP64 one (the same library in
+            # FP64, parity-checked against the oracle) at the initial state
+            r32 = s.rhs(device=True)
+            s64 = esdg.Solver(dev, 64, stream=stream)
+            s64.upload_mesh(w.mesh)
+            s64.set_params(P)
+            s64.set_bathymetry(w.b)
+            s64.set_state(w.h, w.hu, w.hv)
+            r64 = s64.rhs(device=True)
+            s64.close()
+            err32 = {"max_abs_over_max": [float((a - b).abs().max() / b.abs().max()) for a, b in zip(r32, r64)],
+                     "l2_relative": [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                                     for a, b in zip(r32, r64)],
+                     "fields": ["h", "hu", "hv"], "state": "initial state of the workload"}
+            del r32, r64
+            log(f"FP32 rhs vs FP64: max-abs / max {max(err32['max_abs_over_max']):.2e}")
         log(f"uploaded K={K} nodes={nodes}; warmup {warmup} steps")
         s.step(warmup, 0.0)
         choice, tune_ms = s.autotune(5) if args.autotune else (0, None)
@@ -418,6 +436,8 @@ def main():
                    roofline_frac=achieved / HBM_PEAK_GBS,
                    av_ms_per_stage=prof["av_ms"] / (5 * steps),
                    av_launches=prof["av_launches"])
+        if err32 is not None:
+            res["fp32_vs_fp64_rhs"] = err32
         s.close()
         del w
         return res
@@ -457,7 +477,7 @@ def main():
         sweep.append({k: r[k] for k in keys})
     if args.fp32_check and args.precision == 64:
         r = run(args.N, precision=32, steps=args.sweep_steps, warmup=2)
-        sweep.append({k: r[k] for k in keys})
+        sweep.append({k: r[k] for k in keys + ("fp32_vs_fp64_rhs",) if k in r})
 
     ens = None
     if members:
