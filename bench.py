@@ -349,8 +349,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the halo-exchange design for several GPUs is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(the halo exchange over several GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 

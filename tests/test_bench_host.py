@@ -1,0 +1,36 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic byte count of a
+stage-kernel launch against a count written out here from its definition,
+and the refusal of a run on more than one GPU."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_stage_bytes_counts_each_datum_once():
+    N, K, rb = 7, 3, 8
+    npn = (N + 1) ** 2
+    for k in range(5):
+        reads = 3 + (3 if k > 0 else 0) + 4 + 2          # W, dU (not on the first stage), metric, b_x b_y
+        writes = 3 + (3 if k < 4 else 0)                 # W, dU (not on the last stage)
+        per_elem = 4 * (N + 1) + 1                       # face bathymetry, viscosity
+        want = ((reads + writes) * npn * K + per_elem * K) * rb
+        assert bench.stage_bytes(N, K, True, rb, k) == want
+        assert bench.stage_bytes(N, K, False, rb, k) == want - K * rb
+    # viscous elements add their face fluxes and viscous terms
+    extra = bench.stage_bytes(N, K, True, rb, 2, n_visc=2) - bench.stage_bytes(N, K, True, rb, 2)
+    assert extra == (16 * (N + 1) + 2 * npn) * 2 * rb
+    # about 139 bytes per node on average over the five stages at N = 7 in FP64
+    avg = sum(bench.stage_bytes(N, 262144, True, 8, k) for k in range(5)) / 5 / (262144 * npn)
+    assert abs(avg - 138.53) < 0.01
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
