@@ -438,6 +438,28 @@ def dry_dam_break(n: int = 50, N: int = 3) -> Workload:
                          max_dt_retries=3))
 
 
+def three_mound_dam_break(nx: int = 150, ny: int = 100, N: int = 3) -> Workload:
+    """The paper's dam break over three mounds: [0,75] x [0,45] (the domain as
+    the paper states it), nx x ny Cartesian elements, solid walls on all four
+    sides; h = 1.875 where x < 16 (the dam sits on the element interface
+    x = 16 at the paper's mesh, whose nodes take the dry side, as the strict
+    inequality reads), else dry; at rest; bed b = max(0, M1, M2, M3) with the
+    cones M1 = 1 - 0.1 |x - (30, 22.5)|, M2 = 1 - 0.1 |x - (30, 7.5)|,
+    M3 = 2.8 - 0.28 |x - (47.5, 15)|; eps0 = 0.2, g = 9.81, AV and limiter
+    on, SSPRK(3,3) with step halving as in dry_dam_break."""
+    mesh = make_box_mesh(N, nx, ny, 0.0, 0.0, 75.0, 45.0, walls_x=True, walls_y=True)
+    x, y = mesh.x, mesh.y
+    m1 = 1.0 - 0.1 * np.sqrt((x - 30.0) ** 2 + (y - 22.5) ** 2)
+    m2 = 1.0 - 0.1 * np.sqrt((x - 30.0) ** 2 + (y - 7.5) ** 2)
+    m3 = 2.8 - 0.28 * np.sqrt((x - 47.5) ** 2 + (y - 15.0) ** 2)
+    b = np.maximum(np.maximum(0.0, m1), np.maximum(m2, m3))
+    h = np.where(x < 16.0, 1.875, 0.0)
+    z = np.zeros_like(h)
+    return Workload(f"three_mound_dam_break_{nx}x{ny}_N{N}", mesh, _c(b), _c(h), _c(z.copy()), _c(z.copy()),
+                    dict(g=9.81, surface_flux=0, av_on=1, limiter_on=1, eps0=0.2, cfl=0.5, integrator=1,
+                         max_dt_retries=3))
+
+
 def random_states(rng: np.random.Generator, n: int, dry_fraction: float = 0.0,
                   hmax: float = 2.0, umax: float = 1.0):
     """Independent random point states (h, hu, hv, b) for flux-level tests."""
