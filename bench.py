@@ -266,14 +266,16 @@ def paper_cases_bench(esdg, dev, stream):
     the adaptive step: the oscillating lake (200x200, N=3) to T/6 with its
     error against the closed form, the dry dam break (50x50, N=3) to t=1 and
     the dam break over three mounds (150x100, N=3) to t=10 (~25000 steps;
-    the paper shows it up to t=50) with their mass drift and entropy change."""
+    the paper shows it up to t=50) and the run-up on a conical island
+    (50x50, N=3) to t=50, with their mass drift and entropy change."""
     import torch
-    from paper_1804_02221_amd.inputs import dry_dam_break, oscillating_lake, three_mound_dam_break
+    from paper_1804_02221_amd.inputs import conical_island, dry_dam_break, oscillating_lake, three_mound_dam_break
     out = {}
     g = 9.81
     for name, w, t_end in (("oscillating_lake", oscillating_lake(200, 3), 2 * np.pi / np.sqrt(2 * g * 0.1) / 6),
                            ("dry_dam_break", dry_dam_break(50, 3), 1.0),
-                           ("three_mound_dam_break", three_mound_dam_break(150, 100, 3), 10.0)):
+                           ("three_mound_dam_break", three_mound_dam_break(150, 100, 3), 10.0),
+                           ("conical_island", conical_island(50, 50, 3), 50.0)):
         s = esdg.Solver(dev, 64, stream=stream)
         s.upload_mesh(w.mesh)
         s.set_params(esdg.default_params(3, **w.params))

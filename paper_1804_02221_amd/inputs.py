@@ -460,6 +460,30 @@ def three_mound_dam_break(nx: int = 150, ny: int = 100, N: int = 3) -> Workload:
                          max_dt_retries=3))
 
 
+def conical_island(nx: int = 50, ny: int = 50, N: int = 3) -> Workload:
+    """The paper's solitary-wave run-up on a conical island: [0,25] x [0,30],
+    nx x ny Cartesian elements, solid walls everywhere; still water of depth
+    h0 = 0.32 with a solitary wave of amplitude A = 0.064 centred at x = 2.5,
+    eta = A sech^2(gamma (x - 2.5)) with gamma = sqrt(3 A / (4 h0^3)) (the
+    paper prints the same wave in lengths scaled by h0), u = eta sqrt(g / h0),
+    v = 0; the island b = 0.93 (1 - r / 3.6) for r <= 3.6 around (12.5, 15),
+    else 0, and h = max(0, h0 + eta - b); eps0 = 0.1, g = 9.81, AV and
+    limiter on, SSPRK(3,3) with step halving as in dry_dam_break."""
+    mesh = make_box_mesh(N, nx, ny, 0.0, 0.0, 25.0, 30.0, walls_x=True, walls_y=True)
+    x, y = mesh.x, mesh.y
+    g, h0, A = 9.81, 0.32, 0.064
+    gam = np.sqrt(3.0 * A / (4.0 * h0 ** 3))
+    eta = A / np.cosh(gam * (x - 2.5)) ** 2
+    r = np.sqrt((x - 12.5) ** 2 + (y - 15.0) ** 2)
+    b = np.where(r <= 3.6, 0.93 * (1.0 - r / 3.6), 0.0)
+    h = np.maximum(0.0, h0 + eta - b)
+    u = np.where(h > 0.0, eta * np.sqrt(g / h0), 0.0)
+    z = np.zeros_like(h)
+    return Workload(f"conical_island_{nx}x{ny}_N{N}", mesh, _c(b), _c(h), _c(h * u), _c(z),
+                    dict(g=g, surface_flux=0, av_on=1, limiter_on=1, eps0=0.1, cfl=0.5, integrator=1,
+                         max_dt_retries=3))
+
+
 def random_states(rng: np.random.Generator, n: int, dry_fraction: float = 0.0,
                   hmax: float = 2.0, umax: float = 1.0):
     """Independent random point states (h, hu, hv, b) for flux-level tests."""

@@ -131,3 +131,26 @@ def test_oscillating_lake_against_closed_form(orc):
     print("relative L1 errors", e1, e2)
     assert e2 < 0.06
     assert e2 < 0.7 * e1
+
+
+def test_three_mound_dam_break_coarse(orc):
+    """The dam break over three mounds on a 15 x 10 mesh, 20 adaptive
+    SSPRK(3,3) steps: the bed is the maximum of the three cones (apex heights
+    1, 1, 2.8 at their centres), no mass is gained or lost in the closed
+    basin, no height turns negative and the total entropy decreases."""
+    from paper_1804_02221_amd.inputs import three_mound_dam_break
+    w = three_mound_dam_break(15, 10, 3)
+    x, y = w.mesh.x, w.mesh.y
+    cone = lambda a, s, cx, cy: a - s * np.hypot(x - cx, y - cy)
+    want = np.maximum.reduce([np.zeros_like(x), cone(1, 0.1, 30, 22.5), cone(1, 0.1, 30, 7.5),
+                              cone(2.8, 0.28, 47.5, 15)])
+    assert np.abs(w.b - want).max() <= 1e-14
+    assert (w.mesh.nbr_elem < 0).sum() == 2 * (15 + 10)
+    P = orc.params(3, **w.params)
+    d0 = orc.diagnostics(P, w.mesh, w.b, w.h, w.hu, w.hv)
+    h, hu, hv, t, st = orc.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 20, 0.0)
+    assert st == 0 and t > 0
+    d1 = orc.diagnostics(P, w.mesh, w.b, h, hu, hv)
+    assert abs(d1[0] - d0[0]) <= 1e-13 * d0[0]
+    assert h.min() >= 0.0
+    assert d1[3] < d0[3]
