@@ -154,3 +154,24 @@ def test_three_mound_dam_break_coarse(orc):
     assert abs(d1[0] - d0[0]) <= 1e-13 * d0[0]
     assert h.min() >= 0.0
     assert d1[3] < d0[3]
+
+
+def test_conical_island_initial_state(orc):
+    """The island case's initial data against its closed forms: the cone's
+    apex height and radius, the solitary wave's crest A above h0 at x = 2.5
+    with the long-wave speed sqrt(g/h0) in its discharge, a dry island top,
+    and 20 adaptive steps on a 10 x 12 mesh that keep the mass and h >= 0."""
+    from paper_1804_02221_amd.inputs import conical_island
+    w = conical_island(10, 12, 3)
+    x, y = w.mesh.x, w.mesh.y
+    r = np.hypot(x - 12.5, y - 15.0)
+    assert np.abs(w.b - np.where(r <= 3.6, 0.93 * (1 - r / 3.6), 0.0)).max() <= 1e-15
+    crest = np.abs(x - 2.5) < 1e-12
+    assert crest.any() and np.allclose(w.h[crest], 0.32 + 0.064, rtol=0, atol=1e-14)
+    assert np.allclose(w.hu[crest], w.h[crest] * 0.064 * np.sqrt(9.81 / 0.32), rtol=1e-14)
+    assert (w.h[w.b > 0.4] == 0).all() and (w.hv == 0).all()
+    P = orc.params(3, **w.params)
+    d0 = orc.diagnostics(P, w.mesh, w.b, w.h, w.hu, w.hv)
+    h, hu, hv, t, st = orc.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 20, 0.0)
+    d1 = orc.diagnostics(P, w.mesh, w.b, h, hu, hv)
+    assert st == 0 and abs(d1[0] - d0[0]) <= 1e-13 * d0[0] and h.min() >= 0.0
