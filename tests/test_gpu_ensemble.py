@@ -72,17 +72,20 @@ def walled_box(N, nx, ny, wx, wy, rot, seed):
                     h * 0.2 * np.sin(0.8 * y + c[5]), {})
 
 
-def test_ensemble_with_walls_equals_single_instances(esdg):
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_ensemble_with_walls_equals_single_instances(esdg, integrator):
     """Walled boxes (walls on one or both axes) batched with periodic meshes of
-    the same degrees: each instance matches its own solve bitwise."""
+    the same degrees, LSRK(5,4) or SSPRK(3,3): each instance matches its own
+    solve bitwise."""
     ws = [walled_box(3, 5, 4, True, True, 2, 21), dam_break(4, 3, seed=22, rotate_seed=1),
           walled_box(5, 4, 6, True, False, None, 23), smooth_sweep(3, 5, seed=24),
           walled_box(3, 6, 3, False, True, 5, 25), walled_box(7, 3, 3, True, True, 7, 26)]
+    kw = dict(COMMON, integrator=integrator)
     ens = esdg.Ensemble(0, 64)
-    ids = [ens.add_workload(w, **COMMON) for w in ws]
+    ids = [ens.add_workload(w, **kw) for w in ws]
     ens.step(3)
     for w, i in zip(ws, ids):
-        ref, t_ref = single(esdg, w, 3, **COMMON)
+        ref, t_ref = single(esdg, w, 3, **kw)
         got = ens.get_state(i)
         print(f"instance {i} N={w.mesh.N} {w.name}", flush=True)
         for c in range(3):
