@@ -646,8 +646,8 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
                     if (s == 0) L[c][p] -= Fcontra / op->w[0];   /* - G~*_i0 / w_0 */
                 }
             }
-        /* --- source (eq. SourceDisc) with S^{.,*} = 0 (continuous b) and the
-         * split-form bathymetry derivatives.  Readings: the split derivative
+        /* --- source (eq. SourceDisc): the split-form bathymetry derivatives
+         * and the interface penalty S^{.,*}.  Readings: the split derivative
          * carries D (the printed 2D doubles it: lake at rest then fails), and
          * b_y follows the chain rule J b_y = -x_eta b_xi + x_xi b_eta. */
         for (int i = 0; i <= N; ++i)
@@ -667,6 +667,36 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
                 double by = -G->xeta[o + p] * Db_xi - Dxb_xi + G->xxi[o + p] * Db_eta + Dxb_eta;
                 Sx[p] = 0.5 * g * (-h[o + p] * bx);
                 Sy[p] = 0.5 * g * (-h[o + p] * by);
+            }
+        /* Interface penalty S^{x,*}, S^{y,*} of eq. SourceDisc for a bottom
+         * that jumps across a face (the paper defers its form to its earlier
+         * work).  Reading, derived here from Lemma 1.3 and 1.2: at every face
+         * node, with the element's own outward unit normal n and the surface
+         * Jacobian of eq. SurfJac,
+         *     S^{.,*} = -(1/w_0) J^surf {h} [[b]] n,   [[b]] = b_nbr - b_own,
+         * entering S as (g/2) S^{.,*}.  At rest (h + b constant, u = 0) the
+         * interface flux leaves (1/w_0) J^surf (g/2) {h}[[h]] n in L, which
+         * this term cancels ([[h]] = -[[b]]); and it adds -g {h}[[b]]{u.n}
+         * J^surf per face node to the entropy rate, cancelling the g[[b]]F_1
+         * term of the Tadmor condition of the EC flux.  Zero where b is
+         * continuous and at solid walls (the wall's outside bottom is the
+         * element's own). */
+        for (int s = 0; s < 4; ++s)
+            for (int k = 0; k <= N; ++k) {
+                int i, j;
+                side_node(N, s, k, &i, &j);
+                int p = i * n1 + j;
+                int64_t q = o + p, qn = nbr_node(m, e, s, k);
+                double jb = b[qn] - b[q];
+                if (jb == 0.0) continue;
+                double snx, sny;
+                scaled_normal(G, s, q, &snx, &sny);
+                double Js = sqrt(snx * snx + sny * sny);
+                double avg_h = 0.5 * (h[q] + h[qn]);
+                double sxs = -(Js / op->w[0]) * avg_h * jb * (snx / Js);
+                double sys = -(Js / op->w[0]) * avg_h * jb * (sny / Js);
+                Sx[p] += 0.5 * g * sxs;
+                Sy[p] += 0.5 * g * sys;
             }
         /* --- viscous divergence (Theorem 1, eq. ViscTermsDisc) on the
          * momentum rows: D applied to the contravariant viscous fluxes plus
@@ -925,7 +955,7 @@ int orc_dt(const orc_params *P, const orc_mesh *m, const double *b, const double
 /* Time integration                                                          */
 /* ------------------------------------------------------------------------ */
 /* Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage RK, the
- * low-storage scheme of the paper's earlier work (section 2.3). */
+ * low-storage scheme of the paper's earlier work (section 2.2, before eq. RKSSP). */
 static const double LSRK_A[5] = {0.0, -567301805773.0 / 1357537059087.0,
                                  -2404267990393.0 / 2016746695238.0,
                                  -3550918686646.0 / 2091501179385.0,
@@ -1334,6 +1364,29 @@ static int rhs_vjp_acc(const orc_params *P, const orc_ops *op, const orc_mesh *m
                     gb[o + pb] += op->D[j][mm] * (Db_eta_bar + G->yxi[o + pb] * Dyb_eta_bar +
                                                   G->xxi[o + pb] * Dxb_eta_bar);
                 }
+            }
+        /* interface penalty of rhs_impl, S += (g/2) c {h} [[b]] with
+         * c = -(J^surf/w_0) n per component: linear in [[b]] and in {h}, so
+         * its partials are taken where [[b]] = 0 too */
+        for (int s = 0; s < 4; ++s)
+            for (int k = 0; k <= N; ++k) {
+                int i, j;
+                side_node(N, s, k, &i, &j);
+                int p = i * n1 + j;
+                int64_t q = o + p, qn = nbr_node(m, e, s, k);
+                double snx, sny;
+                scaled_normal(G, s, q, &snx, &sny);
+                double Js = sqrt(snx * snx + sny * sny);
+                double cx = 0.5 * g * (-(Js / op->w[0]) * (snx / Js));
+                double cy = 0.5 * g * (-(Js / op->w[0]) * (sny / Js));
+                double avg_h = 0.5 * (h[q] + h[qn]), jb = b[qn] - b[q];
+                double sx_bar = -mu[1][p], sy_bar = -mu[2][p];
+                double avg_bar = (sx_bar * cx + sy_bar * cy) * jb;
+                double jb_bar = (sx_bar * cx + sy_bar * cy) * avg_h;
+                gw[0][q] += 0.5 * avg_bar;
+                gw[0][qn] += 0.5 * avg_bar;
+                gb[qn] += jb_bar;
+                gb[q] -= jb_bar;
             }
     }
     return ORC_OK;
