@@ -56,6 +56,49 @@ def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_v
     return (per_node * n + per_elem * K + visc) * real_bytes
 
 
+def rhs_bytes(N: int, K: int, av: bool, real_bytes: int, n_visc: int = 0) -> float:
+    """Algorithmic HBM bytes of one right-hand-side evaluation (the stage
+    kernel in its RHS form): reads W (3/node), metric directions (4/node),
+    split bathymetry derivatives (2/node), face bathymetry (4(N+1)/element),
+    with AV the element viscosity and the viscous-element terms as in
+    stage_bytes; writes R (3/node)."""
+    nf = N + 1
+    np_ = nf * nf
+    visc = (16 * nf + 2 * np_) * n_visc if av else 0
+    return ((3 + 4 + 2 + 3) * K * np_ + (4 * nf + (1 if av else 0)) * K + visc) * real_bytes
+
+
+def av_faces_bytes(N: int, n_visc: int, real_bytes: int) -> float:
+    """Algorithmic bytes of the BR1 face-flux pass over n_visc viscous
+    elements: per element it reads W (3 (N+1)^2), the neighbours' traces at
+    its 4(N+1) face nodes (3 each), the metric directions at its face nodes
+    (4 each), its viscosity and face map (4 x (4 + 1) bytes); it writes the
+    four viscous flux components at its face nodes (16 (N+1))."""
+    nf = N + 1
+    return n_visc * ((3 * nf * nf + 12 * nf + 16 * nf + 1 + 16 * nf) * real_bytes + 20)
+
+
+def av_div_bytes(N: int, n_visc: int, real_bytes: int) -> float:
+    """Algorithmic bytes of the viscous-divergence pass: per viscous element
+    W (3 (N+1)^2), neighbour traces (12 (N+1)), metric directions
+    (4 (N+1)^2), its own and its neighbours' viscosity (5), the neighbours'
+    face fluxes (16 (N+1)), the face map; writes L^v (2 (N+1)^2)."""
+    nf = N + 1
+    np_ = nf * nf
+    return n_visc * ((3 * np_ + 12 * nf + 4 * np_ + 5 + 16 * nf + 2 * np_) * real_bytes + 20)
+
+
+def dt_pass_bytes(N: int, K: int, av: bool, real_bytes: int) -> float:
+    """Algorithmic bytes of the time-step pass after a step (the last stage
+    left each element's CFL and viscous bounds): the per-element bounds
+    (1 or 2/element), and for the Lemma 2 bounds at every face node the face
+    geometry (unit normal and w_0 J/J^surf: 3 per face node) and the state
+    at the element's 4N distinct face nodes (3 each; the neighbour trace is
+    another element's face node), plus the face map (5 bytes per side)."""
+    nf = N + 1
+    return K * (((2 if av else 1) + 12 * nf + 12 * N) * real_bytes + 20)
+
+
 def stage_flops(N: int, av: bool) -> float:
     """Algorithmic FP64 FLOPs per node of one stage (operation count of the
     method, not of this implementation): the volume term 2(N+1) partner pairs
@@ -311,19 +354,127 @@ def paper_cases_bench(esdg, dev, stream):
     return out
 
 
+def host_threads() -> int:
+    """Host threads the oracle may use: the CPU share this process has (the
+    OpenMP setting when given, else the CPUs it may run on)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(N: int, n_patch: int):
+    """The CPU oracle (test infrastructure, never tuned) on a bounded sample
+    of the timed workload: one full LSRK(5,4) step and one right-hand side on
+    an n_patch^2-element patch of the same recipe, with all the host threads
+    it has and with one."""
     import oracle
     from paper_1804_02221_amd.inputs import smooth_sweep
     w = smooth_sweep(n_patch, N, seed=3)
     P = oracle.params(N, av_on=1, limiter_on=1, eps0=0.025)
-    t0 = time.perf_counter()
-    oracle.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
-    el = time.perf_counter() - t0
     nodes = w.mesh.K * (N + 1) ** 2
-    return dict(value=nodes * 5 / el, unit="DOF-updates/s", cores=1, kind="oracle",
-                sample=f"one LSRK(5,4) step (5 stages, AV + limiter + adaptive dt) on a "
-                       f"{n_patch}x{n_patch}-element patch of the same recipe, N={N} "
-                       f"({nodes} nodes), single thread, {el:.1f} s")
+    threads = host_threads()
+    out = {}
+    for label, nt in (("all", threads), ("one", 1)):
+        oracle.set_threads(nt)
+        t0 = time.perf_counter()
+        oracle.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
+        t_step = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.rhs(P, w.mesh, w.b, w.h, w.hu, w.hv)
+        t_rhs = time.perf_counter() - t0
+        out[label] = (t_step, t_rhs)
+        log(f"CPU oracle, {nt} thread(s): step {t_step:.2f} s, rhs {t_rhs:.2f} s")
+    oracle.set_threads(threads)
+    t_step, t_rhs = out["all"]
+    return dict(value=nodes * 5 / t_step, unit="DOF-updates/s", cores=threads, kind="oracle",
+                sample=(f"one LSRK(5,4) step (5 stages, AV + limiter + adaptive dt) on a {n_patch}x{n_patch}-"
+                        f"element patch of the same recipe, N={N} ({nodes} nodes), {threads} OpenMP threads "
+                        f"over elements, {t_step:.2f} s"),
+                cpu_model=cpu_model(),
+                rhs_only={"value": nodes / t_rhs, "unit": "DOF/s (one right-hand side)", "seconds": t_rhs},
+                single_thread={"value": nodes * 5 / out["one"][0], "step_seconds": out["one"][0],
+                               "rhs_value": nodes / out["one"][1], "rhs_seconds": out["one"][1], "cores": 1})
+
+
+def kernel_times(prof, steps: int):
+    """ms per step of each timed kernel class (profile_read_kernels)."""
+    return {k: {"ms_per_step": ms / steps, "launches": n, "mean_launch_ms": ms / n if n else 0.0}
+            for k, (ms, n) in prof.items() if n}
+
+
+def dam_break_bench(esdg, dev, stream, steps: int, warmup: int):
+    """The curvilinear wet/dry dam break (128x128 elements, N=7, AV with
+    eps0=0.025, limiter, LSRK(5,4), adaptive step): the hot path with its
+    non-smooth parts active.  Reports the stage kernel (bytes including the
+    viscous elements' terms), the two viscosity passes and the time-step
+    pass against the HBM peak, the viscous and limited counts."""
+    import torch
+    from paper_1804_02221_amd.inputs import dam_break
+    w = dam_break(128, 7)
+    N, K = 7, w.mesh.K
+    nodes = K * (N + 1) ** 2
+    s = esdg.Solver(dev, 64, stream=stream)
+    s.upload_mesh(w.mesh)
+    s.set_params(esdg.default_params(N, **w.params))
+    s.set_bathymetry(w.b)
+    s.set_state(w.h, w.hu, w.hv)
+    s.step(warmup, 0.0)
+    _, v0 = s.step_stats()
+    s.profile(True)
+    s.profile_read_kernels()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_sim, _ = s.step(steps, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = s.profile_read_kernels()
+    s.profile(False)
+    limited, v1 = s.step_stats()
+    d = s.diagnostics()
+    s.close()
+    n_visc = 0.5 * (v0 + v1)
+    st_ms, st_n = prof["stage"]
+    stage_b = sum(stage_bytes(N, K, True, 8, k, int(round(n_visc))) for k in range(5)) / 5
+    res = dict(workload=("curvilinear wet/dry dam break, 128x128 elements of [0,10]^2, N=7, 8-Gaussian bottom, "
+                         "AV eps0=0.025 + limiter, ES flux, LSRK(5,4), adaptive dt (CFL, viscous, Lemma 2)"),
+               nodes=nodes, steps=steps, warmup=warmup, t_sim=t_sim, min_h=d[5],
+               value=nodes * 5 * steps / el, unit="DOF-updates/s", ms_per_step=el * 1e3 / steps,
+               viscous_elements={"before": v0, "after": v1}, limited_element_stages=limited,
+               kernels=kernel_times(prof, steps))
+    rl = {}
+    if st_n:
+        t = st_ms / st_n * 1e-3
+        rl["stage_kernel"] = {"bytes_per_launch": stage_b, "GBs": stage_b / t / 1e9,
+                              "frac": stage_b / t / 1e9 / HBM_PEAK_GBS}
+    for k, fn in (("av_faces", av_faces_bytes), ("av_div", av_div_bytes)):
+        ms, n = prof[k]
+        if n:
+            b = fn(N, n_visc, 8)
+            rl[k + "_kernel"] = {"bytes_per_launch": b, "GBs": b / (ms / n * 1e-3) / 1e9,
+                                 "frac": b / (ms / n * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "note": "bytes of the listed viscous elements only (mean count)"}
+    ms, n = prof["dt"]
+    if n:
+        b = dt_pass_bytes(N, K, True, 8)
+        rl["dt_pass"] = {"bytes_per_launch": b, "GBs": b / (ms / n * 1e-3) / 1e9,
+                         "frac": b / (ms / n * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    res["roofline"] = rl
+    return res
 
 
 def main():
@@ -337,20 +488,24 @@ def main():
     ap.add_argument("--no-av", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-patch", type=int, default=256)
-    ap.add_argument("--sweep", default="3,4,5,6,8",
+    ap.add_argument("--sweep", default="2,3,4,5,6,8",
                     help="comma list of further N values to time on the same mesh ('' for none)")
     ap.add_argument("--sweep-steps", type=int, default=10)
-    ap.add_argument("--fp32-check", type=int, default=1,
-                    help="also time the main N in FP32 (reported beside, not as value)")
+    ap.add_argument("--fp32-sweep", type=int, default=1,
+                    help="also time FP32 at the main N and every sweep N, with its error against FP64")
+    ap.add_argument("--rhs-reps", type=int, default=10, help="right-hand-side evaluations timed per N")
+    ap.add_argument("--dam-break", type=int, default=1,
+                    help="time the 128^2 N=7 wet/dry dam break (AV and limiter active)")
+    ap.add_argument("--dam-break-steps", type=int, default=100)
     ap.add_argument("--ensemble", type=int, default=64,
                     help="instances of the batched-ensemble comparison (0: skip)")
-    ap.add_argument("--ensemble-steps", type=int, default=5)
+    ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--adjoint", type=int, default=1,
                     help="time the bathymetry-gradient adjoint (128^2 elements, N=5, 400 steps)")
-    ap.add_argument("--paper-cases", type=int, default=1,
+    ap.add_argument("--paper-cases", type=int, default=0,
                     help="run the walled test cases (oscillating lake, dry dam break) at their resolutions")
     ap.add_argument("--autotune", type=int, default=1,
-                    help="pick the stage-kernel workgroup size per run with the library's autotuner")
+                    help="pick the stage-kernel tile per run with the library's autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -363,7 +518,7 @@ def main():
     if args.ensemble > 0:
         log(f"generating the {args.ensemble}-instance ensemble on the host")
         t0 = time.perf_counter()
-        members = generate_ensemble(ensemble_specs(args.ensemble), min(16, os.cpu_count() or 1))
+        members = generate_ensemble(ensemble_specs(args.ensemble), min(16, host_threads()))
         log(f"ensemble generated in {time.perf_counter() - t0:.1f} s")
 
     import torch
@@ -374,9 +529,7 @@ def main():
     dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream()
 
-    def run(N, precision=args.precision, steps=args.steps, warmup=args.warmup):
-        log(f"generating {args.n}x{args.n} workload at N={N} (FP{precision})")
-        w = smooth_sweep(args.n, N, seed=3)
+    def run(w, N, precision, steps, warmup, rhs_reps, fp64_rhs=None):
         s = esdg.Solver(dev, precision, stream=stream)
         s.upload_mesh(w.mesh)
         P = esdg.default_params(N, av_on=0 if args.no_av else 1, limiter_on=1, eps0=0.025)
@@ -385,104 +538,105 @@ def main():
         s.set_state(w.h, w.hu, w.hv)
         K = w.mesh.K
         nodes = K * (N + 1) ** 2
+        av = not args.no_av
+        rb = 8 if precision == 64 else 4
+        # right-hand side alone: the stage kernel in its RHS form, events per launch
+        s.rhs(device=True)
+        s.profile(True)
+        s.profile_read_kernels()
+        for _ in range(rhs_reps):
+            R = s.rhs(device=True)
+        prof = s.profile_read_kernels()
+        s.profile(False)
+        rhs_ms = prof["stage"][0] / max(prof["stage"][1], 1)
+        rhs_b = rhs_bytes(N, K, av, rb)
         err32 = None
-        if precision == 32:
-            # the FP32 right-hand side against the FP64 one (the same library in
-            # FP64, parity-checked against the oracle) at the initial state
-            r32 = s.rhs(device=True)
-            s64 = esdg.Solver(dev, 64, stream=stream)
-            s64.upload_mesh(w.mesh)
-            s64.set_params(P)
-            s64.set_bathymetry(w.b)
-            s64.set_state(w.h, w.hu, w.hv)
-            r64 = s64.rhs(device=True)
-            s64.close()
-            err32 = {"max_abs_over_max": [float((a - b).abs().max() / b.abs().max()) for a, b in zip(r32, r64)],
+        if fp64_rhs is not None:
+            err32 = {"max_abs_over_max": [float((a - b).abs().max() / b.abs().max()) for a, b in zip(R, fp64_rhs)],
                      "l2_relative": [float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-                                     for a, b in zip(r32, r64)],
+                                     for a, b in zip(R, fp64_rhs)],
                      "fields": ["h", "hu", "hv"], "state": "initial state of the workload"}
-            del r32, r64
-            log(f"FP32 rhs vs FP64: max-abs / max {max(err32['max_abs_over_max']):.2e}")
-        log(f"uploaded K={K} nodes={nodes}; warmup {warmup} steps")
+            log(f"N={N} FP32 rhs vs FP64: max-abs / max {max(err32['max_abs_over_max']):.2e}")
+            R = None
+        elif precision == 64:
+            R = [r.clone() for r in R]
+        else:
+            R = None
         s.step(warmup, 0.0)
         choice, tune_ms = s.autotune(5) if args.autotune else (0, None)
-        if args.autotune:
-            log(f"autotune: stage workgroup variant {choice} (ms {tune_ms[0]:.3f} / {tune_ms[1]:.3f})")
         torch.cuda.synchronize()
         s.profile(True)
-        s.profile_read()
+        s.profile_read_kernels()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         t_sim, _ = s.step(steps, 0.0)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        prof = s.profile_read()
+        prof = s.profile_read_kernels()
         s.profile(False)
+        limited, n_visc = s.step_stats()
         d = s.diagnostics()
-        n_visc = int((s.get_eps() > 0).sum()) if not args.no_av else 0
-        log(f"N={N}: {steps} steps in {el:.3f} s, t={t_sim:.4g}, min h={d[5]:.3g}")
-        rb = 8 if precision == 64 else 4
-        av = not args.no_av
+        log(f"N={N} FP{precision}: {steps} steps in {el:.3f} s, t={t_sim:.4g}, min h={d[5]:.3g}, "
+            f"stage variant {choice}")
         per_step = sum(stage_bytes(N, K, av, rb, k, n_visc) for k in range(5))
-        stage_total = per_step * steps
-        stage_launch = prof["stage_launches"]
-        stage_mean_ms = prof["stage_ms"] / max(stage_launch, 1)
-        achieved = stage_total / (prof["stage_ms"] * 1e-3) / 1e9
+        st_ms, st_n = prof["stage"]
+        stage_mean_ms = st_ms / max(st_n, 1)
+        achieved = per_step * steps / (st_ms * 1e-3) / 1e9
         flops_node = stage_flops(N, av)
+        kt = kernel_times(prof, steps)
+        outside = sum(v["ms_per_step"] for k, v in kt.items() if k != "stage")
         res = dict(N=N, precision=precision, K=K, nodes=nodes, elapsed=el, t_sim=t_sim, n_visc=n_visc,
+                   limited_element_stages=limited,
                    stage_TFLOPs=flops_node * nodes / (stage_mean_ms * 1e-3) / 1e12,
-                   flops_per_node=flops_node,
-                   stage_variant=choice,
-                   value=nodes * 5 * steps / el,
-                   ms_per_step=el * 1e3 / steps,
-                   stage_mean_ms=stage_mean_ms, stage_launches=stage_launch,
-                   stage_bytes_per_launch=per_step / 5,
-                   stage_GBs=achieved,
+                   flops_per_node=flops_node, stage_variant=choice,
+                   value=nodes * 5 * steps / el, ms_per_step=el * 1e3 / steps,
+                   stage_mean_ms=stage_mean_ms, stage_launches=st_n,
+                   stage_bytes_per_launch=per_step / 5, stage_GBs=achieved,
                    roofline_frac=achieved / HBM_PEAK_GBS,
-                   av_ms_per_stage=prof["av_ms"] / (5 * steps),
-                   av_launches=prof["av_launches"])
+                   kernels_ms_per_step=kt, outside_stage_ms_per_step=outside,
+                   rhs_only={"kernel_ms": rhs_ms, "value": nodes / (rhs_ms * 1e-3), "unit": "DOF/s (one RHS)",
+                             "bytes": rhs_b, "GBs": rhs_b / (rhs_ms * 1e-3) / 1e9,
+                             "frac": rhs_b / (rhs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
         if err32 is not None:
             res["fp32_vs_fp64_rhs"] = err32
         s.close()
-        del w
-        return res
+        return res, R
 
-    def memcopy_probe(nbytes):
-        # empirical MemCopy roofline: device copy of (bytes read + written)/2
-        n = int(nbytes // 2 // 8)
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        reps = 10
-        for _ in range(reps):
-            dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        del src, dst
-        return dict(bytes=2 * n * 8, mean_ms=ms, GBs=2 * n * 8 / (ms * 1e-3) / 1e9)
+    keys = ("N", "precision", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs", "roofline_frac",
+            "stage_TFLOPs", "stage_variant", "outside_stage_ms_per_step", "rhs_only")
+    sweep = []
+    main_res = None
+    degrees = [args.N] + [int(t) for t in args.sweep.split(",") if t.strip() and int(t) != args.N]
+    for N in degrees:
+        log(f"generating {args.n}x{args.n} workload at N={N}")
+        w = smooth_sweep(args.n, N, seed=3)
+        is_main = N == args.N
+        steps = args.steps if is_main else args.sweep_steps
+        warm = args.warmup if is_main else 2
+        r64, R64 = run(w, N, args.precision, steps, warm, args.rhs_reps)
+        if is_main:
+            main_res = r64
+        else:
+            sweep.append({k: r64[k] for k in keys})
+        if args.fp32_sweep and args.precision == 64:
+            r32, _ = run(w, N, 32, args.sweep_steps, 2, args.rhs_reps, fp64_rhs=R64)
+            sweep.append({k: r32[k] for k in keys + ("fp32_vs_fp64_rhs",) if k in r32})
+        del w, R64
+        torch.cuda.empty_cache()
 
-    main_res = run(args.N)
     log("memcopy probe")
-    mc = memcopy_probe(main_res["stage_bytes_per_launch"])
+    mc = memcopy_probe(torch, dev, main_res["stage_bytes_per_launch"])
     log("LDS probe")
     lds_bw = esdg.lds_bandwidth(dev)
     # LDS bytes the volume term reads per node: 2(N+1) partners x (metric pair, discharge
     # pair, velocity pair: 16 B each; h and the D entry: 8 B each)
     lds_node = 2 * (args.N + 1) * 64.0
     lds_achieved = lds_node * main_res["nodes"] / (main_res["stage_mean_ms"] * 1e-3)
-    sweep = []
-    keys = ("N", "precision", "nodes", "value", "ms_per_step", "stage_mean_ms", "stage_GBs", "roofline_frac",
-            "stage_TFLOPs", "stage_variant")
-    for tok in [t for t in args.sweep.split(",") if t.strip()]:
-        r = run(int(tok), steps=args.sweep_steps, warmup=2)
-        sweep.append({k: r[k] for k in keys})
-    if args.fp32_check and args.precision == 64:
-        r = run(args.N, precision=32, steps=args.sweep_steps, warmup=2)
-        sweep.append({k: r[k] for k in keys + ("fp32_vs_fp64_rhs",) if k in r})
+
+    dam = None
+    if args.dam_break:
+        log("128^2 N=7 wet/dry dam break")
+        dam = dam_break_bench(esdg, dev, stream, args.dam_break_steps, 5)
 
     ens = None
     if members:
@@ -542,13 +696,12 @@ def main():
             "fp64_vector": {"achieved_TFLOPs": main_res["stage_TFLOPs"],
                             "peak_TFLOPs": 78.6 if args.precision == 64 else 157.3,
                             "flops_per_node": main_res["flops_per_node"],
-                            "note": "algorithmic FLOPs of the method (bench.stage_flops); the rocprofv3 FP64 "
-                                    "instruction counts per degree are in "
-                                    "profiles/stage_kernel_roofline_by_degree_512x512_fp64.md"},
+                            "note": "algorithmic FLOPs of the method (bench.stage_flops)"},
         },
         "cpu_baseline": cpu,
-        "viscosity_kernels": {"ms_per_stage": main_res["av_ms_per_stage"],
-                              "launches": main_res["av_launches"]},
+        "kernels_ms_per_step": main_res["kernels_ms_per_step"],
+        "outside_stage_ms_per_step": main_res["outside_stage_ms_per_step"],
+        "rhs_only": main_res["rhs_only"],
         "memcopy_roofline": {"GBs": mc["GBs"], "bytes": mc["bytes"],
                              "stage_frac": main_res["stage_GBs"] / mc["GBs"]},
         "lds_roofline": {"probe_GBs": lds_bw / 1e9, "volume_bytes_per_node": lds_node,
@@ -556,6 +709,8 @@ def main():
     }
     if sweep:
         out["sweep"] = sweep
+    if dam:
+        out["dam_break"] = dam
     if ens:
         out["ensemble"] = ens
     if adj:
@@ -563,6 +718,26 @@ def main():
     if cases:
         out["paper_cases"] = cases
     print(json.dumps(out), flush=True)
+
+
+def memcopy_probe(torch, dev, nbytes):
+    """The paper's empirical MemCopy roofline: a device copy moving the
+    stage's bytes ((read + written)/2 each way), timed with events."""
+    n = int(nbytes // 2 // 8)
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return dict(bytes=2 * n * 8, mean_ms=ms, GBs=2 * n * 8 / (ms * 1e-3) / 1e9)
 
 
 if __name__ == "__main__":

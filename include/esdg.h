@@ -10,7 +10,7 @@
  * the artificial-viscosity terms of Theorem 1,
  *     J W_t = -(L_xi + L_eta) + S + L^v_xi + L^v_eta,
  * applies the positivity-preserving limiter (eq. PosPres) and advances the
- * solution with a low-storage Runge-Kutta method (section 2.3) or SSPRK(3,3)
+ * solution with a low-storage Runge-Kutta method (section 2.2) or SSPRK(3,3)
  * (eq. RKSSP) at a step chosen from a CFL bound, a viscous bound and the
  * mean-positivity bounds of Lemma 2 (eq. CFLConstraints).  Everything runs
  * in hand-written HIP kernels on one GPU; the host code only validates
@@ -66,7 +66,9 @@ typedef enum {
                               violated); the state is still finite          */
     ESDG_EDTPOS = -6,      /* no admissible time step (all bounds infinite
                               or not positive)                              */
-    ESDG_ENONFINITE = -7   /* non-finite value in the state                 */
+    ESDG_ENONFINITE = -7   /* a stage wrote a non-finite value (NaN or
+                              infinity) into the state; checked once per
+                              esdg_step / esdg_ensemble_step call            */
 } esdg_status;
 
 /* Run-time parameters.  esdg_default_params() fills the defaults. */
@@ -119,8 +121,11 @@ int esdg_upload_mesh(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
  * Nodal bathymetry b [K][(N+1)^2].  Builds the split-form derivatives of
  * eq. SourceDisc (read with D in place of the printed 2D, and with the
  * chain-rule sign of b_y) and the face traces used by the interface flux.
- * b should be continuous across faces; the interface penalty S^{.,*} for
- * discontinuous bathymetry is not applied.
+ * b may jump across faces: the interface penalty S^{.,*} of eq. SourceDisc
+ * (whose form the paper leaves to its earlier work) is taken as the one
+ * Lemma 1.2 and 1.3 fix, -(1/w_0) J^surf {h} [[b]] n at every face node
+ * (entering the source as (g/2) S^{.,*}); it vanishes where b is continuous
+ * and at walls.  Lemma 2's positivity bound assumes a continuous b.
  */
 int esdg_set_bathymetry(esdg_ctx *ctx, const double *b, int mem);
 
@@ -159,6 +164,12 @@ int esdg_compute_dt(esdg_ctx *ctx, double out[4]);
  * step (no host synchronisation unless max_dt_retries > 0).  With
  * limiter_on the limiter follows every stage.  *t_out (may be NULL)
  * receives the accumulated time.  Returns after the last step completed.
+ * Status, checked once at the end of the call (the steps are not stopped
+ * early): ESDG_ENONFINITE if any stage wrote a NaN or an infinity (a NaN
+ * state also leaves no admissible adaptive step; ENONFINITE is reported
+ * first), else ESDG_EDTPOS, else ESDG_ENEGMEAN (after max_dt_retries
+ * halvings of a step).  The kernels run to completion on non-finite
+ * values; the state then holds them.
  */
 int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out);
 
@@ -174,6 +185,12 @@ int esdg_set_time(esdg_ctx *ctx, double t);
  */
 int esdg_diagnostics(esdg_ctx *ctx, double out[8]);
 
+/* Activity of the hot path's non-smooth parts: *limited (may be NULL) =
+ * element-stages the positivity limiter scaled during the last esdg_step
+ * call (eq. PosPres); *viscous (may be NULL) = elements of the current state
+ * with a positive viscosity (appendix A; 0 with av_on = 0). */
+int esdg_step_stats(esdg_ctx *ctx, int64_t *limited, int64_t *viscous);
+
 /* Element viscosities eps [K] of the current state (appendix A). */
 int esdg_get_eps(esdg_ctx *ctx, double *eps, int mem);
 
@@ -184,7 +201,9 @@ int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, dou
 /*
  * Kernel timing: with enable = 1, esdg_step and esdg_rhs record HIP events
  * around every launch of the stage kernel (the fused volume + interface +
- * source + update + limiter kernel) on the context stream.
+ * source + update + limiter kernel), the viscosity kernels and the
+ * time-step pass on the context stream (the events are recorded by the
+ * kernel dispatch itself).
  * esdg_profile_read returns the summed event time in milliseconds and the
  * number of timed launches since the last reset, and resets the counters.
  */
@@ -195,20 +214,33 @@ int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_launches,
  * esdg_adjoint_backward: summed milliseconds and launches since the last
  * read, then reset. */
 int esdg_profile_read_adjoint(esdg_ctx *ctx, double *ms, int64_t *launches);
+/* Per kernel class, summed event milliseconds ms[k] and launches[k] since
+ * the last read (all classes then reset): k = 0 stage kernel, 1 indicator
+ * (viscosity of a state no stage produced), 2 viscous face fluxes (BR1,
+ * Theorem 1), 3 viscous divergence (eq. ViscTermsDisc), 4 time-step pass
+ * (eq. CFLConstraints and the CFL/viscous bounds), 5 adjoint reverse stage.
+ * esdg_profile_read's av figures are classes 1-3. */
+int esdg_profile_read_kernels(esdg_ctx *ctx, double ms[6], int64_t launches[6]);
 
 /*
- * Autotuner of the stage kernel's tile (elements per workgroup): every
- * degree has two compiled workgroup sizes, the default (one 64-lane wave
- * where whole elements fill it -- N = 2, 3, 7 -- else 256 threads) and an
- * alternative (256 resp. 128 threads).  esdg_autotune times reps launches
- * of each on the context's mesh and current state (trial stages write only
- * a scratch state buffer: the state, the LSRK register and the time are
- * unchanged), keeps the faster for all later launches and returns the choice
- * (0 default, 1 alternative) and the mean launch times in ms (either output
- * may be NULL).  esdg_set_stage_variant sets the choice directly.  Results
- * do not depend on the choice (same arithmetic per element).
+ * Autotuner of the stage kernel (the paper tunes its elements per block per
+ * degree and GPU, appendix C).  Every degree has ESDG_STAGE_VARIANTS
+ * compiled variants: 0 the default tile (one 64-lane wave where whole
+ * elements fill it -- N = 2, 3, 7 -- else 256 threads) with its register
+ * budget and partner-loop unroll; 1 the alternative workgroup size (256
+ * resp. 128 threads); 2 the default tile with one wave per SIMD less in its
+ * register budget; 3 the default tile with the other partner-loop unroll.
+ * esdg_autotune times reps launches of each on the context's mesh and
+ * current state, twice (trial stages write only a scratch state buffer: the
+ * state, the LSRK register and the time are unchanged; they are not counted
+ * by esdg_profile), keeps the fastest for all later launches and returns the
+ * choice and the mean launch times in ms, ms[0..ESDG_STAGE_VARIANTS-1]
+ * (either output may be NULL).  esdg_set_stage_variant sets the choice
+ * directly.  Results do not depend on the choice (the same arithmetic per
+ * element in the same order).
  */
-int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2]);
+#define ESDG_STAGE_VARIANTS 4
+int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[ESDG_STAGE_VARIANTS]);
 int esdg_set_stage_variant(esdg_ctx *ctx, int variant);
 
 /* Empirical LDS roofline (the paper's shared-memory roofline): 16-byte LDS

@@ -5,7 +5,8 @@ GPU library is checked against.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import it; the product path never does.
 
 The arithmetic lives in ``esdg_oracle.c`` (plain C, built with
-``gcc -O2 -ffp-contract=off``); this module only marshals numpy arrays.
+``gcc -O2 -ffp-contract=off``; OpenMP over elements, bitwise independent of
+the thread count); this module only marshals numpy arrays.
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-                               "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -73,6 +74,8 @@ def lib():
         L.orc_step.argtypes = [P, P, P, P, P, P, I, C.c_double, P, P]
         L.orc_diagnostics.argtypes = [P, P, P, P, P, P, P]
         L.orc_lsrk_coefficients.argtypes = [P, P]
+        L.orc_set_threads.argtypes = [I]
+        L.orc_get_threads.argtypes = []
         L.orc_rhs_vjp.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_gauge_adjoint.argtypes = [P, P, P, P, P, P, I, C.c_double, I, P, P, P, P, P, P,
                                         P, P, P, P]
@@ -227,6 +230,15 @@ def diagnostics(P: Params, mesh, b, h, hu, hv):
     _check(lib().orc_diagnostics(C.byref(P), C.byref(M.c), _p(_f64(b)), _p(_f64(h)),
                                  _p(_f64(hu)), _p(_f64(hv)), _p(out)), "diagnostics")
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's element loops (results do not depend on it)."""
+    _check(lib().orc_set_threads(int(n)), "set_threads")
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def lsrk_coefficients():

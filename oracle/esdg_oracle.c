@@ -24,6 +24,7 @@
  * result no property of the paper fixes say so below ("parity unpinned").
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -240,6 +241,7 @@ static void geom_free(orc_geom *G)
 static void geometry(const orc_ops *op, const orc_mesh *m, orc_geom *G)
 {
     int N = op->N, n1 = N + 1, np = n1 * n1;
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < m->K; ++e) {
         const double *x = m->x + e * np, *y = m->y + e * np;
         /* The metric terms are derivatives of the mapping, so they do not
@@ -504,6 +506,7 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
     uint8_t *needv = NULL;     /* elements whose viscous fluxes are needed */
     double *Fv2 = NULL, *Fv3 = NULL, *Gv2 = NULL, *Gv3 = NULL;
     if (!u || !v || !eps) { free(u); free(v); free(eps); return ORC_ENOMEM; }
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) {
         u[q] = velocity(hu[q], h[q], htol);
         v[q] = velocity(hv[q], h[q], htol);
@@ -526,6 +529,7 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
                 if (!is_wall(m, e, s)) needv[m->nbr_elem[e * 4 + s]] = 1;
         }
         /* viscosity per element from the stage state (appendix A) */
+#pragma omp parallel for schedule(static)
         for (int64_t e = 0; e < K; ++e)
             if (needv[e]) eps[e] = viscosity_of_element(P, op, h + e * np);
         /* BR1 gradients of the gradient variables u, v (eq. BR1).  Readings:
@@ -534,6 +538,7 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
          * chain rule of eq. NablaRelation with the same metric signs as the
          * volume part (the printed signs of the eta-surface term in U1/V1 and
          * the xi-surface term in U2/V2 are inconsistent with it). */
+#pragma omp parallel for schedule(static)
         for (int64_t e = 0; e < K; ++e) {
             if (!needv[e]) continue;
             double Us[4][ORC_NMAX + 1], Vs[4][ORC_NMAX + 1];   /* U* = {u} per side */
@@ -581,6 +586,9 @@ static int rhs_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
     if (eps_out)
         for (int64_t e = 0; e < K; ++e) eps_out[e] = eps[e];
 
+    /* every element writes its own nodes only: the loop is element-parallel
+     * and bitwise the same at any thread count */
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t e = 0; e < K; ++e) {
         if (need && !need[e]) continue;
         const int64_t o = e * np;
@@ -805,8 +813,9 @@ static int limit_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
                       const orc_geom *G, double *h, double *hu, double *hv, int64_t *n_limited)
 {
     const int N = op->N, n1 = N + 1, np = n1 * n1;
-    int status = ORC_OK;
+    int negmean = 0;
     int64_t nl = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nl) reduction(| : negmean)
     for (int64_t e = 0; e < m->K; ++e) {
         const int64_t o = e * np;
         /* Jacobian-weighted element means and the minimum (eq. AverageTerm) */
@@ -826,7 +835,7 @@ static int limit_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
          * (no division at m = hbar), theta = 0 and an error flag if hbar < 0. */
         double theta = 1.0;
         if (hmin < 0.0) {
-            if (mh < 0.0) { theta = 0.0; status = ORC_ENEGMEAN; }
+            if (mh < 0.0) { theta = 0.0; negmean = 1; }
             else theta = fmin(1.0, mh / (mh - hmin));
             ++nl;
         }
@@ -842,7 +851,7 @@ static int limit_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
         }
     }
     if (n_limited) *n_limited = nl;
-    return status;
+    return negmean ? ORC_ENEGMEAN : ORC_OK;
 }
 
 int orc_limit(const orc_params *P, const orc_mesh *m, double *h, double *hu, double *hv,
@@ -878,6 +887,8 @@ static void dt_impl(const orc_params *P, const orc_ops *op, const orc_mesh *m,
     const double g = P->g, htol = P->h_tol;
     double dt_cfl = INFINITY, dt_visc = INFINITY, dt_pos = INFINITY;
     (void)b;
+    /* minima are exact: the same bounds at any thread count */
+#pragma omp parallel for schedule(static) reduction(min : dt_cfl, dt_visc, dt_pos)
     for (int64_t e = 0; e < m->K; ++e) {
         const int64_t o = e * np;
         double gmax = 0.0;
@@ -966,6 +977,16 @@ static const double LSRK_B[5] = {1432997174477.0 / 9575080441755.0,
                                  3134564353537.0 / 4481467310338.0,
                                  2277821191437.0 / 14882151754819.0};
 
+/* Threads of the element loops (OpenMP); the results do not depend on it. */
+int orc_set_threads(int n)
+{
+    if (n < 1) return ORC_EINVAL;
+    omp_set_num_threads(n);
+    return ORC_OK;
+}
+
+int orc_get_threads(void) { return omp_get_max_threads(); }
+
 int orc_lsrk_coefficients(double *a, double *b)
 {
     for (int k = 0; k < 5; ++k) { a[k] = LSRK_A[k]; b[k] = LSRK_B[k]; }
@@ -983,10 +1004,12 @@ static int one_step(const orc_params *P, const orc_ops *op, const orc_mesh *m,
     int status = ORC_OK, st;
     if (P->integrator == 0) {
         double *d0 = work + 3 * n, *d1 = work + 4 * n, *d2 = work + 5 * n;
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < n; ++q) { d0[q] = 0; d1[q] = 0; d2[q] = 0; }
         for (int k = 0; k < 5; ++k) {
             st = rhs_impl(P, op, m, G, b, h, hu, hv, R0, R1, R2, NULL, NULL, NULL);
             if (st) return st;
+#pragma omp parallel for schedule(static)
             for (int64_t q = 0; q < n; ++q) {
                 d0[q] = LSRK_A[k] * d0[q] + dt * R0[q];
                 d1[q] = LSRK_A[k] * d1[q] + dt * R1[q];
@@ -1003,12 +1026,14 @@ static int one_step(const orc_params *P, const orc_ops *op, const orc_mesh *m,
     } else {
         /* SSPRK(3,3) in the Shu-Osher form of eq. RKSSP */
         double *W0 = work + 3 * n, *W1 = work + 4 * n, *W2 = work + 5 * n;
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < n; ++q) { W0[q] = h[q]; W1[q] = hu[q]; W2[q] = hv[q]; }
         static const double alpha[3] = {0.0, 0.75, 1.0 / 3.0};
         static const double beta[3] = {1.0, 0.25, 2.0 / 3.0};
         for (int k = 0; k < 3; ++k) {
             st = rhs_impl(P, op, m, G, b, h, hu, hv, R0, R1, R2, NULL, NULL, NULL);
             if (st) return st;
+#pragma omp parallel for schedule(static)
             for (int64_t q = 0; q < n; ++q) {
                 h[q] = alpha[k] * W0[q] + beta[k] * (h[q] + dt * R0[q]);
                 hu[q] = alpha[k] * W1[q] + beta[k] * (hu[q] + dt * R1[q]);

@@ -35,7 +35,9 @@
 //    are one reverse evaluation of the own term's flux.  At a solid wall the
 //    outside trace is the own trace with the normal velocity reversed: the
 //    outside cotangent returns to this node through that (symmetric) mirror,
-//    and there is no neighbour term.
+//    and there is no neighbour term.  The interface bathymetry penalty of
+//    eq. SourceDisc, linear in {h} and [[b]], is reversed the same way (its
+//    b-partials are nonzero also where b is continuous).
 // The derivative of |x| is taken as sign(x) with sign(0) = 0; velocities
 // below the dry cut-off are constants (zero derivative).
 #pragma once
@@ -234,6 +236,15 @@ __global__ __launch_bounds__(Shape<N>::T) void adjoint_stage_kernel(AdjArgs a)
             interface_flux_vjp<R>(ho, wo.x, wo.y, bo, hn, un, vn, bn, nx, ny, P, so * (s_m[0][lp] + nm0),
                                   so * (s_m[1][lp] + nm1), so * (s_m[2][lp] + nm2), g1, g2);
             gh = g1.h; gu = g1.u; gv = g1.v; gb = g1.b;
+            if (!wall) {
+                // interface bathymetry penalty (g/(4 w_0)) (h + h_n)(b_n - b) J^surf n
+                // in L of both sides (the neighbour's with its own normal, -n
+                // up to rounding): d/dh and d/db of this node from both terms
+                const R wpen = R(0.25) * P.g * a.tab.iw0 *
+                               ((s_m[1][lp] - nm1) * snx + (s_m[2][lp] - nm2) * sny);
+                gh += wpen * (bn - bo);
+                gb -= wpen * (ho + hn);
+            }
             if (wall) {
                 // the outside trace is (h, M(u, v), b), M = I - 2 n n^T = M^T:
                 // its cotangent returns through the mirror

@@ -58,7 +58,7 @@ hipError_t Launch<N, R>::geometry(const Bufs &B, const Tab<double> &td, hipStrea
     const int64_t n = B.K * np;
     const int bs = 256;
     hipLaunchKernelGGL((geometry_kernel<N, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, B.K,
-                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.flags + 3, td);
+                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.flags + kFlagBadJ, td);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((gmax_kernel<N, R>), dim3((unsigned)((B.K + bs - 1) / bs)), dim3(bs), 0, s,
@@ -148,20 +148,24 @@ hipError_t Launch<N, R>::av_div(const Bufs &B, int in, int reset, const Phys<R> 
     return hipGetLastError();
 }
 
+template <int N, typename R, int MODE, int V>
+static void launch_stage_variant(StageArgs<R> a, int64_t K, hipStream_t s, Ev ev)
+{
+    using S = TileShape<N, StageCfg<N, V>::T>;
+    a.ntiles = (K + S::E - 1) / S::E;
+    const dim3 grid((unsigned)(((a.ntiles + kXcds - 1) / kXcds) * kXcds));
+    hipExtLaunchKernelGGL((stage_kernel<N, R, MODE, V>), grid, dim3(S::T), 0, s, ev.a, ev.b, 0, a);
+}
+
 template <int N, typename R, int MODE>
 static void launch_stage(StageArgs<R> a, int64_t K, hipStream_t s, Ev ev)
 {
-    // both workgroup sizes of the stage kernel (the autotuner picks one)
-    if (a.variant == 0) {
-        using S = TileShape<N, Shape<N>::T>;
-        a.ntiles = (K + S::E - 1) / S::E;
-        const dim3 grid((unsigned)(((a.ntiles + kXcds - 1) / kXcds) * kXcds));
-        hipExtLaunchKernelGGL((stage_kernel<N, R, MODE, S::T>), grid, dim3(S::T), 0, s, ev.a, ev.b, 0, a);
-    } else {
-        using S = TileShape<N, AltThreads<N>::value>;
-        a.ntiles = (K + S::E - 1) / S::E;
-        const dim3 grid((unsigned)(((a.ntiles + kXcds - 1) / kXcds) * kXcds));
-        hipExtLaunchKernelGGL((stage_kernel<N, R, MODE, S::T>), grid, dim3(S::T), 0, s, ev.a, ev.b, 0, a);
+    // the compiled variants of the stage kernel (the autotuner picks one)
+    switch (a.variant) {
+    case 1: launch_stage_variant<N, R, MODE, 1>(a, K, s, ev); break;
+    case 2: launch_stage_variant<N, R, MODE, 2>(a, K, s, ev); break;
+    case 3: launch_stage_variant<N, R, MODE, 3>(a, K, s, ev); break;
+    default: launch_stage_variant<N, R, MODE, 0>(a, K, s, ev); break;
     }
 }
 
@@ -219,7 +223,7 @@ hipError_t Launch<N, R>::limit(const Bufs &B, int buf, const Phys<R> &P, const T
 }
 
 template <int N, typename R>
-hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s)
+hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s, Ev ev)
 {
     DtArgs<R> a;
     a.m = mesh_view<R>(B);
@@ -238,14 +242,14 @@ hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, bool fused, const Ph
     a.nchunks = B.nchunks;
     if (B.n_inst > 1) {
         const unsigned grid = (unsigned)(B.nchunks < (int64_t)kDtMaxBlocks ? B.nchunks : (int64_t)kDtMaxBlocks);
-        hipLaunchKernelGGL((dt_batch_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, a);
+        hipExtLaunchKernelGGL((dt_batch_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, ev.a, ev.b, 0, a);
         return hipGetLastError();
     }
     constexpr int64_t np = (N + 1) * (N + 1);
     const int64_t items = fused ? B.K * 4 * (N + 1) : B.K * np;
     const int64_t want = ((items + kDtThreads * kXcds - 1) / (kDtThreads * kXcds)) * kXcds;
     const unsigned grid = (unsigned)(want < (int64_t)kDtMaxBlocks ? want : (int64_t)kDtMaxBlocks);
-    hipLaunchKernelGGL((dt_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, a);
+    hipExtLaunchKernelGGL((dt_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, ev.a, ev.b, 0, a);
     return hipGetLastError();
 }
 

@@ -40,9 +40,8 @@ struct Shape {
     static_assert(E * np <= T, "elements must fit the workgroup");
 };
 
-// The stage kernel comes in two workgroup sizes per degree, chosen at run
-// time (esdg_autotune): the default above and an alternative (256 threads
-// where the default is one wave, else 128).
+// The alternative workgroup size of the stage kernel: 256 threads where the
+// default is one wave, else 128.
 template <int N>
 struct AltThreads {
     static constexpr int value = Shape<N>::T == 64 ? 256 : 128;
@@ -58,14 +57,35 @@ struct TileShape {
     static_assert(E * np <= T, "elements must fit the workgroup");
 };
 
-// Waves per SIMD the stage kernel is compiled for (its register budget) in
-// the FP64 update modes with the default shape: six at N = 6, five otherwise
-// (N = 7 reaches six by its partner-loop unroll); the few spilled bytes at
-// N = 2, 6 cost less than the occupancy they buy (measured).  No constraint
-// otherwise.
-template <int N, typename R, int MODE, int TT = Shape<N>::T>
+// Compiled variants of the stage kernel, chosen at run time by the
+// autotuner (esdg_autotune); every variant does the same arithmetic per
+// element in the same order (results are bitwise the same):
+//   0  the default tile of Shape, its register budget and partner unroll;
+//   1  the alternative workgroup size (AltThreads), no register budget;
+//   2  the default tile with one wave per SIMD less in its register budget
+//      (more registers, no spills where the default spills);
+//   3  the default tile with the other partner-loop unroll (full where the
+//      default unrolls partly, by two where it unrolls fully).
+// Default register budget in the FP64 update modes: six waves per SIMD at
+// N = 6, five otherwise (N = 7 reaches six by its partner-loop unroll); no
+// constraint in FP32 and in the right-hand-side mode.  Default unroll: fully,
+// except at N = 7 with one-wave tiles (by two: 79 VGPRs and six waves per
+// SIMD instead of five), N = 6 (by two) and N = 8 (by three: five waves).
+constexpr int kStageVariants = 4;
+
+template <int N, int V>
+struct StageCfg {
+    static_assert(V >= 0 && V < kStageVariants, "stage variant");
+    static constexpr int T = V == 1 ? AltThreads<N>::value : Shape<N>::T;
+    static constexpr int base_waves = V == 1 ? 1 : ((N == 6 || N == 7) ? 6 : 5);
+    static constexpr int waves = V == 2 ? base_waves - 1 : base_waves;
+    static constexpr int vu_default = (N == 7 && T == 64) ? 2 : (N == 8 ? 3 : (N == 6 ? 2 : N + 1));
+    static constexpr int VU = V == 3 ? (vu_default == N + 1 ? 2 : N + 1) : vu_default;
+};
+
+template <int N, typename R, int MODE, int V>
 struct StageWaves {
-    static constexpr int value = (sizeof(R) == 8 && MODE != 0 && TT == Shape<N>::T) ? (N == 6 ? 6 : 5) : 1;
+    static constexpr int value = (sizeof(R) == 8 && MODE != 0) ? StageCfg<N, V>::waves : 1;
 };
 
 // Workgroup barrier for exchanges through LDS only: orders LDS accesses
@@ -82,6 +102,11 @@ __device__ __forceinline__ void lds_sync()
 
 constexpr int kXcds = 8;
 constexpr int kDtSlots = 64;
+
+// Device status flags of a context: negative element mean, limited
+// elements, no admissible step, J <= 0 at mesh upload, non-finite output.
+constexpr int kFlagNegMean = 0, kFlagLimited = 1, kFlagDtPos = 2, kFlagBadJ = 3, kFlagNonFinite = 4;
+constexpr int kNumFlags = 8;
 
 // Tile of workgroup b when B = round_up(ntiles, 8) workgroups are launched:
 // hardware places workgroup b on XCD b % 8, so XCD x gets tiles
@@ -883,12 +908,12 @@ struct StageArgs {
     const R *gmax;               // [K] max |grad xi|^2 + |grad eta|^2 (viscous bound)
     const double *dt;            // per instance k: the current step at dt[8k]
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
-    int *flags;                  // [0]: negative mean seen, [1]: limited elements
+    int *flags;                  // status flags (kFlag*)
     int64_t ntiles;
-    int variant;                 // workgroup size: 0 the default, 1 the alternative (launch side)
+    int variant;                 // compiled variant 0..kStageVariants-1 (launch side)
 };
 
-// Face slot data loaded ahead of the LDS staging (slot = lane).
+// Face slot data loaded ahead of the LDS staging (slots t, t + T, ... of lane t).
 template <typename R>
 struct FacePrefetch {
     int64_t qn = 0, en = 0;
@@ -917,10 +942,10 @@ __device__ __forceinline__ void prefetch_face(const StageArgs<R> &a, int t, int6
     if (a.eps) pf.visc_nbr = !(a.eps[fe] > R(0)) && a.eps[pf.en] > R(0);
 }
 
-template <int N, typename R, int MODE, int TT>
-__global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage_kernel(StageArgs<R> a)
+template <int N, typename R, int MODE, int V>
+__global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::value)) void stage_kernel(StageArgs<R> a)
 {
-    using S = TileShape<N, TT>;
+    using S = TileShape<N, StageCfg<N, V>::T>;
     constexpr int nf = S::nf, np = S::np, E = S::E, T = S::T, NF = S::NFACE;
     static_assert((T & (T - 1)) == 0, "workgroup size must be a power of two");
     using V2 = typename Vec2<R>::type;
@@ -955,11 +980,14 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
         h = a.h[q]; hu = a.hu[q]; hv = a.hv[q];
         Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
     }
-    // When every face slot has a lane of its own, the slot's neighbour trace
-    // and face bathymetry are loaded here, with the element's own data, so
-    // that their latency is not paid a second time after the LDS staging.
-    FacePrefetch<R> pf;
-    if constexpr (NF <= T) prefetch_face<N, R, E, NF>(a, t, e0, pf);
+    // The face slots' neighbour traces and face bathymetry are loaded here,
+    // with the element's own data, so that their latency is not paid a second
+    // time after the LDS staging; a lane holds NS slots (two at N = 2, where
+    // seven elements' 84 face nodes outnumber the 64 lanes).
+    constexpr int NS = (NF + T - 1) / T;
+    FacePrefetch<R> pf[NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) prefetch_face<N, R, E, NF>(a, t + r * T, e0, pf[r]);
     const R eps_e = (av && act) ? a.eps[e] : R(0);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
@@ -978,21 +1006,16 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     // ---- interface: (1/w_0) J^surf F*(own, nbr, n_out) per face node; for
     // an element without viscosity next to one with viscosity, also its only
     // viscous term: (1/(2 w_0)) n_s . Fv_nbr (its own viscous fluxes are 0) ----
-    for (int f = t; f < NF; f += T) {
+    auto face_slot = [&](const int f, const FacePrefetch<R> &pfr) {
         const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
         const int64_t fe = e0 + fel;
         R c0 = 0, c1 = 0, c2 = 0;
         if (fe < a.m.K) {
-            int fi, fj, ns, kk;
-            int64_t en;
+            int fi, fj;
             side_node<N>(s, k, fi, fj);
             const int lp = fel * np + fi * nf + fj;
-            int64_t qn;
-            if constexpr (NF <= T) {
-                qn = pf.qn; en = pf.en; ns = pf.ns; kk = pf.kk;
-            } else {
-                qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
-            }
+            const int64_t qn = pfr.qn, en = pfr.en;
+            const int ns = pfr.ns, kk = pfr.kk;
             // outward scaled normal: +-J grad(xi) on xi = +-1, +-J grad(eta) on eta = +-1
             const V2 dir = (s & 1) ? s_a[lp] : s_b[lp];
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
@@ -1008,22 +1031,13 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
                 un = w.x;
                 vn = w.y;
             } else {
-                R hun, hvn;
-                if constexpr (NF <= T) {
-                    hn = pf.h; hun = pf.hu; hvn = pf.hv;
-                } else {
-                    hn = a.h[qn]; hun = a.hu[qn]; hvn = a.hv[qn];
-                }
+                hn = pfr.h;
                 const R in = rcp_wet(hn, P.h_tol);
-                un = hun * in;
-                vn = hvn * in;
+                un = pfr.hu * in;
+                vn = pfr.hv * in;
             }
-            if constexpr (NF <= T) {
-                bo = pf.bo; bn = pf.bn;
-            } else {
-                bo = a.m.bface[(fe * 4 + s) * nf + k];
-                bn = a.m.bface[(en * 4 + ns) * nf + kk];
-            }
+            bo = pfr.bo;
+            bn = pfr.bn;
             if (is_wall(a.m, fe, s)) wall_mirror(snx * ijs, sny * ijs, un, vn);
             R F0, F1, F2;
             const V2 wl = s_w[lp];
@@ -1031,10 +1045,12 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
                               F1, F2);
             const R sc = js * a.tab.iw0;
             c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
-            bool visc_nbr;
-            if constexpr (NF <= T) visc_nbr = av && pf.visc_nbr;
-            else visc_nbr = av && !(a.eps[fe] > R(0)) && a.eps[en] > R(0);
-            if (visc_nbr) {
+            // interface bathymetry penalty of eq. SourceDisc for a bottom
+            // that jumps at the face, (1/w_0) (g/2) {h} [[b]] J^surf n in L
+            // (zero for a continuous bottom and at walls, where bn = bo)
+            const R pen = R(0.25) * P.g * a.tab.iw0 * (s_h[lp] + hn) * (bn - bo);
+            c1 += pen * snx; c2 += pen * sny;
+            if (av && pfr.visc_nbr) {
                 const R *vn = a.vtr + ((en * 4 + ns) * nf + kk) * 4;
                 const R hw = R(0.5) * a.tab.iw0;
                 c1 -= hw * (snx * vn[0] + sny * vn[2]);
@@ -1042,6 +1058,13 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             }
         }
         s_fl[0][f] = c0; s_fl[1][f] = c1; s_fl[2][f] = c2;
+    };
+    if constexpr (NS == 1) {
+        for (int f = t; f < NF; f += T) face_slot(f, pf[0]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NS; ++r)
+            if (t + r * T < NF) face_slot(t + r * T, pf[r]);
     }
 
     // ---- volume: sum_m 2 D_im F~(i,m) + sum_m 2 D_jm G~(j,m) (D~ has a zero
@@ -1054,13 +1077,8 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
     R A1 = 0, A2 = 0, A3 = 0, C2 = 0, C3 = 0;
     {
         const int base = el * np;
-        // partner loops unrolled fully, except at N = 7 (one element per
-        // wave), where unrolling by two keeps the kernel at 79 VGPRs and six
-        // waves per SIMD instead of five (5% faster; slower at N <= 5), at
-        // N = 6, where it brings six waves within reach of a few spilled
-        // registers (2.5% faster), and at N = 8, where unrolling by three
-        // fits five waves (96 VGPRs, 8%)
-        constexpr int VU = (N == 7 && T == 64) ? 2 : (N == 8 ? 3 : (N == 6 ? 2 : nf));
+        // partner-loop unroll of the variant (StageCfg)
+        constexpr int VU = StageCfg<N, V>::VU;
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
             // the self pair has coefficient 0 (no branch: D~ has a zero diagonal)
@@ -1150,12 +1168,12 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
                 if (act && mn < R(0)) {
                     if (mh < R(0)) {
                         th = R(0);
-                        atomicOr(&a.flags[0], 1);
+                        atomicOr(&a.flags[kFlagNegMean], 1);
                     } else {
                         th = mh / (mh - mn);
                         th = th < R(1) ? th : R(1);
                     }
-                    atomicAdd(&a.flags[1], 1);
+                    atomicAdd(&a.flags[kFlagLimited], 1);
                 }
                 s_lim[4 * el + 0] = th; s_lim[4 * el + 1] = mh;
                 s_lim[4 * el + 2] = mhu; s_lim[4 * el + 3] = mhv;
@@ -1170,6 +1188,9 @@ __global__ __launch_bounds__(TT, (StageWaves<N, R, MODE, TT>::value)) void stage
             }
         }
         if (P.limiter_on && nh < P.h_tol) { nhu = R(0); nhv = R(0); }
+        // a non-finite value in any of the three (an infinity or NaN makes
+        // their sum non-finite) is reported once per esdg_step
+        if (act && !__builtin_isfinite(nh + nhu + nhv)) atomicOr(&a.flags[kFlagNonFinite], 1);
         if (act) {
             a.oh[q] = nh; a.ohu[q] = nhu; a.ohv[q] = nhv;
             if constexpr (MODE == kModeLsrk) {
@@ -1233,12 +1254,12 @@ __global__ __launch_bounds__(Shape<N>::T) void limit_kernel(Mesh<R> m, Phys<R> P
         R th;
         if (mh < R(0)) {
             th = R(0);
-            if (p == 0) atomicOr(&flags[0], 1);
+            if (p == 0) atomicOr(&flags[kFlagNegMean], 1);
         } else {
             th = mh / (mh - mn);
             th = th < R(1) ? th : R(1);
         }
-        if (p == 0) atomicAdd(&flags[1], 1);
+        if (p == 0) atomicAdd(&flags[kFlagLimited], 1);
         nh = th * (nh - mh) + mh;
         nhu = th * (nhu - mhu) + mhu;
         nhv = th * (nhv - mhv) + mhv;

@@ -38,7 +38,7 @@ struct Bufs {
     int64_t *cstart = nullptr;  // [nchunks + 1] element chunks of the time-step pass (never across instances)
     int32_t *cinst = nullptr;   // [nchunks] instance of each chunk
     int64_t nchunks = 0;
-    int *flags = nullptr;    // [0] neg mean, [1] limited count, [2] bad dt, [3] bad J
+    int *flags = nullptr;    // status flags (kFlag* in esdg_kernels.hpp)
     double *part = nullptr;  // diagnostics partial sums
     int64_t part_cap = 0;
 };
@@ -82,7 +82,7 @@ struct Launch {
     static hipError_t stage(const Bufs &B, const StageCall &c, const Phys<R> &P, const Tab<R> &t,
                             hipStream_t s, Ev ev);
     static hipError_t limit(const Bufs &B, int buf, const Phys<R> &P, const Tab<R> &t, hipStream_t s);
-    static hipError_t dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s);
+    static hipError_t dt(const Bufs &B, int in, bool av, bool fused, const Phys<R> &P, hipStream_t s, Ev ev);
     static hipError_t adjoint_stage(const Bufs &B, const AdjCall &c, const Phys<R> &P, const Tab<R> &t,
                                     hipStream_t s, Ev ev);
     static hipError_t bathymetry_adjoint(const Bufs &B, const Tab<double> &td, const double *gbx,

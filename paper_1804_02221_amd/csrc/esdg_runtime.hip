@@ -18,6 +18,10 @@
 
 namespace esdg {
 
+// Kernel classes timed by esdg_profile (index of esdg_profile_read_kernels).
+constexpr int kProfStage = 0, kProfIndicator = 1, kProfAvFaces = 2, kProfAvDiv = 3, kProfDt = 4,
+              kProfAdjoint = 5, kProfClasses = 6;
+
 // Reduce the dt slots: dt[0] = step, dt[1..3] = CFL, viscous, Lemma 2
 // bounds; fixed > 0 overrides the step.  Adds the step to *tacc when
 // advance.  Resets the slots to +inf.
@@ -47,7 +51,7 @@ __global__ void dt_finalize_kernel(unsigned long long *slots_all, double *dt_all
             step = fmin(s[0][0], s[1][0]);
             if (use_pos) step = fmin(step, s[2][0]);
             if (!(step > 0.0) || !(step < __builtin_huge_val())) {
-                atomicOr(&flags[2], 1);
+                atomicOr(&flags[kFlagDtPos], 1);
                 step = 0.0;
             }
         }
@@ -69,6 +73,15 @@ __global__ void fill_int_kernel(int *p, int v, int n)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) p[t] = v;
+}
+
+// Step status flags: [0] negative element mean, [1] limited elements,
+// [2] no admissible step, [3] J <= 0 at mesh upload (kept), [4] non-finite
+// stage output.  Clears all but [3].
+__global__ void reset_flags_kernel(int *flags)
+{
+    const int t = threadIdx.x;
+    if (t < kNumFlags && t != kFlagBadJ) flags[t] = 0;
 }
 
 // Retry support: step <- f * step, time corrected by the removed part.
@@ -144,7 +157,9 @@ struct esdg_ctx {
     int cur = 0;
     bool eps_valid[3] = {false, false, false};   // viscosity/list of state buffer b are current
     int dtb_buf = -1;   // state buffer whose per-element dt bounds are in dtc/dtv (-1: none)
-    int stage_variant = 0;   // stage-kernel workgroup size (esdg_autotune)
+    int stage_variant = 0;   // compiled stage-kernel variant (esdg_autotune)
+    hipEvent_t tune_ev[2] = {nullptr, nullptr};   // the autotuner's own timing events
+    int64_t last_limited = 0;   // limited element-stages of the last esdg_step call
     // instances (ensembles): element ranges [inst_off[k], inst_off[k+1]) in
     // the caller's order and, since the locality order permutes inside each
     // range, in the internal order too
@@ -156,10 +171,11 @@ struct esdg_ctx {
     int32_t *perm = nullptr;     // [K] caller's element of each internal element
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_stage, ev_av, ev_adj;
+    // timed launches per kernel class (kProf*) and their drained totals
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_log[kProfClasses];
     size_t ev_next = 0;
-    double acc_ms[3] = {0, 0, 0};   // drained event times: stage, viscosity, adjoint stage
-    int64_t acc_n[3] = {0, 0, 0};
+    double acc_ms[kProfClasses] = {};
+    int64_t acc_n[kProfClasses] = {};
     std::string err = "no error";
     std::vector<int32_t> inv_h;   // caller's element -> internal element
     uint64_t b_version = 0;       // bumped by every esdg_set_bathymetry
@@ -318,8 +334,9 @@ hipEvent_t next_event(esdg_ctx *c)
 // Launch with optional timing: the events are recorded by the kernel
 // dispatch itself (no marker packets between kernels).
 template <typename F>
-int timed(esdg_ctx *ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F &&launch)
+int timed(esdg_ctx *ctx, int cls, F &&launch)
 {
+    auto &log = ctx->ev_log[cls];
     Ev ev;
     if (ctx->prof) {
         ev.a = next_event(ctx);
@@ -345,7 +362,7 @@ int ensure_eps(esdg_ctx *ctx, int buf)
     if (ctx->eps_valid[buf]) return ESDG_OK;
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.count + buf, 0, 1);
     CK(hipGetLastError());
-    TRY(timed(ctx, ctx->ev_av, [&](Ev ev) {
+    TRY(timed(ctx, kProfIndicator, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
             return decltype(L)::indicator(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
@@ -360,13 +377,13 @@ int ensure_eps(esdg_ctx *ctx, int buf)
 int launch_viscous(esdg_ctx *ctx, int buf, int reset)
 {
     TRY(ensure_eps(ctx, buf));
-    TRY(timed(ctx, ctx->ev_av, [&](Ev ev) {
+    TRY(timed(ctx, kProfAvFaces, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
             return decltype(L)::av_faces(ctx->B, buf, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
         });
     }));
-    return timed(ctx, ctx->ev_av, [&](Ev ev) {
+    return timed(ctx, kProfAvDiv, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
             return decltype(L)::av_div(ctx->B, buf, reset, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
@@ -377,7 +394,7 @@ int launch_viscous(esdg_ctx *ctx, int buf, int reset)
 int launch_stage(esdg_ctx *ctx, StageCall sc)
 {
     sc.variant = ctx->stage_variant;
-    return timed(ctx, ctx->ev_stage, [&](Ev ev) {
+    return timed(ctx, kProfStage, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
             return decltype(L)::stage(ctx->B, sc, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
@@ -393,9 +410,11 @@ int launch_dt(esdg_ctx *ctx, int buf, double fixed, int advance)
     if (!(fixed > 0.0)) {
         const bool fused = ctx->dtb_buf == buf;
         if (av && !fused) TRY(ensure_eps(ctx, buf));
-        CK(dispatch(ctx, [&](auto L, auto r) {
-            using R = decltype(r);
-            return decltype(L)::dt(ctx->B, buf, av, fused, phys<R>(ctx), ctx->stream);
+        TRY(timed(ctx, kProfDt, [&](Ev ev) {
+            return dispatch(ctx, [&](auto L, auto r) {
+                using R = decltype(r);
+                return decltype(L)::dt(ctx->B, buf, av, fused, phys<R>(ctx), ctx->stream, ev);
+            });
         }));
     }
     hipLaunchKernelGGL(dt_finalize_kernel, dim3(n_inst(ctx)), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
@@ -406,14 +425,14 @@ int launch_dt(esdg_ctx *ctx, int buf, double fixed, int advance)
 
 int reset_flags(esdg_ctx *ctx)
 {
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.flags, 0, 3);
+    hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.flags);
     CK(hipGetLastError());
     return ESDG_OK;
 }
 
-int read_flags(esdg_ctx *ctx, int flags[4])
+int read_flags(esdg_ctx *ctx, int flags[kNumFlags])
 {
-    CK(hipMemcpyAsync(flags, ctx->B.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(flags, ctx->B.flags, kNumFlags * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     return ESDG_OK;
 }
@@ -545,7 +564,9 @@ int run_rhs(esdg_ctx *ctx, int buf)
 
 extern "C" {
 
-int esdg_abi_version(void) { return 102; }
+static_assert(kStageVariants == ESDG_STAGE_VARIANTS, "header and kernels disagree on the variant count");
+
+int esdg_abi_version(void) { return 103; }
 
 void esdg_default_params(esdg_params *p, int N)
 {
@@ -591,6 +612,8 @@ int esdg_destroy(esdg_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_bufs(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->tune_ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
     return ESDG_OK;
 }
@@ -639,9 +662,10 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     std::vector<int32_t> ne(4 * K);
     std::vector<int8_t> ns(4 * K), fl(4 * K);
     if (mem) {
-        CK(hipMemcpy(ne.data(), nbr_elem, 4 * K * sizeof(int32_t), hipMemcpyDeviceToHost));
-        CK(hipMemcpy(ns.data(), nbr_side, 4 * K, hipMemcpyDeviceToHost));
-        CK(hipMemcpy(fl.data(), flip, 4 * K, hipMemcpyDeviceToHost));
+        CK(hipMemcpyAsync(ne.data(), nbr_elem, 4 * K * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipMemcpyAsync(ns.data(), nbr_side, 4 * K, hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipMemcpyAsync(fl.data(), flip, 4 * K, hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
     } else {
         std::memcpy(ne.data(), nbr_elem, 4 * K * sizeof(int32_t));
         std::memcpy(ns.data(), nbr_side, 4 * K);
@@ -672,8 +696,9 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     if (mem) {
         hx.resize(K * npn);
         hy.resize(K * npn);
-        CK(hipMemcpy(hx.data(), x, K * npn * sizeof(double), hipMemcpyDeviceToHost));
-        CK(hipMemcpy(hy.data(), y, K * npn * sizeof(double), hipMemcpyDeviceToHost));
+        CK(hipMemcpyAsync(hx.data(), x, K * npn * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipMemcpyAsync(hy.data(), y, K * npn * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
         xs = hx.data();
         ys = hy.data();
     }
@@ -784,7 +809,7 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         CK(hipMemcpyAsync(B.cinst, cin.data(), cin.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
     }
-    TRY(alloc(ctx, &B.flags, 4 * sizeof(int)));
+    TRY(alloc(ctx, &B.flags, kNumFlags * sizeof(int)));
     int64_t T = 0;
     (void)dispatch(ctx, [&](auto L, auto) {
         T = decltype(L)::threads();
@@ -800,7 +825,7 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     CK(hipMemsetAsync(B.count, 0, 4 * sizeof(int), ctx->stream));
     invalidate_eps(ctx);
     CK(hipMemsetAsync(B.dscal, 0, 8 * ni * sizeof(double), ctx->stream));
-    CK(hipMemsetAsync(B.flags, 0, 4 * sizeof(int), ctx->stream));
+    CK(hipMemsetAsync(B.flags, 0, kNumFlags * sizeof(int), ctx->stream));
     hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)ni), dim3(3 * kDtSlots), 0, ctx->stream, B.slots,
                        0x7FF0000000000000ull, 3 * kDtSlots * ni);
     CK(hipGetLastError());
@@ -824,9 +849,9 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         CK(hipGetLastError());
     }
     CK(dispatch(ctx, [&](auto L, auto) { return decltype(L)::geometry(ctx->B, ctx->td, ctx->stream); }));
-    int flags[4];
+    int flags[kNumFlags];
     TRY(read_flags(ctx, flags));
-    if (flags[3]) {
+    if (flags[kFlagBadJ]) {
         free_bufs(ctx);
         return fail(ctx, ESDG_EMESH, "Jacobian not positive at some node");
     }
@@ -923,10 +948,10 @@ int esdg_limit(esdg_ctx *ctx, int64_t *n_limited)
     }));
     ctx->eps_valid[ctx->cur] = false;
     if (ctx->dtb_buf == ctx->cur) ctx->dtb_buf = -1;
-    int flags[4];
+    int flags[kNumFlags];
     TRY(read_flags(ctx, flags));
-    if (n_limited) *n_limited = flags[1];
-    if (flags[0]) return fail(ctx, ESDG_ENEGMEAN, "negative element mean in the limiter");
+    if (n_limited) *n_limited = flags[kFlagLimited];
+    if (flags[kFlagNegMean]) return fail(ctx, ESDG_ENEGMEAN, "negative element mean in the limiter");
     return ESDG_OK;
 }
 
@@ -964,10 +989,11 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 ctx->cur = base;
                 TRY(launch_one_step(ctx, dt, false));
             }
-            int flags[4];
+            int flags[kNumFlags];
             TRY(read_flags(ctx, flags));
-            if (!flags[0] || attempt >= retries) {
-                if (flags[0]) status = ESDG_ENEGMEAN;
+            if (flags[kFlagNonFinite]) break;   // reported below; halving the step cannot help
+            if (!flags[kFlagNegMean] || attempt >= retries) {
+                if (flags[kFlagNegMean]) status = ESDG_ENEGMEAN;
                 break;
             }
             // negative mean: restart from W^n (untouched) with half the step
@@ -978,11 +1004,16 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
             TRY(reset_flags(ctx));
         }
     }
-    int flags[4];
+    int flags[kNumFlags];
     TRY(read_flags(ctx, flags));
-    if (t_out) CK(hipMemcpy(t_out, ctx->B.dscal + 4, sizeof(double), hipMemcpyDeviceToHost));
-    if (flags[2]) return fail(ctx, ESDG_EDTPOS, "no admissible time step");
-    if (status == ESDG_OK && flags[0] && retries <= 0) status = ESDG_ENEGMEAN;
+    if (t_out) {
+        CK(hipMemcpyAsync(t_out, ctx->B.dscal + 4, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->last_limited = flags[kFlagLimited];
+    if (flags[kFlagNonFinite]) return fail(ctx, ESDG_ENONFINITE, "non-finite value in a stage output");
+    if (flags[kFlagDtPos]) return fail(ctx, ESDG_EDTPOS, "no admissible time step");
+    if (status == ESDG_OK && flags[kFlagNegMean] && retries <= 0) status = ESDG_ENEGMEAN;
     if (status == ESDG_ENEGMEAN) return fail(ctx, ESDG_ENEGMEAN, "negative element mean in the limiter");
     return ESDG_OK;
 }
@@ -1068,7 +1099,7 @@ int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, dou
     return ESDG_OK;
 }
 
-int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2])
+int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[ESDG_STAGE_VARIANTS])
 {
     if (!check_ctx(ctx, true)) return ESDG_EINVAL;
     if (reps < 1 || reps > 1000) return fail(ctx, ESDG_EINVAL, "reps outside [1, 1000]");
@@ -1078,12 +1109,18 @@ int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2])
     if (av) TRY(launch_viscous(ctx, base, -1));
     // trial stages: SSP form W^n -> o1 (W^n and dU untouched), each variant
     // timed over reps launches, twice, alternating
-    hipEvent_t e0 = next_event(ctx), e1 = next_event(ctx);
-    if (!e0 || !e1) return fail(ctx, ESDG_EHIP, "hipEventCreate failed");
-    double best[2] = {1e300, 1e300};
+    if (!ctx->tune_ev[0]) {
+        CK(hipEventCreate(&ctx->tune_ev[0]));
+        CK(hipEventCreate(&ctx->tune_ev[1]));
+    }
+    hipEvent_t e0 = ctx->tune_ev[0], e1 = ctx->tune_ev[1];
+    double best[kStageVariants];
+    for (double &b : best) b = 1e300;
     const int keep = ctx->stage_variant;
+    const bool prof = ctx->prof;
+    ctx->prof = false;   // trial launches stay out of the kernel timings
     for (int round = 0; round < 2; ++round)
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < kStageVariants; ++v) {
             ctx->stage_variant = v;
             CK(hipEventRecord(e0, ctx->stream));
             for (int r = 0; r < reps; ++r) {
@@ -1093,6 +1130,7 @@ int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2])
                 const int st = launch_stage(ctx, sc);
                 if (st) {
                     ctx->stage_variant = keep;
+                    ctx->prof = prof;
                     return st;
                 }
             }
@@ -1102,23 +1140,42 @@ int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[2])
             CK(hipEventElapsedTime(&t, e0, e1));
             best[v] = std::min(best[v], (double)t / reps);
         }
-    ctx->ev_next = 0;
-    ctx->stage_variant = best[1] < best[0] ? 1 : 0;
+    ctx->prof = prof;
+    int pick = 0;
+    for (int v = 1; v < kStageVariants; ++v)
+        if (best[v] < best[pick]) pick = v;
+    ctx->stage_variant = pick;
     ctx->eps_valid[o1] = false;
     if (ctx->dtb_buf == o1) ctx->dtb_buf = -1;
     TRY(reset_flags(ctx));
-    if (choice) *choice = ctx->stage_variant;
-    if (ms) {
-        ms[0] = best[0];
-        ms[1] = best[1];
-    }
+    if (choice) *choice = pick;
+    if (ms)
+        for (int v = 0; v < kStageVariants; ++v) ms[v] = best[v];
     return ESDG_OK;
 }
 
 int esdg_set_stage_variant(esdg_ctx *ctx, int variant)
 {
-    if (!ctx || (variant != 0 && variant != 1)) return ctx ? fail(ctx, ESDG_EINVAL, "variant must be 0 or 1") : ESDG_EINVAL;
+    if (!ctx || variant < 0 || variant >= kStageVariants)
+        return ctx ? fail(ctx, ESDG_EINVAL, "variant outside [0, %d)", kStageVariants) : ESDG_EINVAL;
     ctx->stage_variant = variant;
+    return ESDG_OK;
+}
+
+int esdg_step_stats(esdg_ctx *ctx, int64_t *limited, int64_t *viscous)
+{
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    if (limited) *limited = ctx->last_limited;
+    if (viscous) {
+        *viscous = 0;
+        if (ctx->P.av_on) {
+            TRY(ensure_eps(ctx, ctx->cur));
+            int cnt = 0;
+            CK(hipMemcpyAsync(&cnt, ctx->B.count + ctx->cur, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            CK(hipStreamSynchronize(ctx->stream));
+            *viscous = cnt;
+        }
+    }
     return ESDG_OK;
 }
 
@@ -1139,15 +1196,14 @@ int drain_events(esdg_ctx *ctx)
 {
     CK(hipSetDevice(ctx->device));
     CK(hipStreamSynchronize(ctx->stream));
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> *logs[3] = {&ctx->ev_stage, &ctx->ev_av, &ctx->ev_adj};
-    for (int k = 0; k < 3; ++k) {
-        for (auto &pr : *logs[k]) {
+    for (int k = 0; k < kProfClasses; ++k) {
+        for (auto &pr : ctx->ev_log[k]) {
             float ms = 0;
             CK(hipEventElapsedTime(&ms, pr.first, pr.second));
             ctx->acc_ms[k] += ms;
         }
-        ctx->acc_n[k] += (int64_t)logs[k]->size();
-        logs[k]->clear();
+        ctx->acc_n[k] += (int64_t)ctx->ev_log[k].size();
+        ctx->ev_log[k].clear();
     }
     ctx->ev_next = 0;
     return ESDG_OK;
@@ -1161,11 +1217,31 @@ int esdg_profile_read(esdg_ctx *ctx, double *stage_ms, int64_t *stage_n, double 
 {
     if (!ctx) return ESDG_EINVAL;
     TRY(drain_events(ctx));
-    if (stage_ms) *stage_ms = ctx->acc_ms[0];
-    if (stage_n) *stage_n = ctx->acc_n[0];
-    if (av_ms) *av_ms = ctx->acc_ms[1];
-    if (av_n) *av_n = ctx->acc_n[1];
-    for (int k = 0; k < 2; ++k) {
+    if (stage_ms) *stage_ms = ctx->acc_ms[kProfStage];
+    if (stage_n) *stage_n = ctx->acc_n[kProfStage];
+    const int av[3] = {kProfIndicator, kProfAvFaces, kProfAvDiv};
+    double ams = 0;
+    int64_t an = 0;
+    for (int k : av) {
+        ams += ctx->acc_ms[k];
+        an += ctx->acc_n[k];
+    }
+    if (av_ms) *av_ms = ams;
+    if (av_n) *av_n = an;
+    for (int k : {kProfStage, kProfIndicator, kProfAvFaces, kProfAvDiv, kProfDt}) {
+        ctx->acc_ms[k] = 0;
+        ctx->acc_n[k] = 0;
+    }
+    return ESDG_OK;
+}
+
+int esdg_profile_read_kernels(esdg_ctx *ctx, double ms[6], int64_t launches[6])
+{
+    if (!ctx || !ms || !launches) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    TRY(drain_events(ctx));
+    for (int k = 0; k < kProfClasses; ++k) {
+        ms[k] = ctx->acc_ms[k];
+        launches[k] = ctx->acc_n[k];
         ctx->acc_ms[k] = 0;
         ctx->acc_n[k] = 0;
     }
@@ -1176,10 +1252,10 @@ int esdg_profile_read_adjoint(esdg_ctx *ctx, double *ms, int64_t *n)
 {
     if (!ctx) return ESDG_EINVAL;
     TRY(drain_events(ctx));
-    if (ms) *ms = ctx->acc_ms[2];
-    if (n) *n = ctx->acc_n[2];
-    ctx->acc_ms[2] = 0;
-    ctx->acc_n[2] = 0;
+    if (ms) *ms = ctx->acc_ms[kProfAdjoint];
+    if (n) *n = ctx->acc_n[kProfAdjoint];
+    ctx->acc_ms[kProfAdjoint] = 0;
+    ctx->acc_n[kProfAdjoint] = 0;
     return ESDG_OK;
 }
 
@@ -1391,11 +1467,12 @@ int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
         }
     int status = ESDG_OK;
     for (auto &G : en->groups) {
-        int flags[4];
+        int flags[kNumFlags];
         const int st = read_flags(G.ctx, flags);
         if (st) return efail_ctx(en, G.ctx, st);
-        if (flags[2]) return efail(en, ESDG_EDTPOS, "no admissible time step");
-        if (flags[0]) status = ESDG_ENEGMEAN;
+        if (flags[kFlagNonFinite]) return efail(en, ESDG_ENONFINITE, "non-finite value in a stage output");
+        if (flags[kFlagDtPos]) return efail(en, ESDG_EDTPOS, "no admissible time step");
+        if (flags[kFlagNegMean]) status = ESDG_ENEGMEAN;
     }
     if (status) return efail(en, status, "negative element mean in the limiter");
     return ESDG_OK;
@@ -1621,7 +1698,7 @@ int adj_forward_stage(esdg_ctx *ctx, double *in, double *out, double *base, int 
 
 int adj_stage(esdg_ctx *ctx, const AdjCall &c)
 {
-    return timed(ctx, ctx->ev_adj, [&](Ev ev) {
+    return timed(ctx, kProfAdjoint, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
             return decltype(L)::adjoint_stage(ctx->B, c, phys<R>(ctx), tab<R>(ctx), ctx->stream, ev);
@@ -1800,11 +1877,14 @@ int esdg_adjoint_forward(esdg_ctx *ctx, int nsteps, double dt, int every, const 
     }
     hipLaunchKernelGGL(misfit_loss_kernel, dim3(1), dim3(256), 0, ctx->stream, A.Hg, A.Tg, nh, dt, A.loss);
     CK(hipGetLastError());
-    int flags[4];
+    int flags[kNumFlags];
     TRY(read_flags(ctx, flags));
-    if (flags[0] || flags[1])
+    if (flags[kFlagNegMean] || flags[kFlagLimited])
         return fail(ctx, ESDG_EINVAL, "the limiter acted during the run: outside the adjoint's scope");
-    if (loss) CK(hipMemcpy(loss, A.loss, sizeof(double), hipMemcpyDeviceToHost));
+    if (loss) {
+        CK(hipMemcpyAsync(loss, A.loss, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+    }
     if (H) {
         CK(hipMemcpyAsync(H, A.Hg, nh * sizeof(double), mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                           ctx->stream));

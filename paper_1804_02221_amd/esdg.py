@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesdg.so")
 
 OK, EINVAL, ENOMEM, EHIP, EMESH, ENEGMEAN, EDTPOS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+STAGE_VARIANTS = 4   # ESDG_STAGE_VARIANTS of include/esdg.h
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EMESH: "EMESH", ENEGMEAN: "ENEGMEAN",
           EDTPOS: "EDTPOS", ENONFINITE: "ENONFINITE"}
 
@@ -76,6 +77,7 @@ def lib() -> C.CDLL:
             "esdg_set_time": ([P, D], I),
             "esdg_diagnostics": ([P, P], I),
             "esdg_get_eps": ([P, P, I], I),
+            "esdg_step_stats": ([P, P, P], I),
             "esdg_get_geometry": ([P, P, P, P, P, P, I], I),
             "esdg_profile": ([P, I], I),
             "esdg_profile_read": ([P, P, P, P, P], I),
@@ -100,6 +102,7 @@ def lib() -> C.CDLL:
             "esdg_adjoint_forward": ([P, I, D, I, P, I, P, P], I),
             "esdg_adjoint_backward": ([P, D, P, P, P, P, I], I),
             "esdg_profile_read_adjoint": ([P, P, P], I),
+            "esdg_profile_read_kernels": ([P, P, P], I),
             "esdg_lds_bandwidth": ([I, P], I),
         }
         for name, (args, res) in sig.items():
@@ -312,6 +315,12 @@ class Solver:
         self._check(lib().esdg_diagnostics(self._ctx, out.ctypes.data_as(C.c_void_p)))
         return out
 
+    def step_stats(self):
+        """(limited element-stages of the last step call, viscous elements now)."""
+        lim, vis = C.c_int64(0), C.c_int64(0)
+        self._check(lib().esdg_step_stats(self._ctx, C.byref(lim), C.byref(vis)))
+        return int(lim.value), int(vis.value)
+
     def get_eps(self, device: bool = False):
         (o,) = self._outs(1, self.K, device)
         a = _Arg(o)
@@ -325,9 +334,10 @@ class Solver:
         return dict(zip(("xxi", "xeta", "yxi", "yeta", "J"), self._shape(outs)))
 
     def autotune(self, reps: int = 5):
-        """Pick the faster stage-kernel workgroup size; returns (choice, [ms0, ms1])."""
+        """Pick the fastest compiled stage-kernel variant; returns (choice,
+        mean ms per variant)."""
         c = C.c_int(0)
-        ms = np.zeros(2)
+        ms = np.zeros(STAGE_VARIANTS)
         self._check(lib().esdg_autotune(self._ctx, int(reps), C.byref(c), ms.ctypes.data_as(C.c_void_p)))
         return c.value, ms
 
@@ -341,6 +351,17 @@ class Solver:
         sm, sn, am, an = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
         self._check(lib().esdg_profile_read(self._ctx, C.byref(sm), C.byref(sn), C.byref(am), C.byref(an)))
         return dict(stage_ms=sm.value, stage_launches=sn.value, av_ms=am.value, av_launches=an.value)
+
+    KERNEL_CLASSES = ("stage", "indicator", "av_faces", "av_div", "dt", "adjoint")
+
+    def profile_read_kernels(self):
+        """Summed event milliseconds and launch counts per kernel class since
+        the last read (then reset): {class: (ms, launches)}."""
+        ms = np.zeros(6)
+        n = np.zeros(6, dtype=np.int64)
+        self._check(lib().esdg_profile_read_kernels(self._ctx, ms.ctypes.data_as(C.c_void_p),
+                                                    n.ctypes.data_as(C.c_void_p)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_CLASSES)}
 
     def profile_read_adjoint(self):
         ms, n = C.c_double(), C.c_int64()

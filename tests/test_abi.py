@@ -32,4 +32,4 @@ def test_default_params_host_only():
     p = esdg.default_params(7)
     assert p.g == 9.81 and p.h_tol == 1e-4 and p.cfl == 0.5
     assert p.sigma_min < p.sigma_max
-    assert esdg.lib().esdg_abi_version() == 102
+    assert esdg.lib().esdg_abi_version() == 103

@@ -20,11 +20,11 @@ TOL_VJP = 1e-12
 TOL_GRAD = 1e-10
 # Richardson-extrapolated central differences (steps 1e-4 and 5e-5) of the
 # full-size loss along continuous random directions (bathymetries stay
-# continuous, as the method assumes): the loss is smooth along them and the
-# extrapolation is accurate to ~1e-9 relative.  (Along directions that differ
-# between coincident nodes, b jumps across faces, the lake at rest is lost
-# at first order and velocities cross zero at the |.| kinks of the
-# dissipation: differences then carry an O(eps) error.)
+# continuous): the loss is smooth along them and the extrapolation is
+# accurate to ~1e-9 relative.  (Along directions that differ between
+# coincident nodes, b jumps across faces and the velocities of the resting
+# water cross zero at the |.| kinks of the dissipation: differences then
+# carry an O(eps) error.)
 FD_TOL = 1e-6
 
 
@@ -70,6 +70,21 @@ def test_rhs_vjp_parity(esdg, orc, N, n, ec, rot):
     got = s.rhs_vjp(*lam)
     want = orc.rhs_vjp(oparams(orc, P), w.mesh, w.b, w.h, w.hu, w.hv, *lam)
     check(got, want, TOL_VJP, f"N={N}")
+    s.close()
+
+
+@pytest.mark.parametrize("N,rot,ec", [(3, 3, 0), (6, None, 1), (8, 8, 0)])
+def test_rhs_vjp_parity_jumping_bottom(esdg, orc, N, rot, ec):
+    """A bottom that jumps at every face: the reverse mode of the interface
+    bathymetry penalty (eq. SourceDisc) on both sides of each face."""
+    w = smooth_sweep(4, N, seed=90 + N, rotate_seed=rot)
+    b = w.b + 0.15 * np.random.default_rng(N).uniform(size=(w.mesh.K, 1))
+    s, P = make_solver(esdg, w.mesh, b, w.h, w.hu, w.hv, N, surface_flux=ec, limiter_on=1)
+    rng = np.random.default_rng(200 + N)
+    lam = [rng.standard_normal(w.h.shape) for _ in range(3)]
+    got = s.rhs_vjp(*lam)
+    want = orc.rhs_vjp(oparams(orc, P), w.mesh, b, w.h, w.hu, w.hv, *lam)
+    check(got, want, TOL_VJP, f"jumping bottom N={N}")
     s.close()
 
 
