@@ -7,9 +7,17 @@ benchmark's CPU-baseline leg may import it; the product path never does.
 The arithmetic lives in ``esdg_oracle.c`` (plain C, built with
 ``gcc -O2 -ffp-contract=off``; OpenMP over elements, bitwise independent of
 the thread count); this module only marshals numpy arrays.
+
+A second build of the same source, the *rounding twin*, lets the compiler
+fuse multiplies and adds (``-ffp-contract=fast -mfma``): the same formulas
+in the same order, rounded differently.  The tests use the spread between
+the two builds as the size of a pure rounding-order difference (see
+``tests/parity_floor.py``); ``rounding_twin()`` switches every function of
+this module to it for the duration of a ``with`` block.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 import os
@@ -20,18 +28,41 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "esdg_oracle.c")
 _LIB = os.path.join(_HERE, "libesdg_oracle.so")
+_LIB_TWIN = os.path.join(_HERE, "libesdg_oracle_fma.so")
 
 OK, EINVAL, ENOMEM, ENEGMEAN = 0, -1, -2, -5
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle shared library in place (gcc, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+_FLAGS = {_LIB: ["-ffp-contract=off"], _LIB_TWIN: ["-ffp-contract=fast", "-mfma", "-mavx2"]}
+
+
+def _build_one(path: str, force: bool) -> None:
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O2", *_FLAGS[path], "-fno-fast-math", "-std=c11",
                                "-fopenmp", "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+        os.replace(tmp, path)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library and its rounding twin in place (gcc,
+    no fast-math)."""
+    _build_one(_LIB, force)
+    _build_one(_LIB_TWIN, force)
     return _LIB
+
+
+def host_has_fma() -> bool:
+    """True when the host CPU executes the twin's fused multiply-adds."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("flags"):
+                    fl = line.split()
+                    return "fma" in fl and "avx2" in fl
+    except OSError:
+        pass
+    return False
 
 
 class Params(C.Structure):
@@ -51,15 +82,29 @@ class _Parts(C.Structure):
                 ("grad", C.c_void_p * 4)]
 
 
-_lib = None
+_libs = {}
+_active = _LIB
+
+
+@contextlib.contextmanager
+def rounding_twin():
+    """Within the block every function of this module runs the twin build."""
+    global _active
+    if not host_has_fma():
+        raise RuntimeError("the rounding twin needs a host CPU with FMA and AVX2")
+    prev, _active = _active, _LIB_TWIN
+    try:
+        yield
+    finally:
+        _active = prev
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+    path = _active
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _build_one(path, force=True)
+        L = C.CDLL(path)
         P, I, I64 = C.c_void_p, C.c_int, C.c_int64
         L.orc_operators.argtypes = [I, P, P, P, P, P, P]
         L.orc_geometry.argtypes = [I, I64, P, P, P, P, P, P, P]
@@ -79,8 +124,8 @@ def lib():
         L.orc_rhs_vjp.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_gauge_adjoint.argtypes = [P, P, P, P, P, P, I, C.c_double, I, P, P, P, P, P, P,
                                         P, P, P, P]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _p(a):
