@@ -127,6 +127,46 @@ def test_lemma2_bound_is_nearly_sharp(orc, N):
     assert m4[e] < 0
 
 
+@pytest.mark.parametrize("N", [3, 5])
+def test_lemma2_second_bound_only_where_it_can_bind(orc, N):
+    """Reading of Lemma 2's second bound (eq. CFLConstraints): the proof
+    (eq. UpdateConditions) shows that the third term, h^- + dt/(g w_0 a)
+    {c} B [[u~]], can only turn negative where {c} B [[u~]] < 0, so the bound
+    is enforced there only.  State: an element holding a thin film
+    (h = 1e-3, u~ = 0.1) beside a deep, fast neighbour (h = 1, u~ = 3) that
+    moves away from it: B [[u~]] > 0 at their shared face, where the printed
+    formula taken unconditionally would allow a step about two orders of
+    magnitude smaller.  One Euler step at the oracle's dt_pos keeps every
+    element mean non-negative, and the film's mean grows."""
+    nx = 4
+    mesh = make_periodic_mesh(N, nx, nx, 4.0, 4.0)      # Cartesian: unit normals +-x, +-y
+    K, npn = mesh.K, mesh.n_p
+    h = np.full((K, npn), 0.5)
+    u = np.zeros((K, npn))
+    e_film, e_deep = 5, 6                                # e = iy*nx + ix: e_deep is the +x neighbour
+    h[e_film], u[e_film] = 1e-3, 0.1
+    h[e_deep], u[e_deep] = 1.0, 3.0
+    hu, hv = h * u, np.zeros_like(h)
+    b = np.zeros_like(h)
+    P = orc.params(N, limiter_on=1)
+    dt_pos = orc.dt(P, mesh, b, h, hu, hv)[3]
+    # the printed second bound at the shared face (side xi = +1 of the film):
+    # a = J / J^surf = dx / 2 on this mesh, w_0 = 2 / (N (N + 1))
+    w0, a = 2.0 / (N * (N + 1)), 0.5
+    um, up = 0.1, 3.0
+    cbar = 0.5 * (np.sqrt(G * 1e-3) + np.sqrt(G * 1.0))
+    ubar = 0.5 * (um + up)
+    B = abs(ubar + cbar) - abs(ubar - cbar)
+    assert B * (up - um) > 0
+    printed = abs(w0 * a * G * 1e-3 / (cbar * B * (up - um)))
+    assert dt_pos > 50 * printed
+    Rh = orc.rhs(P, mesh, b, h, hu, hv)[0]
+    (m0,), _ = means(orc, mesh, h)
+    (m1,), _ = means(orc, mesh, h + dt_pos * Rh)
+    assert m1.min() >= 0.0
+    assert m1[e_film] > m0[e_film]
+
+
 def test_lake_at_rest_100_steps(orc):
     """End to end: 16x16 N=3 lake at rest (no bump) stays at rest over 100
     LSRK(5,4) steps at CFL 0.5."""
