@@ -914,12 +914,17 @@ struct StageArgs {
 };
 
 // Face slot data loaded ahead of the LDS staging (slots t, t + T, ... of lane t).
+// Kept small (it is live across the LDS staging): the neighbour element as
+// int32 and one packed word, the neighbour node's index recomputed from them.
 template <typename R>
 struct FacePrefetch {
-    int64_t qn = 0, en = 0;
-    int ns = 0, kk = 0;
+    int32_t en = 0;          // neighbour element
+    int code = 0;            // neighbour side | face node << 2 | (visc_nbr) << 8
     R h = 0, hu = 0, hv = 0, bo = 0, bn = 0;
-    bool visc_nbr = false;   // with AV: the element has no viscosity, its neighbour has
+    __device__ int ns() const { return code & 3; }
+    __device__ int kk() const { return (code >> 2) & 63; }
+    // with AV: the element has no viscosity, its neighbour has
+    __device__ bool visc_nbr() const { return (code >> 8) & 1; }
 };
 
 template <int N, typename R, int E, int NF>
@@ -930,16 +935,20 @@ __device__ __forceinline__ void prefetch_face(const StageArgs<R> &a, int t, int6
     const int fel = t / (4 * nf), s = (t / nf) & 3, k = t - (t / nf) * nf;
     const int64_t fe = e0 + fel;
     if (fe >= a.m.K) return;
-    pf.qn = nbr_node<N>(a.m, fe, s, k, pf.en, pf.ns, pf.kk);
-    const int64_t ql = pf.qn - e0 * np;
+    int64_t en;
+    int ns, kk;
+    const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+    const int64_t ql = qn - e0 * np;
     if (!(ql >= 0 && ql < E * np)) {
-        pf.h = a.h[pf.qn];
-        pf.hu = a.hu[pf.qn];
-        pf.hv = a.hv[pf.qn];
+        pf.h = a.h[qn];
+        pf.hu = a.hu[qn];
+        pf.hv = a.hv[qn];
     }
     pf.bo = a.m.bface[(fe * 4 + s) * nf + k];
-    pf.bn = a.m.bface[(pf.en * 4 + pf.ns) * nf + pf.kk];
-    if (a.eps) pf.visc_nbr = !(a.eps[fe] > R(0)) && a.eps[pf.en] > R(0);
+    pf.bn = a.m.bface[(en * 4 + ns) * nf + kk];
+    const bool vn = a.eps && !(a.eps[fe] > R(0)) && a.eps[en] > R(0);
+    pf.en = (int32_t)en;
+    pf.code = ns | (kk << 2) | ((int)vn << 8);
 }
 
 template <int N, typename R, int MODE, int V>
@@ -986,8 +995,13 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     // seven elements' 84 face nodes outnumber the 64 lanes).
     constexpr int NS = (NF + T - 1) / T;
     FacePrefetch<R> pf[NS];
+    if constexpr (NS == 1) {
+        // (a one-trip loop here costs a VGPR and a dozen spilled SGPRs at N = 7)
+        prefetch_face<N, R, E, NF>(a, t, e0, pf[0]);
+    } else {
 #pragma unroll
-    for (int r = 0; r < NS; ++r) prefetch_face<N, R, E, NF>(a, t + r * T, e0, pf[r]);
+        for (int r = 0; r < NS; ++r) prefetch_face<N, R, E, NF>(a, t + r * T, e0, pf[r]);
+    }
     const R eps_e = (av && act) ? a.eps[e] : R(0);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
@@ -1014,8 +1028,11 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             int fi, fj;
             side_node<N>(s, k, fi, fj);
             const int lp = fel * np + fi * nf + fj;
-            const int64_t qn = pfr.qn, en = pfr.en;
-            const int ns = pfr.ns, kk = pfr.kk;
+            const int64_t en = pfr.en;
+            const int ns = pfr.ns(), kk = pfr.kk();
+            int ni, nj;
+            side_node<N>(ns, kk, ni, nj);
+            const int64_t qn = en * np + ni * nf + nj;
             // outward scaled normal: +-J grad(xi) on xi = +-1, +-J grad(eta) on eta = +-1
             const V2 dir = (s & 1) ? s_a[lp] : s_b[lp];
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
@@ -1050,7 +1067,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             // (zero for a continuous bottom and at walls, where bn = bo)
             const R pen = R(0.25) * P.g * a.tab.iw0 * (s_h[lp] + hn) * (bn - bo);
             c1 += pen * snx; c2 += pen * sny;
-            if (av && pfr.visc_nbr) {
+            if (av && pfr.visc_nbr()) {
                 const R *vn = a.vtr + ((en * 4 + ns) * nf + kk) * 4;
                 const R hw = R(0.5) * a.tab.iw0;
                 c1 -= hw * (snx * vn[0] + sny * vn[2]);
@@ -1406,6 +1423,31 @@ __device__ __forceinline__ R lemma2_bound(const DtArgs<R> &a, int64_t f)
     return posb;
 }
 
+// Minimum of the Lemma 2 bounds over the face nodes of range r.  Each
+// iteration takes U face nodes at once, with clamped indices and no branch,
+// so that the loads of all U (face map, then both traces) are in flight
+// together; the minimum does not depend on the order.
+template <int N, typename R>
+__device__ __forceinline__ R lemma2_min(const DtArgs<R> &a, XcdRange r)
+{
+    constexpr int U = 4;
+    R posb = R(3.0e38);
+    for (; r.b < r.e; r.b += U * r.stride) {
+        R v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t f = r.b + u * r.stride;
+            v[u] = lemma2_bound<N, R>(a, f < r.e ? f : r.e - 1);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = r.b + u * r.stride < r.e;
+            posb = (in && v[u] < posb) ? v[u] : posb;
+        }
+    }
+    return posb;
+}
+
 // CFL bound at node q from the stored state and metric.
 template <int N, typename R>
 __device__ __forceinline__ R cfl_node(const DtArgs<R> &a, int64_t q)
@@ -1470,12 +1512,7 @@ __global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
             }
         }
     }
-    if (a.P.limiter_on) {
-        for (XcdRange r(K * 4 * nf, T); r.b < r.e; r.b += r.stride) {
-            const R v = lemma2_bound<N, R>(a, r.b);
-            posb = v < posb ? v : posb;
-        }
-    }
+    if (a.P.limiter_on) posb = lemma2_min<N, R>(a, XcdRange(K * 4 * nf, T));
     dt_block_min<R>(cflb, viscb, posb, a.slots, blockIdx.x % kDtSlots);
 }
 
