@@ -475,8 +475,15 @@ class Ensemble:
     def build(self):
         self._check(lib().esdg_ensemble_build(self._h))
 
-    def step(self, nsteps: int):
-        self._check(lib().esdg_ensemble_step(self._h, int(nsteps)))
+    def step(self, nsteps: int, raise_negmean: bool = True) -> int:
+        """Advance every instance nsteps steps; returns the status (ENEGMEAN
+        only with raise_negmean=False: an element mean went negative, the
+        limiter set it to its mean, the states are finite)."""
+        st = lib().esdg_ensemble_step(self._h, int(nsteps))
+        if st == ENEGMEAN and not raise_negmean:
+            return st
+        self._check(st)
+        return st
 
     def __len__(self):
         n = C.c_int(0)

@@ -346,7 +346,9 @@ def ensemble_member(n: int, N: int, dam: bool, seed: int) -> Workload:
     the dam break (h = 1 for undeformed centroid X < 5, else dry) or, when
     not dam, a wet Gaussian surface bump H = 1.2 + 0.1 exp(-|x - x0|^2) over
     the bed (h = max(H - b, 0)); at rest.  AV and limiter on; eps0 = 0.05 at
-    N = 3, 0.025 otherwise."""
+    N = 3, 0.025 otherwise; SSPRK(3,3), the integrator the paper adopts for
+    wet/dry runs because Lemma 2's mean positivity covers it (section 2.2,
+    eq. RKSSP)."""
     if dam:
         w = dam_break(n, N, seed=seed)
     else:
@@ -363,7 +365,7 @@ def ensemble_member(n: int, N: int, dam: bool, seed: int) -> Workload:
         w = Workload("bump", mesh, _c(b), _c(h), _c(z), _c(z.copy()),
                      dict(g=9.81, surface_flux=0, av_on=1, limiter_on=1, eps0=0.025, cfl=0.5))
     w.name = f"{'dam' if dam else 'bump'}_{n}x{n}_N{N}"
-    w.params = dict(w.params, eps0=0.05 if N == 3 else 0.025)
+    w.params = dict(w.params, eps0=0.05 if N == 3 else 0.025, integrator=1)
     return w
 
 
