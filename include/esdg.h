@@ -185,6 +185,24 @@ int esdg_set_time(esdg_ctx *ctx, double t);
  */
 int esdg_diagnostics(esdg_ctx *ctx, double out[8]);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs as esdg_diagnostics, bitwise (the same kernels, and the partial
+ * sums added in the same order), with the per-workgroup partial sums held
+ * in a fixed device array of the library instead of the context's buffer,
+ * and their final sum taken on the device.  The array holds 65536 partial
+ * rows (4 MiB on each GPU the library runs on, kept until the process
+ * ends); a mesh needing more -- more than 65536 * T nodes, T = 64 threads
+ * per workgroup at N = 2, 3, 7 and 256 at N = 4, 5, 6, 8, i.e. 4,194,304
+ * resp. 16,777,216 nodes -- returns ESDG_EINVAL with the limit in
+ * esdg_last_error.  The call allocates nothing and returns after out[]
+ * has arrived.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap in time on the same GPU (from several host threads or contexts)
+ * race and must be serialised by the caller.
+ */
+int esdg_diagnostics_noalloc(esdg_ctx *ctx, double out[8]);
+
 /* Activity of the hot path's non-smooth parts: *limited (may be NULL) =
  * element-stages the positivity limiter scaled during the last esdg_step
  * call (eq. PosPres); *viscous (may be NULL) = elements of the current state

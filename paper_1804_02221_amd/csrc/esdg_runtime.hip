@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -141,9 +142,63 @@ __global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const
     out[4 * n + o] = ce * ax - cx * ae;
 }
 
+// Diagnostics without allocation (esdg_diagnostics_noalloc): the
+// per-workgroup partial rows of diag_kernel go to a fixed array of the
+// library, `scratch`, one copy per GPU, instead of the context's buffer;
+// row kScratchRows receives the final sums.  Host code never passes the
+// array's name to a kernel or copy: it uses the device address that
+// hipGetSymbolAddress returns for the current GPU (scratch_ptr below).
+constexpr int64_t kScratchRows = 65536;   // 65536 x 8 doubles = 4 MiB
+static __device__ __align__(256) double scratch[(kScratchRows + 1) * 8];
+
+// Sums the nb partial rows in row order, as the host loop of
+// esdg_diagnostics does (the same operations in the same order, so the
+// results are bitwise those of that loop): columns 0-4 and 7 are sums,
+// 5 a minimum, 6 a maximum.  One lane per column.
+__global__ void diag_reduce_kernel(const double *__restrict__ part, int64_t nb, double *__restrict__ out)
+{
+    const int c = threadIdx.x;
+    if (c >= 8) return;
+    double acc = c == 5 ? __builtin_huge_val() : (c == 6 ? -__builtin_huge_val() : 0.0);
+#pragma unroll 8
+    for (int64_t b = 0; b < nb; ++b) {
+        const double v = part[b * 8 + c];
+        acc = c == 5 ? fmin(acc, v) : (c == 6 ? fmax(acc, v) : acc + v);
+    }
+    out[c] = acc;
+}
+
 }  // namespace esdg
 
 using namespace esdg;
+
+namespace {
+
+// Device address of `scratch` on each GPU, looked up once per device (with
+// that device current) by esdg_create.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t lookup_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+    return hipSuccess;
+}
+
+double *scratch_ptr(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
+}  // namespace
 
 struct esdg_ctx {
     int device = 0;
@@ -596,6 +651,8 @@ int esdg_create(esdg_ctx **out, int device, int precision)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ESDG_EHIP;
     if (hipSetDevice(device) != hipSuccess) return ESDG_EHIP;
+    // device address of the fixed diagnostics scratch on this GPU (once per device)
+    if (lookup_scratch(device) != hipSuccess) return ESDG_EHIP;
     esdg_ctx *c = new (std::nothrow) esdg_ctx;
     if (!c) return ESDG_ENOMEM;
     c->device = device;
@@ -1058,6 +1115,40 @@ int esdg_diagnostics(esdg_ctx *ctx, double out[8])
         acc[7] += part[b * 8 + 7];
     }
     std::memcpy(out, acc, sizeof acc);
+    return ESDG_OK;
+}
+
+int esdg_diagnostics_noalloc(esdg_ctx *ctx, double out[8])
+{
+    if (!out) return ctx ? fail(ctx, ESDG_EINVAL, "null pointer") : ESDG_EINVAL;
+    if (!check_ctx(ctx, true)) return ESDG_EINVAL;
+    double *sc = scratch_ptr(ctx->device);
+    if (!sc) return fail(ctx, ESDG_EHIP, "no scratch address for device %d", ctx->device);
+    int64_t T = 0;
+    (void)dispatch(ctx, [&](auto L, auto) {
+        T = decltype(L)::threads();
+        return hipSuccess;
+    });
+    const int64_t nb = (ctx->K * (int64_t)(ctx->N + 1) * (ctx->N + 1) + T - 1) / T;
+    if (nb > kScratchRows)
+        return fail(ctx, ESDG_EINVAL,
+                    "mesh too large for esdg_diagnostics_noalloc: %lld partial rows of %lld threads, "
+                    "the fixed scratch holds %lld (at most %lld nodes at this degree)",
+                    (long long)nb, (long long)T, (long long)kScratchRows, (long long)(kScratchRows * T));
+    TRY(run_rhs(ctx, ctx->cur));
+    Bufs B = ctx->B;
+    B.part = sc;
+    B.part_cap = kScratchRows;
+    int64_t nb2 = 0;
+    CK(dispatch(ctx, [&](auto L, auto r) {
+        using R = decltype(r);
+        return decltype(L)::diag(B, ctx->cur, phys<R>(ctx), tab<R>(ctx), &nb2, ctx->stream);
+    }));
+    double *fin = sc + kScratchRows * 8;
+    hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(64), 0, ctx->stream, sc, nb2, fin);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(out, fin, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
     return ESDG_OK;
 }
 

@@ -76,6 +76,7 @@ def lib() -> C.CDLL:
             "esdg_get_time": ([P, P], I),
             "esdg_set_time": ([P, D], I),
             "esdg_diagnostics": ([P, P], I),
+            "esdg_diagnostics_noalloc": ([P, P], I),
             "esdg_get_eps": ([P, P, I], I),
             "esdg_step_stats": ([P, P, P], I),
             "esdg_get_geometry": ([P, P, P, P, P, P, I], I),
@@ -313,6 +314,12 @@ class Solver:
     def diagnostics(self):
         out = np.zeros(8)
         self._check(lib().esdg_diagnostics(self._ctx, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def diagnostics_noalloc(self):
+        """esdg_diagnostics_noalloc: the same outputs, no device allocation."""
+        out = np.zeros(8)
+        self._check(lib().esdg_diagnostics_noalloc(self._ctx, out.ctypes.data_as(C.c_void_p)))
         return out
 
     def step_stats(self):
