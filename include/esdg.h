@@ -173,6 +173,20 @@ int esdg_compute_dt(esdg_ctx *ctx, double out[4]);
  */
 int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out);
 
+/*
+ * Graph replay of esdg_step (enable = 1, the default; an ensemble replays
+ * per degree group).  Once the launch sequence of a step is fixed -- kernel
+ * timing off, max_dt_retries = 0, the current state's viscosity and (for an
+ * adaptive step) its time-step bounds already on the device -- each step
+ * is launched as one HIP graph captured from the same launches: one graph
+ * per start state buffer, kept until the parameters, the stage variant, the
+ * fixed step or the mesh change.  Results are bitwise those of the eager
+ * launches.  enable = 0 launches every kernel separately and frees the
+ * graphs.  If graph capture fails the context falls back to eager launches
+ * for good.
+ */
+int esdg_set_graphs(esdg_ctx *ctx, int enable);
+
 /* Accumulated simulation time, and its reset. */
 int esdg_get_time(esdg_ctx *ctx, double *t);
 int esdg_set_time(esdg_ctx *ctx, double t);

@@ -32,6 +32,16 @@ static Mesh<R> mesh_view(const Bufs &B)
     return m;
 }
 
+// Kernel launch with the optional timing events recorded by the dispatch
+// itself; without events a plain launch (which stream capture records as a
+// kernel node).
+template <typename Kern, typename... Args>
+static void launch_ev(Kern kernel, dim3 grid, dim3 block, hipStream_t s, Ev ev, Args... args)
+{
+    if (ev.a) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev.a, ev.b, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 template <int N>
 static int64_t ntiles_of(int64_t K)
 {
@@ -100,7 +110,7 @@ hipError_t Launch<N, R>::indicator(const Bufs &B, int buf, const Phys<R> &P, con
     a.list = B.list[buf];
     a.count = B.count + buf;
     a.ntiles = ntiles_of<N>(B.K);
-    hipExtLaunchKernelGGL((indicator_kernel<N, R>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0, a);
+    launch_ev(indicator_kernel<N, R>, tile_grid<N>(B.K), dim3(Shape<N>::T), s, ev, a);
     return hipGetLastError();
 }
 
@@ -133,8 +143,7 @@ template <int N, typename R>
 hipError_t Launch<N, R>::av_faces(const Bufs &B, int in, const Phys<R> &P, const Tab<R> &t, hipStream_t s,
                                   Ev ev)
 {
-    hipExtLaunchKernelGGL((av_faces_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0,
-                          list_args<N, R>(B, in, P, t));
+    launch_ev(av_faces_kernel<N, R>, dim3(kListBlocks), dim3(Shape<N>::T), s, ev, list_args<N, R>(B, in, P, t));
     return hipGetLastError();
 }
 
@@ -144,7 +153,7 @@ hipError_t Launch<N, R>::av_div(const Bufs &B, int in, int reset, const Phys<R> 
 {
     ListArgs<N, R> a = list_args<N, R>(B, in, P, t);
     a.count_reset = reset >= 0 ? B.count + reset : nullptr;
-    hipExtLaunchKernelGGL((av_div_kernel<N, R>), dim3(kListBlocks), dim3(Shape<N>::T), 0, s, ev.a, ev.b, 0, a);
+    launch_ev(av_div_kernel<N, R>, dim3(kListBlocks), dim3(Shape<N>::T), s, ev, a);
     return hipGetLastError();
 }
 
@@ -154,7 +163,7 @@ static void launch_stage_variant(StageArgs<R> a, int64_t K, hipStream_t s, Ev ev
     using S = TileShape<N, StageCfg<N, V>::T>;
     a.ntiles = (K + S::E - 1) / S::E;
     const dim3 grid((unsigned)(((a.ntiles + kXcds - 1) / kXcds) * kXcds));
-    hipExtLaunchKernelGGL((stage_kernel<N, R, MODE, V>), grid, dim3(S::T), 0, s, ev.a, ev.b, 0, a);
+    launch_ev(stage_kernel<N, R, MODE, V>, grid, dim3(S::T), s, ev, a);
 }
 
 template <int N, typename R, int MODE>
@@ -201,6 +210,7 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.count_out = c.out_rhs ? nullptr : B.count + c.out;
     a.dtc_out = c.dt_next && !c.out_rhs ? (R *)B.dtc : nullptr;
     a.dtv_out = c.dt_next && !c.out_rhs && c.av ? (R *)B.dtv : nullptr;
+    a.frec_out = c.dt_next && !c.out_rhs && P.limiter_on ? (R *)B.frec : nullptr;
     a.gmax = (const R *)B.gmax;
     a.inst = B.n_inst > 1 ? B.inst : nullptr;
     a.dt = B.dscal;
@@ -236,20 +246,21 @@ hipError_t Launch<N, R>::dt(const Bufs &B, int in, bool av, bool fused, const Ph
     a.dtv = fused && av ? (const R *)B.dtv : nullptr;
     a.gmax = (const R *)B.gmax;
     a.fgeo = (const R *)B.fgeo;
+    a.frec = fused && P.limiter_on ? (const R *)B.frec : nullptr;
     a.slots = B.slots;
     a.cstart = B.cstart;
     a.cinst = B.cinst;
     a.nchunks = B.nchunks;
     if (B.n_inst > 1) {
         const unsigned grid = (unsigned)(B.nchunks < (int64_t)kDtMaxBlocks ? B.nchunks : (int64_t)kDtMaxBlocks);
-        hipExtLaunchKernelGGL((dt_batch_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, ev.a, ev.b, 0, a);
+        launch_ev(dt_batch_kernel<N, R>, dim3(grid), dim3(kDtThreads), s, ev, a);
         return hipGetLastError();
     }
     constexpr int64_t np = (N + 1) * (N + 1);
     const int64_t items = fused ? B.K * 4 * (N + 1) : B.K * np;
     const int64_t want = ((items + kDtThreads * kXcds - 1) / (kDtThreads * kXcds)) * kXcds;
     const unsigned grid = (unsigned)(want < (int64_t)kDtMaxBlocks ? want : (int64_t)kDtMaxBlocks);
-    hipExtLaunchKernelGGL((dt_kernel<N, R>), dim3(grid), dim3(kDtThreads), 0, s, ev.a, ev.b, 0, a);
+    launch_ev(dt_kernel<N, R>, dim3(grid), dim3(kDtThreads), s, ev, a);
     return hipGetLastError();
 }
 
@@ -296,8 +307,7 @@ hipError_t Launch<N, R>::adjoint_stage(const Bufs &B, const AdjCall &c, const Ph
         a.dt = c.dt;
         a.sa = c.sa;
         a.ntiles = ntiles_of<N>(B.K);
-        hipExtLaunchKernelGGL((adjoint_stage_kernel<N>), tile_grid<N>(B.K), dim3(Shape<N>::T), 0, s, ev.a, ev.b,
-                              0, a);
+        launch_ev(adjoint_stage_kernel<N>, tile_grid<N>(B.K), dim3(Shape<N>::T), s, ev, a);
         return hipGetLastError();
     } else {
         (void)B; (void)c; (void)P; (void)t; (void)s; (void)ev;

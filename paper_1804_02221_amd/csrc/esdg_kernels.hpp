@@ -904,6 +904,7 @@ struct StageArgs {
     int32_t *list_out;           // elements of the output state with eps > 0
     int *count_out;
     R *dtc_out, *dtv_out;        // last stage of a step: per-element CFL / viscous bounds of the output
+    R *frec_out;                 // with them (limiter on): face records [K][4][nf][3] (h, u, v) of the output
     const int32_t *inst;         // [K] instance of each element (ensembles), nullptr: one instance
     const R *gmax;               // [K] max |grad xi|^2 + |grad eta|^2 (viscous bound)
     const double *dt;            // per instance k: the current step at dt[8k]
@@ -1226,6 +1227,24 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             }
         }
         if (a.dtc_out) {
+            // face records of the new state for the Lemma 2 bounds of the
+            // next step: per face node the height and both velocities, the
+            // values the time-step pass would read from the state (corner
+            // nodes write both sides)
+            if (a.frec_out && act) {
+                const R ihn = rcp_wet(nh, P.h_tol);
+                const R un = nhu * ihn, vn = nhv * ihn;
+                auto rec = [&](int s, int k) {
+                    R *const r = a.frec_out + ((e * 4 + s) * nf + k) * 3;
+                    r[0] = nh;
+                    r[1] = un;
+                    r[2] = vn;
+                };
+                if (j == 0) rec(0, i);
+                if (i == N) rec(1, j);
+                if (j == N) rec(2, i);
+                if (i == 0) rec(3, j);
+            }
             // CFL and viscous bounds of the new state for the next step
             R vals[1] = {act ? cfl_bound<N, R>(nh, nhu, nhv, Ax, Cx, Ae, Ce, J, P) : R(3.0e38)};
             lds_sync<T>();   // scratch free
@@ -1312,6 +1331,7 @@ struct DtArgs {
     const R *dtc, *dtv;        // per-element CFL / viscous bounds from the stage epilogue (nullptr: full pass)
     const R *gmax;             // [K] max over the element's nodes of |grad xi|^2 + |grad eta|^2
     const R *fgeo;             // [K][4][nf][3] outward unit normal and w_0 J / J^surf per face node
+    const R *frec;             // with dtc: [K][4][nf][3] face records (h, u, v) of the state
     unsigned long long *slots; // [instance][3][kDtSlots]
     const int64_t *cstart;     // ensembles: element chunks [cstart[c], cstart[c+1]) inside one instance
     const int32_t *cinst;      //   and the instance of chunk c
@@ -1394,6 +1414,22 @@ struct XcdRange {
     }
 };
 
+// The two bounds of eq. CFLConstraints for own trace (hm, utm) and
+// neighbour (hp, utp), normal velocities along the outward unit normal.
+template <typename R>
+__device__ __forceinline__ R lemma2_formula(R hm, R hp, R utm, R utp, R w0a, const Phys<R> &P)
+{
+    const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
+    const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
+    const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
+    R posb = R(3.0e38);
+    const R den1 = A + R(2) * au;
+    if (den1 > R(0)) { const R bnd = w0a / den1; posb = bnd < posb ? bnd : posb; }
+    const R den2 = ac * B * (utp - utm);
+    if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0a * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
+    return posb;
+}
+
 // Lemma 2 bounds at face node f (own trace '-', neighbour '+').
 template <int N, typename R>
 __device__ __forceinline__ R lemma2_bound(const DtArgs<R> &a, int64_t f)
@@ -1412,22 +1448,34 @@ __device__ __forceinline__ R lemma2_bound(const DtArgs<R> &a, int64_t f)
     const R im = rcp_wet(hm, P.h_tol), ip = rcp_wet(hp, P.h_tol);
     const R utm = nx * (a.hu[qo] * im) + ny * (a.hv[qo] * im);
     const R utp = is_wall(a.m, fe, s) ? -utm : nx * (a.hu[qn] * ip) + ny * (a.hv[qn] * ip);
-    const R cm = sqrt(P.g * (hm > R(0) ? hm : R(0))), cp = sqrt(P.g * (hp > R(0) ? hp : R(0)));
-    const R au = R(0.5) * (utm + utp), ac = R(0.5) * (cm + cp);
-    const R A = fabs(au + ac) + fabs(au - ac), B = fabs(au + ac) - fabs(au - ac);
-    R posb = R(3.0e38);
-    const R den1 = A + R(2) * au;
-    if (den1 > R(0)) { const R bnd = w0a / den1; posb = bnd < posb ? bnd : posb; }
-    const R den2 = ac * B * (utp - utm);
-    if (hm > R(0) && den2 < R(0)) { const R bnd = fabs(w0a * P.g * hm / den2); posb = bnd < posb ? bnd : posb; }
-    return posb;
+    return lemma2_formula<R>(hm, hp, utm, utp, w0a, P);
+}
+
+// Lemma 2 bounds at face node f from the face records the last stage left:
+// the same heights and velocities lemma2_bound reads from the state, so the
+// same bounds bit for bit, without reading whole elements.
+template <int N, typename R>
+__device__ __forceinline__ R lemma2_bound_rec(const DtArgs<R> &a, int64_t f)
+{
+    constexpr int nf = N + 1;
+    const int64_t fe = f / (4 * nf);
+    const int rr = (int)(f - fe * 4 * nf), s = rr / nf, k = rr - s * nf;
+    const int64_t en = a.m.nbr[fe * 4 + s];
+    const int c = a.m.code[fe * 4 + s];
+    const int ns = c & 3, kk = ((c >> 2) & 1) ? N - k : k;
+    const R *const rm = a.frec + f * 3, *const rp = a.frec + ((en * 4 + ns) * nf + kk) * 3;
+    const R nx = a.fgeo[f * 3 + 0], ny = a.fgeo[f * 3 + 1], w0a = a.fgeo[f * 3 + 2];
+    const R hm = rm[0], hp = rp[0];
+    const R utm = nx * rm[1] + ny * rm[2];
+    const R utp = is_wall(a.m, fe, s) ? -utm : nx * rp[1] + ny * rp[2];
+    return lemma2_formula<R>(hm, hp, utm, utp, w0a, a.P);
 }
 
 // Minimum of the Lemma 2 bounds over the face nodes of range r.  Each
 // iteration takes U face nodes at once, with clamped indices and no branch,
 // so that the loads of all U (face map, then both traces) are in flight
 // together; the minimum does not depend on the order.
-template <int N, typename R>
+template <int N, typename R, bool REC>
 __device__ __forceinline__ R lemma2_min(const DtArgs<R> &a, XcdRange r)
 {
     constexpr int U = 4;
@@ -1437,7 +1485,9 @@ __device__ __forceinline__ R lemma2_min(const DtArgs<R> &a, XcdRange r)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t f = r.b + u * r.stride;
-            v[u] = lemma2_bound<N, R>(a, f < r.e ? f : r.e - 1);
+            const int64_t fc = f < r.e ? f : r.e - 1;
+            if constexpr (REC) v[u] = lemma2_bound_rec<N, R>(a, fc);
+            else v[u] = lemma2_bound<N, R>(a, fc);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1512,7 +1562,11 @@ __global__ __launch_bounds__(kDtThreads) void dt_kernel(DtArgs<R> a)
             }
         }
     }
-    if (a.P.limiter_on) posb = lemma2_min<N, R>(a, XcdRange(K * 4 * nf, T));
+    if (a.P.limiter_on) {
+        // after a step: the face records its last stage left (with dtc)
+        posb = a.frec ? lemma2_min<N, R, true>(a, XcdRange(K * 4 * nf, T))
+                      : lemma2_min<N, R, false>(a, XcdRange(K * 4 * nf, T));
+    }
     dt_block_min<R>(cflb, viscb, posb, a.slots, blockIdx.x % kDtSlots);
 }
 
@@ -1553,7 +1607,7 @@ __global__ __launch_bounds__(kDtThreads) void dt_batch_kernel(DtArgs<R> a)
         }
         if (a.P.limiter_on) {
             for (int64_t f = lo * 4 * nf + t; f < hi * 4 * nf; f += T) {
-                const R v = lemma2_bound<N, R>(a, f);
+                const R v = a.frec ? lemma2_bound_rec<N, R>(a, f) : lemma2_bound<N, R>(a, f);
                 posb = v < posb ? v : posb;
             }
         }

@@ -25,6 +25,7 @@ struct Bufs {
     void *gmax = nullptr;    // [K] max |grad xi|^2 + |grad eta|^2 per element (mesh constant)
     void *tabg = nullptr;    // Tab<R> in device memory
     void *fgeo = nullptr;    // [K][4][nf][3] face unit normals and w_0 J / J^surf (mesh constant)
+    void *frec = nullptr;    // [K][4][nf][3] face records (h, u, v) of the state whose bounds are in dtc
     void *dtc = nullptr, *dtv = nullptr;  // [K] per-element CFL / viscous bounds of one state
     void *eps[3] = {};       // [K] element viscosity of each state buffer
     int32_t *list[3] = {};   // [K] elements of each state buffer with eps > 0

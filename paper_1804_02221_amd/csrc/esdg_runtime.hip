@@ -213,6 +213,21 @@ struct esdg_ctx {
     bool eps_valid[3] = {false, false, false};   // viscosity/list of state buffer b are current
     int dtb_buf = -1;   // state buffer whose per-element dt bounds are in dtc/dtv (-1: none)
     int stage_variant = 0;   // compiled stage-kernel variant (esdg_autotune)
+    // Executable graphs of one time step (esdg_step), one per start buffer:
+    // the kernel sequence of a step is fixed once the viscosity of the start
+    // state and (adaptive step) its dt bounds are current.  A graph is valid
+    // for its start buffer, fixed step (0: adaptive), variant and generation;
+    // the generation changes with anything captured by value (parameters,
+    // tables, variant) or by address (buffers).
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        double dt = 0.0;
+        int variant = -1;
+        uint64_t gen = 0;
+    } graphs[3];
+    uint64_t graph_gen = 1;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;   // private stream the graphs are captured on
     hipEvent_t tune_ev[2] = {nullptr, nullptr};   // the autotuner's own timing events
     int64_t last_limited = 0;   // limited element-stages of the last esdg_step call
     // instances (ensembles): element ranges [inst_off[k], inst_off[k+1]) in
@@ -348,9 +363,15 @@ hipError_t dispatch(const esdg_ctx *c, F &&f)
 
 void free_bufs(esdg_ctx *c)
 {
+    // the step graphs hold the buffers' addresses
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = esdg_ctx::StepGraph{};
+    }
+    ++c->graph_gen;
     Bufs &B = c->B;
     void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
-                  B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
+                  B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.frec, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
                   B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2], B.inst, B.cstart, B.cinst};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -608,6 +629,94 @@ int launch_one_step(esdg_ctx *ctx, double dt, bool with_dt = true)
     return ESDG_OK;
 }
 
+void destroy_graphs(esdg_ctx *ctx)
+{
+    for (auto &g : ctx->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = esdg_ctx::StepGraph{};
+    }
+    ++ctx->graph_gen;
+}
+
+// The host-side bookkeeping of launch_one_step(ctx, dt) without launching.
+void advance_step_bookkeeping(esdg_ctx *ctx)
+{
+    const bool av = ctx->P.av_on != 0;
+    const int nst = ctx->P.integrator == 1 ? 3 : 5;
+    const int base = ctx->cur, o1 = (base + 1) % 3, o2 = (base + 2) % 3;
+    for (int k = 0; k < nst; ++k) ctx->eps_valid[(k % 2 == 0) ? o1 : o2] = av;
+    ctx->cur = o1;
+    ctx->dtb_buf = o1;
+}
+
+// A step can replay a captured graph when nothing of its launch sequence
+// depends on host-side state other than the graph's key: no kernel timing,
+// and the start state's viscosity (AV) and dt bounds (adaptive step)
+// already on the device.
+bool graph_ready(const esdg_ctx *ctx, double dt)
+{
+    if (!ctx->use_graphs || ctx->prof) return false;
+    if (ctx->P.av_on && !ctx->eps_valid[ctx->cur]) return false;
+    if (!(dt > 0.0) && ctx->dtb_buf != ctx->cur) return false;
+    return true;
+}
+
+// One time step by graph replay: capture it first if the cached graph of
+// this start buffer does not match (capture records the launches on a
+// private stream without running them), then launch it on the context
+// stream.  If capture is unavailable the step runs eagerly and graphs stay
+// off for the context.
+int graph_step(esdg_ctx *ctx, double dt)
+{
+    const double key_dt = dt > 0.0 ? dt : 0.0;
+    auto &g = ctx->graphs[ctx->cur];
+    if (!(g.exec && g.dt == key_dt && g.variant == ctx->stage_variant && g.gen == ctx->graph_gen)) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = esdg_ctx::StepGraph{};
+        if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            ctx->cap_stream = nullptr;
+            ctx->use_graphs = false;
+            return launch_one_step(ctx, dt);
+        }
+        // capture the launches of one step; the bookkeeping they change is
+        // restored afterwards and applied again after the replay
+        const int cur = ctx->cur, dtb = ctx->dtb_buf;
+        bool ev[3];
+        std::copy(ctx->eps_valid, ctx->eps_valid + 3, ev);
+        hipStream_t run = ctx->stream;
+        ctx->stream = ctx->cap_stream;
+        hipGraph_t graph = nullptr;
+        int st = ESDG_OK;
+        if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            st = ESDG_EHIP;
+        } else {
+            st = launch_one_step(ctx, dt);
+            const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+            if (e != hipSuccess) st = ESDG_EHIP;
+        }
+        ctx->stream = run;
+        ctx->cur = cur;
+        ctx->dtb_buf = dtb;
+        std::copy(ev, ev + 3, ctx->eps_valid);
+        hipGraphExec_t exec = nullptr;
+        if (st == ESDG_OK && graph && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            exec = nullptr;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();   // a failed capture leaves its error behind
+        if (!exec) {
+            ctx->use_graphs = false;
+            return launch_one_step(ctx, dt);
+        }
+        g.exec = exec;
+        g.dt = key_dt;
+        g.variant = ctx->stage_variant;
+        g.gen = ctx->graph_gen;
+    }
+    CK(hipGraphLaunch(g.exec, ctx->stream));
+    advance_step_bookkeeping(ctx);
+    return ESDG_OK;
+}
+
 int run_rhs(esdg_ctx *ctx, int buf)
 {
     if (ctx->P.av_on) TRY(launch_viscous(ctx, buf, -1));
@@ -668,6 +777,7 @@ int esdg_destroy(esdg_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_bufs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->tune_ev)
         if (e) (void)hipEventDestroy(e);
@@ -691,6 +801,7 @@ int esdg_set_params(esdg_ctx *ctx, const esdg_params *p)
         return fail(ctx, ESDG_EINVAL, "invalid parameter value");
     ctx->P = *p;
     invalidate_eps(ctx);
+    destroy_graphs(ctx);
     return ESDG_OK;
 }
 
@@ -834,6 +945,7 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     TRY(alloc(ctx, &B.dtc, K * r));
     TRY(alloc(ctx, &B.dtv, K * r));
     TRY(alloc(ctx, &B.fgeo, K * 4 * nf * 3 * r));
+    TRY(alloc(ctx, &B.frec, K * 4 * nf * 3 * r));
     TRY(alloc(ctx, &B.tabg, ctx->prec == 64 ? sizeof(Tab<double>) : sizeof(Tab<float>)));
     if (ctx->prec == 64)
         CK(hipMemcpyAsync(B.tabg, &ctx->td, sizeof(Tab<double>), hipMemcpyHostToDevice, ctx->stream));
@@ -1033,7 +1145,8 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
     int status = ESDG_OK;
     for (int it = 0; it < nsteps; ++it) {
         if (retries <= 0) {
-            TRY(launch_one_step(ctx, dt));
+            if (graph_ready(ctx, dt)) TRY(graph_step(ctx, dt));
+            else TRY(launch_one_step(ctx, dt));
             continue;
         }
         const int base = ctx->cur;
@@ -1250,6 +1363,18 @@ int esdg_set_stage_variant(esdg_ctx *ctx, int variant)
     if (!ctx || variant < 0 || variant >= kStageVariants)
         return ctx ? fail(ctx, ESDG_EINVAL, "variant outside [0, %d)", kStageVariants) : ESDG_EINVAL;
     ctx->stage_variant = variant;
+    return ESDG_OK;
+}
+
+int esdg_set_graphs(esdg_ctx *ctx, int enable)
+{
+    if (!ctx) return ESDG_EINVAL;
+    ctx->use_graphs = enable != 0;
+    if (!ctx->use_graphs) {
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        destroy_graphs(ctx);
+    }
     return ESDG_OK;
 }
 
@@ -1553,7 +1678,7 @@ int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
     // ordered on its own stream
     for (int it = 0; it < nsteps; ++it)
         for (auto &G : en->groups) {
-            const int st = launch_one_step(G.ctx, 0.0);
+            const int st = graph_ready(G.ctx, 0.0) ? graph_step(G.ctx, 0.0) : launch_one_step(G.ctx, 0.0);
             if (st) return efail_ctx(en, G.ctx, st);
         }
     int status = ESDG_OK;

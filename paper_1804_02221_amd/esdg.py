@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
             "esdg_ensemble_autotune": ([P, I, P], I),
             "esdg_autotune": ([P, I, P, P], I),
             "esdg_set_stage_variant": ([P, I], I),
+            "esdg_set_graphs": ([P, I], I),
             "esdg_rhs_vjp": ([P, P, P, P, P, P, P, P, I], I),
             "esdg_set_gauges": ([P, I, P, P, P], I),
             "esdg_gauge_values": ([P, P, I], I),
@@ -350,6 +351,10 @@ class Solver:
 
     def set_stage_variant(self, variant: int):
         self._check(lib().esdg_set_stage_variant(self._ctx, int(variant)))
+
+    def set_graphs(self, enable: bool = True):
+        """esdg_set_graphs: replay each step as one captured HIP graph."""
+        self._check(lib().esdg_set_graphs(self._ctx, int(bool(enable))))
 
     def profile(self, enable: bool = True):
         self._check(lib().esdg_profile(self._ctx, int(bool(enable))))

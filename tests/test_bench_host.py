@@ -17,15 +17,25 @@ def test_stage_bytes_counts_each_datum_once():
         reads = 3 + (3 if k > 0 else 0) + 4 + 2          # W, dU (not on the first stage), metric, b_x b_y
         writes = 3 + (3 if k < 4 else 0)                 # W, dU (not on the last stage)
         per_elem = 4 * (N + 1) + 1                       # face bathymetry, viscosity
-        want = ((reads + writes) * npn * K + per_elem * K) * rb
+        records = 12 * (N + 1) if k == 4 else 0          # last stage: face records (h, u, v)
+        want = ((reads + writes) * npn * K + (per_elem + records) * K) * rb
         assert bench.stage_bytes(N, K, True, rb, k) == want
         assert bench.stage_bytes(N, K, False, rb, k) == want - K * rb
+        assert bench.stage_bytes(N, K, True, rb, k, limiter=False) == want - records * K * rb
     # viscous elements add their face fluxes and viscous terms
     extra = bench.stage_bytes(N, K, True, rb, 2, n_visc=2) - bench.stage_bytes(N, K, True, rb, 2)
     assert extra == (16 * (N + 1) + 2 * npn) * 2 * rb
-    # about 139 bytes per node on average over the five stages at N = 7 in FP64
+    # about 140 bytes per node on average over the five stages at N = 7 in FP64
     avg = sum(bench.stage_bytes(N, 262144, True, 8, k) for k in range(5)) / 5 / (262144 * npn)
-    assert abs(avg - 138.53) < 0.01
+    assert abs(avg - (138.53 + 96 * 8 / 64 / 5)) < 0.01
+
+
+def test_dt_pass_bytes():
+    N, K, rb = 7, 5, 8
+    nf = N + 1
+    # per element: CFL and viscous bound; per face node: record (3) and face geometry (3); face map 5 B per side
+    assert bench.dt_pass_bytes(N, K, True, rb) == K * ((2 + 4 * nf * 6) * rb + 4 * 5)
+    assert bench.dt_pass_bytes(N, K, False, rb) == K * ((1 + 4 * nf * 6) * rb + 4 * 5)
 
 
 def test_more_than_one_gpu_is_refused():
