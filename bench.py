@@ -201,6 +201,14 @@ def ensemble_bench(esdg, dev, members, steps: int):
     st_ens = ens.step(steps, raise_negmean=False)
     torch.cuda.synchronize()
     t_ens = time.perf_counter() - t0
+    # the same number of further steps with every kernel launched on its own:
+    # the difference is the launch overhead the graphs remove
+    ens.set_graphs(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(steps, raise_negmean=False)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
     ens.close()
     t_seq = 0.0
     negmean_seq = 0
@@ -218,6 +226,7 @@ def ensemble_bench(esdg, dev, members, steps: int):
     return dict(instances=len(members), nodes=nodes, steps=steps, stages_per_step=stages,
                 integrator="SSPRK(3,3)" if stages == 3 else "LSRK(5,4)",
                 value=nodes * stages * steps / t_ens, ms_per_step=t_ens * 1e3 / steps,
+                eager_ms_per_step=t_eager * 1e3 / steps,
                 sequential_value=nodes * stages * steps / t_seq, sequential_ms_per_step=t_seq * 1e3 / steps,
                 speedup=t_seq / t_ens, stage_variant={str(k): v for k, v in tuned.items()},
                 negative_mean_reported={"ensemble": int(st_ens != 0), "sequential_instances": negmean_seq})

@@ -321,6 +321,9 @@ int esdg_ensemble_add(esdg_ensemble *en, const esdg_params *p, int N, int64_t K,
                       const double *hv, int *id);
 int esdg_ensemble_build(esdg_ensemble *en);
 int esdg_ensemble_step(esdg_ensemble *en, int nsteps);
+/* Graph replay of every degree group's steps (esdg_set_graphs; on by
+ * default).  Builds the ensemble if needed. */
+int esdg_ensemble_set_graphs(esdg_ensemble *en, int enable);
 int esdg_ensemble_size(const esdg_ensemble *en, int *n);
 int esdg_ensemble_get_state(esdg_ensemble *en, int id, double *h, double *hu, double *hv, int mem);
 int esdg_ensemble_get_time(esdg_ensemble *en, int id, double *t);

@@ -29,11 +29,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "esdg_oracle.c")
 _LIB = os.path.join(_HERE, "libesdg_oracle.so")
 _LIB_TWIN = os.path.join(_HERE, "libesdg_oracle_fma.so")
+_LIB_ASAN = os.path.join(_HERE, "libesdg_oracle_asan.so")
 
 OK, EINVAL, ENOMEM, ENEGMEAN = 0, -1, -2, -5
 
 
-_FLAGS = {_LIB: ["-ffp-contract=off"], _LIB_TWIN: ["-ffp-contract=fast", "-mfma", "-mavx2"]}
+_FLAGS = {_LIB: ["-ffp-contract=off"], _LIB_TWIN: ["-ffp-contract=fast", "-mfma", "-mavx2"],
+          # AddressSanitizer + UndefinedBehaviorSanitizer build (tests load it in a
+          # process that preloads the ASan runtime; see use_sanitized)
+          _LIB_ASAN: ["-ffp-contract=off", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                      "-fno-omit-frame-pointer", "-g"]}
 
 
 def _build_one(path: str, force: bool) -> None:
@@ -50,6 +55,20 @@ def build(force: bool = True) -> str:
     _build_one(_LIB, force)
     _build_one(_LIB_TWIN, force)
     return _LIB
+
+
+def build_sanitized(force: bool = True) -> str:
+    """Compile the AddressSanitizer/UBSan build of the oracle in place."""
+    _build_one(_LIB_ASAN, force)
+    return _LIB_ASAN
+
+
+def use_sanitized() -> None:
+    """Switch every function of this module to the sanitizer build, for the
+    rest of the process.  The process must have the ASan runtime loaded
+    first (LD_PRELOAD of gcc's libasan.so)."""
+    global _active
+    _active = _LIB_ASAN
 
 
 def host_has_fma() -> bool:

@@ -1694,6 +1694,17 @@ int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
     return ESDG_OK;
 }
 
+int esdg_ensemble_set_graphs(esdg_ensemble *en, int enable)
+{
+    if (!en) return ESDG_EINVAL;
+    TRY(ensemble_build(en));
+    for (auto &G : en->groups) {
+        const int st = esdg_set_graphs(G.ctx, enable);
+        if (st) return efail_ctx(en, G.ctx, st);
+    }
+    return ESDG_OK;
+}
+
 int esdg_ensemble_size(const esdg_ensemble *en, int *n)
 {
     if (!en || !n) return ESDG_EINVAL;

@@ -41,6 +41,16 @@ class Params(C.Structure):
 _lib = None
 
 
+def use_sanitized_build() -> None:
+    """Load libesdg_hostsan.so instead: the same kernels, with the host code
+    built under AddressSanitizer (``build.py --sanitize``).  Call before the
+    first use, in a process that preloads gcc's ASan runtime."""
+    global LIB_PATH
+    if _lib is not None:
+        raise RuntimeError("the library is already loaded")
+    LIB_PATH = os.path.join(os.path.dirname(LIB_PATH), "libesdg_hostsan.so")
+
+
 def lib() -> C.CDLL:
     """Load libesdg.so (built by ``paper_1804_02221_amd.build``)."""
     global _lib
@@ -89,6 +99,7 @@ def lib() -> C.CDLL:
             "esdg_ensemble_add": ([P, P, I, I64, P, P, P, P, P, P, P, P, P, P], I),
             "esdg_ensemble_build": ([P], I),
             "esdg_ensemble_step": ([P, I], I),
+            "esdg_ensemble_set_graphs": ([P, I], I),
             "esdg_ensemble_size": ([P, P], I),
             "esdg_ensemble_get_state": ([P, I, P, P, P, I], I),
             "esdg_ensemble_get_time": ([P, I, P], I),
@@ -496,6 +507,10 @@ class Ensemble:
             return st
         self._check(st)
         return st
+
+    def set_graphs(self, enable: bool = True):
+        """esdg_ensemble_set_graphs: graph replay per degree group."""
+        self._check(lib().esdg_ensemble_set_graphs(self._h, int(bool(enable))))
 
     def __len__(self):
         n = C.c_int(0)

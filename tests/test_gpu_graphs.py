@@ -89,3 +89,28 @@ def test_graph_steps_plain_method(esdg):
         same(g, e, f"{n} steps")
     g.close()
     e.close()
+
+
+def test_ensemble_graph_steps_equal_eager_steps(esdg):
+    """An ensemble (three degrees, uneven grids) stepping with graph replay
+    per degree group against the same ensemble launching every kernel."""
+    from paper_1804_02221_amd.inputs import ensemble_member
+    specs = [(8, 3, True, 41), (12, 5, False, 42), (6, 7, True, 43), (10, 3, False, 44)]
+    members = [ensemble_member(*sp) for sp in specs]
+    ens = []
+    for graphs in (True, False):
+        e = esdg.Ensemble(0, 64)
+        for w in members:
+            e.add_workload(w)
+        e.set_graphs(graphs)
+        ens.append(e)
+    for n in (1, 4, 2, 6):
+        for e in ens:
+            e.step(n, raise_negmean=False)
+        for i in range(len(members)):
+            a, b = ens[0].get_state(i), ens[1].get_state(i)
+            for c in range(3):
+                assert np.array_equal(a[c], b[c]), (n, i, c)
+            assert ens[0].get_time(i) == ens[1].get_time(i)
+    for e in ens:
+        e.close()
