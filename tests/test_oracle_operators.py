@@ -128,3 +128,35 @@ def test_lsrk_coefficients_fourth_order(orc):
     errs = [abs(run(n) - 0.5) for n in (8, 16, 32)]
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) > 3.8, rates
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_indicator_second_shell(orc, N):
+    """The second energy ratio of appendix A: the energy in the mode shell
+    N-1 over the energy of the modes up to N-1 (the top shell N left out of
+    the denominator).  Q = 1 + beta mode(N-1, 0) has no top-shell energy
+    (r1 = 0) and r2 = beta^2 / (4 + beta^2); with a top-shell part alpha
+    mode(N, 0) as well, r1 = alpha^2 / (4 + alpha^2 + beta^2) while r2 keeps
+    its value (a denominator over all modes would give beta^2 / (4 + alpha^2
+    + beta^2)); the transposed mode(0, N-1) is in the same shell."""
+    op = orc.operators(N)
+    xi = op["xi"]
+    smin, smax = -4.0, 0.0
+    P = orc.params(N, eps0=1.0, sigma_min=smin, sigma_max=smax, av_on=1)
+
+    def ramp(r):
+        s = np.log10(r)
+        return 0.5 * (1 + np.sin(np.pi * (s - 0.5 * (smax + smin)) / (smax - smin)))
+
+    for beta in [0.05, 0.3]:
+        r2 = beta ** 2 / (4.0 + beta ** 2)
+        for Q in (1.0 + beta * _mode(N, xi, N - 1, 0), 1.0 + beta * _mode(N, xi, 0, N - 1)):
+            got = orc.indicator(P, N, Q[None, :])[0]
+            assert got == pytest.approx(ramp(r2), rel=1e-10)
+        alpha = 0.5 * beta
+        Q = 1.0 + alpha * _mode(N, xi, N, 0) + beta * _mode(N, xi, N - 1, 1)
+        r1 = alpha ** 2 / (4.0 + alpha ** 2 + beta ** 2)
+        assert r2 > r1
+        got = orc.indicator(P, N, Q[None, :])[0]
+        assert got == pytest.approx(ramp(r2), rel=1e-10)
+        assert abs(got - ramp(beta ** 2 / (4.0 + alpha ** 2 + beta ** 2))) > 1e-6
