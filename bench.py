@@ -725,6 +725,7 @@ def main():
                          f"limiter, ES flux, LSRK(5,4), adaptive dt"),
             "N": args.N, "elements": main_res["K"], "nodes": main_res["nodes"],
             "stage_variant": main_res["stage_variant"],
+            "autotune_ms": main_res["autotune_ms"],
             "stages_per_step": 5, "parallelism": "single GPU",
         },
         "roofline": {

@@ -261,7 +261,9 @@ int esdg_profile_read_kernels(esdg_ctx *ctx, double ms[6], int64_t launches[6]);
  * elements fill it -- N = 2, 3, 7 -- else 256 threads) with its register
  * budget and partner-loop unroll; 1 the alternative workgroup size (256
  * resp. 128 threads); 2 the default tile with one wave per SIMD less in its
- * register budget; 3 the default tile with the other partner-loop unroll.
+ * register budget; 3 the default tile with the other partner-loop unroll;
+ * 4 the default tile with the staged fields' LDS rows padded by one node
+ * (the paper's LDS padding: fewer bank conflicts, more LDS per tile).
  * esdg_autotune times reps launches of each on the context's mesh and
  * current state, twice (trial stages write only a scratch state buffer: the
  * state, the LSRK register and the time are unchanged; they are not counted
@@ -271,7 +273,7 @@ int esdg_profile_read_kernels(esdg_ctx *ctx, double ms[6], int64_t launches[6]);
  * directly.  Results do not depend on the choice (the same arithmetic per
  * element in the same order).
  */
-#define ESDG_STAGE_VARIANTS 4
+#define ESDG_STAGE_VARIANTS 5
 int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[ESDG_STAGE_VARIANTS]);
 int esdg_set_stage_variant(esdg_ctx *ctx, int variant);
 

@@ -174,6 +174,7 @@ static void launch_stage(StageArgs<R> a, int64_t K, hipStream_t s, Ev ev)
     case 1: launch_stage_variant<N, R, MODE, 1>(a, K, s, ev); break;
     case 2: launch_stage_variant<N, R, MODE, 2>(a, K, s, ev); break;
     case 3: launch_stage_variant<N, R, MODE, 3>(a, K, s, ev); break;
+    case 4: launch_stage_variant<N, R, MODE, 4>(a, K, s, ev); break;
     default: launch_stage_variant<N, R, MODE, 0>(a, K, s, ev); break;
     }
 }

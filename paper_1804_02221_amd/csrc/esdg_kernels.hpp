@@ -65,13 +65,16 @@ struct TileShape {
 //   2  the default tile with one wave per SIMD less in its register budget
 //      (more registers, no spills where the default spills);
 //   3  the default tile with the other partner-loop unroll (full where the
-//      default unrolls partly, by two where it unrolls fully).
+//      default unrolls partly, by two where it unrolls fully);
+//   4  the default tile with the staged fields' LDS rows padded by one node
+//      (the paper's LDS padding, appendix C: the eta-direction partner reads
+//      of a wave no longer share banks), at the cost of more LDS per tile.
 // Default register budget in the FP64 update modes: six waves per SIMD at
 // N = 6, five otherwise (N = 7 reaches six by its partner-loop unroll); no
 // constraint in FP32 and in the right-hand-side mode.  Default unroll: fully,
 // except at N = 7 with one-wave tiles (by two: 79 VGPRs and six waves per
 // SIMD instead of five), N = 6 (by two) and N = 8 (by three: five waves).
-constexpr int kStageVariants = 4;
+constexpr int kStageVariants = 5;
 
 template <int N, int V>
 struct StageCfg {
@@ -81,6 +84,9 @@ struct StageCfg {
     static constexpr int waves = V == 2 ? base_waves - 1 : base_waves;
     static constexpr int vu_default = (N == 7 && T == 64) ? 2 : (N == 8 ? 3 : (N == 6 ? 2 : N + 1));
     static constexpr int VU = V == 3 ? (vu_default == N + 1 ? 2 : N + 1) : vu_default;
+    // LDS row padding of the staged fields (one spare node per row of N + 1):
+    // the eta-direction partner reads of a wave then fall on different banks
+    static constexpr int PAD = V == 4 ? 1 : 0;
 };
 
 template <int N, typename R, int MODE, int V>
@@ -961,12 +967,16 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     using V2 = typename Vec2<R>::type;
     // one contiguous staging region: reused as reduction scratch at the end.
     // Pairs read together are stored together (one 16-byte LDS read in FP64).
-    __shared__ __align__(16) R s_st[9 * T];
-    V2 *const s_q = (V2 *)s_st;               // (hu, hv)
-    V2 *const s_w = (V2 *)(s_st + 2 * T);     // (u, v)
-    V2 *const s_a = (V2 *)(s_st + 4 * T);     // J grad(xi)  = (Ax, Cx)
-    V2 *const s_b = (V2 *)(s_st + 6 * T);     // J grad(eta) = (Ae, Ce)
-    R *const s_h = s_st + 8 * T;
+    // Node (i, j) of tile element el sits at el*PS + i*RS + j (RS = N + 1 +
+    // PAD); lanes past the tile's nodes write to spare slots after them.
+    constexpr int RS = nf + StageCfg<N, V>::PAD, PS = nf * RS, LEN = E * PS + (T - E * np);
+    static_assert(LEN >= T, "staging rows");
+    __shared__ __align__(16) R s_st[9 * LEN];
+    V2 *const s_q = (V2 *)s_st;                 // (hu, hv)
+    V2 *const s_w = (V2 *)(s_st + 2 * LEN);     // (u, v)
+    V2 *const s_a = (V2 *)(s_st + 4 * LEN);     // J grad(xi)  = (Ax, Cx)
+    V2 *const s_b = (V2 *)(s_st + 6 * LEN);     // J grad(eta) = (Ae, Ce)
+    R *const s_h = s_st + 8 * LEN;
     __shared__ R s_fl[3][NF];
     __shared__ R s_lim[4 * E];
     __shared__ R s_vinv[nf * nf];       // V^{-1} for the indicator epilogue (with AV)
@@ -1006,11 +1016,12 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     const R eps_e = (av && act) ? a.eps[e] : R(0);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
-    s_h[t] = h;
-    s_q[t] = V2{hu, hv};
-    s_w[t] = V2{u, v};
-    s_a[t] = V2{Ax, Cx};
-    s_b[t] = V2{Ae, Ce};
+    const int st = lane ? el * PS + i * RS + j : E * PS + (t - E * np);
+    s_h[st] = h;
+    s_q[st] = V2{hu, hv};
+    s_w[st] = V2{u, v};
+    s_a[st] = V2{Ax, Cx};
+    s_b[st] = V2{Ae, Ce};
     if constexpr (MODE != kModeRhs)
         if (av) stage_vinv<N, R, T>(s_vinv, *a.tg, t);
     // the per-lane table entries of the volume term from LDS rather than
@@ -1028,7 +1039,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         if (fe < a.m.K) {
             int fi, fj;
             side_node<N>(s, k, fi, fj);
-            const int lp = fel * np + fi * nf + fj;
+            const int lp = fel * PS + fi * RS + fj;
             const int64_t en = pfr.en;
             const int ns = pfr.ns(), kk = pfr.kk();
             int ni, nj;
@@ -1044,8 +1055,10 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             const int64_t ql = qn - e0 * np;
             R hn, un, vn, bo, bn;
             if (ql >= 0 && ql < E * np) {
-                hn = s_h[ql];
-                const V2 w = s_w[ql];
+                const int qe = (int)ql / np, qp = (int)ql - qe * np;
+                const int qs = qe * PS + (qp / nf) * RS + (qp - (qp / nf) * nf);
+                hn = s_h[qs];
+                const V2 w = s_w[qs];
                 un = w.x;
                 vn = w.y;
             } else {
@@ -1094,13 +1107,13 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     //   sum D F2' = u sum D F1' + sum D F1' u_m + 2g h sum D h_m sA   (F3' alike)
     R A1 = 0, A2 = 0, A3 = 0, C2 = 0, C3 = 0;
     {
-        const int base = el * np;
+        const int base = el * PS;
         // partner-loop unroll of the variant (StageCfg)
         constexpr int VU = StageCfg<N, V>::VU;
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
             // the self pair has coefficient 0 (no branch: D~ has a zero diagonal)
-            const int qq = base + mm * nf + j;
+            const int qq = base + mm * RS + j;
             const R d = s_dz[i * nf + mm];
             const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ax + am.x, sC = Cx + am.y;
@@ -1114,7 +1127,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         }
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
-            const int qq = base + i * nf + mm;
+            const int qq = base + i * RS + mm;
             const R d = s_dz[j * nf + mm];
             const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ae + bm.x, sC = Ce + bm.y;

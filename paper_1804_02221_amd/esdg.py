@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesdg.so")
 
 OK, EINVAL, ENOMEM, EHIP, EMESH, ENEGMEAN, EDTPOS, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
-STAGE_VARIANTS = 4   # ESDG_STAGE_VARIANTS of include/esdg.h
+STAGE_VARIANTS = 5   # ESDG_STAGE_VARIANTS of include/esdg.h
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EMESH: "EMESH", ENEGMEAN: "ENEGMEAN",
           EDTPOS: "EDTPOS", ENONFINITE: "ENONFINITE"}
 
