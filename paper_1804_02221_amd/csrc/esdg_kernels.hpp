@@ -219,6 +219,14 @@ __device__ __forceinline__ R rcp_wet(R h, R h_tol)
     return h > h_tol ? rcp_nr(h) : R(0);
 }
 
+// The single-precision stage kernel forms the volume and interface terms from
+// jumps to the own node (interface_flux_delta and the volume loop): the
+// two-point sums of flux-sized terms whose result is a derivative lose the
+// flux-to-derivative ratio (about N^2 / element size) in relative accuracy,
+// which double precision absorbs and single precision does not.
+template <typename R>
+constexpr bool kJumpForm = sizeof(R) == 4;
+
 // Rotated numerical interface flux along the unit normal (nx, ny), '-' =
 // own trace, '+' = neighbour (appendix B): EC part plus, for the entropy
 // stable flux, -1/2 R |Lambda| R^T [[q~]] expanded in closed form.
@@ -241,6 +249,50 @@ __device__ __forceinline__ void interface_flux(R hm, R um, R vm, R bm, R hp, R u
         const R dq1 = g * ((hp + bp) - (hm + bm)) -
                       R(0.5) * ((utp * utp + vtp * vtp) - (utm * utm + vtm * vtm));
         const R dq2 = utp - utm, dq3 = vtp - vtm;
+        const R lp = fabs(au + ac) * P.i2g, l2 = fabs(ah * au), lm = fabs(au - ac) * P.i2g;
+        const R r1 = lp * (dq1 + (au + ac) * dq2 + av * dq3);
+        const R r2 = l2 * dq3;
+        const R r3 = lm * (dq1 + (au - ac) * dq2 + av * dq3);
+        f0 -= R(0.5) * (r1 + r3);
+        f1 -= R(0.5) * ((au + ac) * r1 + (au - ac) * r3);
+        f2 -= R(0.5) * (av * (r1 + r3) + r2);
+    }
+    F0 = f0;
+    F1 = nx * f1 - ny * f2;
+    F2 = ny * f1 + nx * f2;
+}
+
+// The same interface flux less the own trace's physical flux along n,
+// f*(-, +) - f(-).n, written in the jumps dh = h+ - h-, du, dv only (the
+// single-precision stage kernel).  With a mean m = a- + d/2:
+//   {h}{u_n} - h- u_n-           = (h- du_n + dh {u_n}) / 2
+//   {h}{u_n}^2 - h- u_n-^2       = {u_n} df0 + du_n h- u_n- / 2
+//   g/2 ({h^2} - h-^2)           = g dh {h} / 2
+//   {h}{u_n}{v_t} - h- u_n- v_t- = {v_t} df0 + dv_t h- u_n- / 2
+// and, in the dissipation, [[g(h+b) - |u|^2/2]] with |u+|^2 - |u-|^2 =
+// du (u+ + u-) + dv (v+ + v-).  The own flux is the row-sum part of the
+// volume term's two-point sums at a face node, where it cancels against this
+// subtracted part; formed from the jumps, neither part is rounded at the
+// size of the flux itself, only at the size of its variation.
+template <typename R>
+__device__ __forceinline__ void interface_flux_delta(R hm, R um, R vm, R bm, R hp, R up, R vp, R bp, R nx,
+                                                     R ny, const Phys<R> &P, R &F0, R &F1, R &F2)
+{
+    const R g = P.g;
+    const R dh = hp - hm, du = up - um, dv = vp - vm;
+    const R utm = nx * um + ny * vm, vtm = nx * vm - ny * um;
+    const R dut = nx * du + ny * dv, dvt = nx * dv - ny * du;
+    const R ah = R(0.5) * (hm + hp), au = utm + R(0.5) * dut, av = vtm + R(0.5) * dvt;
+    const R fo = hm * utm;
+    R f0 = R(0.5) * (hm * dut + dh * au);
+    R f1 = au * f0 + R(0.5) * (dut * fo + g * dh * ah);
+    R f2 = av * f0 + R(0.5) * dvt * fo;
+    if (!P.ec) {
+        const R cm = sqrt(g * fmax(hm, R(0)));
+        const R cp = sqrt(g * fmax(hp, R(0)));
+        const R ac = R(0.5) * (cm + cp);
+        const R dq1 = g * (dh + (bp - bm)) - R(0.5) * (du * (up + um) + dv * (vp + vm));
+        const R dq2 = dut, dq3 = dvt;
         const R lp = fabs(au + ac) * P.i2g, l2 = fabs(ah * au), lm = fabs(au - ac) * P.i2g;
         const R r1 = lp * (dq1 + (au + ac) * dq2 + av * dq3);
         const R r2 = l2 * dq3;
@@ -1072,8 +1124,12 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             if (is_wall(a.m, fe, s)) wall_mirror(snx * ijs, sny * ijs, un, vn);
             R F0, F1, F2;
             const V2 wl = s_w[lp];
-            interface_flux<R>(s_h[lp], wl.x, wl.y, bo, hn, un, vn, bn, snx * ijs, sny * ijs, P, F0,
-                              F1, F2);
+            if constexpr (kJumpForm<R>)
+                interface_flux_delta<R>(s_h[lp], wl.x, wl.y, bo, hn, un, vn, bn, snx * ijs, sny * ijs, P,
+                                        F0, F1, F2);
+            else
+                interface_flux<R>(s_h[lp], wl.x, wl.y, bo, hn, un, vn, bn, snx * ijs, sny * ijs, P, F0,
+                                  F1, F2);
             const R sc = js * a.tab.iw0;
             c0 = sc * F0; c1 = sc * F1; c2 = sc * F2;
             // interface bathymetry penalty of eq. SourceDisc for a bottom
@@ -1106,7 +1162,58 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     // directions at once:
     //   sum D F2' = u sum D F1' + sum D F1' u_m + 2g h sum D h_m sA   (F3' alike)
     R A1 = 0, A2 = 0, A3 = 0, C2 = 0, C3 = 0;
-    {
+    if constexpr (kJumpForm<R>) {
+        // single precision: the same sums taken over the partners' jumps
+        // from the own node (dX = X_m - X, t = 2 x own metric pair).  With
+        // F1'(own) = 4 (hu A + hv C) and F2'(own) the own momentum part,
+        //   F1'_m - F1'(own) = s_hu dA + s_hv dC + tA dhu + tC dhv
+        //   F2'_m - F2'(own) = 2u (F1'_m - F1'(own)) + du F1'_m + 2g h (h_m dA + tA dh)
+        // (F3' alike), so sum_m D (F' - F'(own)) holds no term of the size of
+        // the flux itself; the row-sum parts D~ 1 F'(own) left out are the
+        // own-flux parts the face slots subtract (interface_flux_delta).
+        const int base = el * PS;
+        constexpr int VU = StageCfg<N, V>::VU;
+        {
+            const R tA = R(2) * Ax, tC = R(2) * Cx;
+#pragma unroll VU
+            for (int mm = 0; mm < nf; ++mm) {
+                const int qq = base + mm * RS + j;
+                const R d = s_dz[i * nf + mm];
+                const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
+                const R hm = s_h[qq];
+                const R dA = am.x - Ax, dC = am.y - Cx, dh = hm - h;
+                const R s1 = hu + qm.x, s2 = hv + qm.y;
+                const R F1 = s1 * (Ax + am.x) + s2 * (Cx + am.y);
+                const R dF1 = s1 * dA + s2 * dC + tA * (qm.x - hu) + tC * (qm.y - hv);
+                const R dF = d * F1;
+                A1 += d * dF1;
+                A2 += dF * (wm.x - u);
+                A3 += dF * (wm.y - v);
+                C2 += d * (hm * dA + tA * dh);
+                C3 += d * (hm * dC + tC * dh);
+            }
+        }
+        {
+            const R tA = R(2) * Ae, tC = R(2) * Ce;
+#pragma unroll VU
+            for (int mm = 0; mm < nf; ++mm) {
+                const int qq = base + i * RS + mm;
+                const R d = s_dz[j * nf + mm];
+                const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
+                const R hm = s_h[qq];
+                const R dA = bm.x - Ae, dC = bm.y - Ce, dh = hm - h;
+                const R s1 = hu + qm.x, s2 = hv + qm.y;
+                const R F1 = s1 * (Ae + bm.x) + s2 * (Ce + bm.y);
+                const R dF1 = s1 * dA + s2 * dC + tA * (qm.x - hu) + tC * (qm.y - hv);
+                const R dF = d * F1;
+                A1 += d * dF1;
+                A2 += dF * (wm.x - u);
+                A3 += dF * (wm.y - v);
+                C2 += d * (hm * dA + tA * dh);
+                C3 += d * (hm * dC + tC * dh);
+            }
+        }
+    } else {
         const int base = el * PS;
         // partner-loop unroll of the variant (StageCfg)
         constexpr int VU = StageCfg<N, V>::VU;
@@ -1141,7 +1248,9 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         }
     }
     const R h2g = R(2) * P.g * h;
-    R L1 = R(0.5) * A1, L2 = R(0.25) * (u * A1 + A2 + h2g * C2), L3 = R(0.25) * (v * A1 + A3 + h2g * C3);
+    // (the jump form's mass sum enters the momentum sums twice: 2u dF1)
+    const R uA = kJumpForm<R> ? R(2) * u : u, vA = kJumpForm<R> ? R(2) * v : v;
+    R L1 = R(0.5) * A1, L2 = R(0.25) * (uA * A1 + A2 + h2g * C2), L3 = R(0.25) * (vA * A1 + A3 + h2g * C3);
     lds_sync<T>();   // face slots complete; staging region free from here on
     {
         const int fb = el * 4 * nf;
