@@ -38,12 +38,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def geometry_fields(N: int, real_bytes: int) -> int:
+    """Geometry the stage kernel reads per node: the four metric directions,
+    or, in FP64 at N <= 4, the two coordinates (relative to the element's
+    first node) from which it forms them."""
+    return 2 if (real_bytes == 8 and N <= 4) else 4
+
+
 def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_visc: int = 0,
                 limiter: bool = True) -> float:
     """Algorithmic HBM bytes of one launch of the fused stage kernel: every
     datum the stage must read or write, counted once.
     Reads: W (3/node), dU (3/node, not on the first LSRK stage), metric
-    directions (4/node), split bathymetry derivatives (2/node), face
+    directions (4/node; 2 coordinates at N <= 4 in FP64, geometry_fields),
+    split bathymetry derivatives (2/node), face
     bathymetry (4(N+1)/element); with AV the element viscosity (1/element)
     and, for the n_visc elements with viscosity, their viscous face fluxes
     (16(N+1)/element, read by their neighbours) and viscous terms (2/node).
@@ -54,7 +62,8 @@ def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_v
     nf = N + 1
     np_ = nf * nf
     n = K * np_
-    per_node = 3 + (3 if stage_index > 0 else 0) + 4 + 2 + 3 + (3 if stage_index < 4 else 0)
+    per_node = (3 + (3 if stage_index > 0 else 0) + geometry_fields(N, real_bytes) + 2 + 3
+                + (3 if stage_index < 4 else 0))
     per_elem = 4 * nf + (1 if av else 0) + (12 * nf if (limiter and stage_index == 4) else 0)
     visc = (16 * nf + 2 * np_) * n_visc if av else 0
     return (per_node * n + per_elem * K + visc) * real_bytes
@@ -62,14 +71,15 @@ def stage_bytes(N: int, K: int, av: bool, real_bytes: int, stage_index: int, n_v
 
 def rhs_bytes(N: int, K: int, av: bool, real_bytes: int, n_visc: int = 0) -> float:
     """Algorithmic HBM bytes of one right-hand-side evaluation (the stage
-    kernel in its RHS form): reads W (3/node), metric directions (4/node),
-    split bathymetry derivatives (2/node), face bathymetry (4(N+1)/element),
+    kernel in its RHS form): reads W (3/node), metric directions (4/node, or
+    geometry_fields), split bathymetry derivatives (2/node), face bathymetry (4(N+1)/element),
     with AV the element viscosity and the viscous-element terms as in
     stage_bytes; writes R (3/node)."""
     nf = N + 1
     np_ = nf * nf
     visc = (16 * nf + 2 * np_) * n_visc if av else 0
-    return ((3 + 4 + 2 + 3) * K * np_ + (4 * nf + (1 if av else 0)) * K + visc) * real_bytes
+    return ((3 + geometry_fields(N, real_bytes) + 2 + 3) * K * np_ + (4 * nf + (1 if av else 0)) * K
+            + visc) * real_bytes
 
 
 def av_faces_bytes(N: int, n_visc: int, real_bytes: int) -> float:

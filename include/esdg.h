@@ -93,8 +93,12 @@ typedef struct {
     int limiter_on;    /* positivity limiter after every stage (eq. PosPres),
                           and the Lemma 2 bound enters the adaptive step     */
     int integrator;    /* 0: LSRK(5,4) 2N-storage, 1: SSPRK(3,3)              */
-    int max_dt_retries;/* on ESDG_ENEGMEAN redo the step with dt/2 this many
-                          times (each retry synchronises with the host)     */
+    int max_dt_retries;/* redo a step from W^n with dt/2, at most this many
+                          times, when it meets a negative element mean or,
+                          for an adaptive step, exceeds twice the smaller of
+                          the CFL and viscous bounds of the state it
+                          produced (each step then synchronises with the
+                          host)                                             */
 } esdg_params;
 
 /* Fill *p with the defaults for degree N (N selects sigma_min/sigma_max). */
@@ -174,6 +178,13 @@ int esdg_compute_dt(esdg_ctx *ctx, double out[4]);
  * first), else ESDG_EDTPOS, else ESDG_ENEGMEAN (after max_dt_retries
  * halvings of a step).  The kernels run to completion on non-finite
  * values; the state then holds them.
+ * With max_dt_retries > 0 a step is also checked after the fact (section 6:
+ * the CFL step is adjusted when a smaller one proves necessary): a negative
+ * element mean in the limiter, or an adaptive step larger than twice the
+ * smaller of the CFL and viscous bounds of the state it produced (its wave
+ * speeds or viscosity grew that much within the step), restarts the step
+ * from W^n with half its size.  Out of retries the step is kept; only a
+ * negative mean is then reported.
  */
 int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out);
 

@@ -1050,9 +1050,18 @@ static int one_step(const orc_params *P, const orc_ops *op, const orc_mesh *m,
 
 /* nsteps steps; dt_fixed > 0 gives a fixed step, otherwise the step is
  * min(CFL, viscous, positivity) bound evaluated at the start of each step.
- * A negative element mean in the limiter restarts the step from W^n with
- * half the step, at most max_dt_retries times (reading of "adjust it
- * accordingly", section 6).  t (in/out) accumulates the time. */
+ * The step is redone from W^n with half its size, at most max_dt_retries
+ * times, when it proves too large (reading of the section 6 remark that the
+ * step is adjusted when a smaller one is found to be needed):
+ *   - a negative element mean in the limiter (any step);
+ *   - an adaptive step larger than ORC_STEP_BOUND_FACTOR times the smaller
+ *     of the CFL and viscous bounds of the state it produced (the bounds
+ *     hold the factors cfl and cfl_visc), i.e. the wave speeds or the
+ *     viscosity grew so much within the step that its CFL number, measured
+ *     on its result, is above twice the one it was chosen for.
+ * Out of retries the step is kept (a negative mean is reported).  t (in/out)
+ * accumulates the time. */
+#define ORC_STEP_BOUND_FACTOR 2.0
 int orc_step(const orc_params *P, const orc_mesh *m, const double *b, double *h, double *hu,
              double *hv, int nsteps, double dt_fixed, double *t, double *last_dt)
 {
@@ -1068,12 +1077,15 @@ int orc_step(const orc_params *P, const orc_mesh *m, const double *b, double *h,
     if (!work) { geom_free(&G); return ORC_ENOMEM; }
     double *s0 = work + 6 * n, *s1 = work + 7 * n, *s2 = work + 8 * n;
     int status = ORC_OK;
+    const int adaptive = !(dt_fixed > 0.0);
+    double next[4];          /* bounds of the current state when already known */
+    int have_next = 0;
     for (int it = 0; it < nsteps; ++it) {
         double dt = dt_fixed;
-        if (!(dt > 0.0)) {
-            double o4[4];
-            dt_impl(P, &op, m, &G, b, h, hu, hv, o4);
-            dt = o4[0];
+        if (adaptive) {
+            if (!have_next) dt_impl(P, &op, m, &G, b, h, hu, hv, next);
+            dt = next[0];
+            have_next = 0;
         }
         memcpy(s0, h, sizeof(double) * n);
         memcpy(s1, hu, sizeof(double) * n);
@@ -1081,12 +1093,20 @@ int orc_step(const orc_params *P, const orc_mesh *m, const double *b, double *h,
         int tries = 0;
         for (;;) {
             st = one_step(P, &op, m, &G, b, h, hu, hv, dt, work);
-            if (st == ORC_ENEGMEAN && tries < P->max_dt_retries) {
+            int redo = st == ORC_ENEGMEAN;
+            if (!redo && st == ORC_OK && adaptive && P->max_dt_retries > 0) {
+                /* the bounds of the result: the check, and the next step */
+                dt_impl(P, &op, m, &G, b, h, hu, hv, next);
+                have_next = 1;
+                redo = dt > ORC_STEP_BOUND_FACTOR * fmin(next[1], next[2]);
+            }
+            if (redo && tries < P->max_dt_retries) {
                 memcpy(h, s0, sizeof(double) * n);
                 memcpy(hu, s1, sizeof(double) * n);
                 memcpy(hv, s2, sizeof(double) * n);
                 dt *= 0.5;
                 ++tries;
+                have_next = 0;
                 continue;
             }
             break;

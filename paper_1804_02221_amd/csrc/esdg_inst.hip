@@ -25,6 +25,8 @@ static Mesh<R> mesh_view(const Bufs &B)
     m.Ce = (const R *)B.Ce;
     m.bx = (const R *)B.bx;
     m.by = (const R *)B.by;
+    m.xr = B.xr;
+    m.yr = B.yr;
     m.bface = (const R *)B.bface;
     m.nbr = B.nbr;
     m.code = B.code;
@@ -68,7 +70,8 @@ hipError_t Launch<N, R>::geometry(const Bufs &B, const Tab<double> &td, hipStrea
     const int64_t n = B.K * np;
     const int bs = 256;
     hipLaunchKernelGGL((geometry_kernel<N, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, B.K,
-                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.flags + kFlagBadJ, td);
+                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.xr, B.yr, B.flags + kFlagBadJ,
+                       td);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((gmax_kernel<N, R>), dim3((unsigned)((B.K + bs - 1) / bs)), dim3(bs), 0, s,

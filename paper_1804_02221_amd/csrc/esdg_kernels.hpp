@@ -112,6 +112,8 @@ constexpr int kDtSlots = 64;
 // Device status flags of a context: negative element mean, limited
 // elements, no admissible step, J <= 0 at mesh upload, non-finite output.
 constexpr int kFlagNegMean = 0, kFlagLimited = 1, kFlagDtPos = 2, kFlagBadJ = 3, kFlagNonFinite = 4;
+// an adaptive step that exceeded twice the CFL / viscous bound of the state it produced
+constexpr int kFlagStepBound = 5;
 constexpr int kNumFlags = 8;
 
 // Tile of workgroup b when B = round_up(ntiles, 8) workgroups are launched:
@@ -151,6 +153,7 @@ struct Mesh {
     const R *Ax, *Cx;   // J grad(xi)  = ( y_eta, -x_eta)  [K][np]
     const R *Ae, *Ce;   // J grad(eta) = (-y_xi,   x_xi)   [K][np]
     const R *bx, *by;   // split-form bathymetry derivatives (eq. SourceDisc)
+    const double *xr, *yr;  // float64 coordinates less the element's first node [K][np] (float64 contexts)
     const R *bface;     // bathymetry on the faces [K][4][nf]
     const int32_t *nbr; // [K][4] neighbour element
     const int8_t *code; // [K][4] neighbour side | flip << 2 | wall << 3 (a wall names the element itself)
@@ -226,6 +229,18 @@ __device__ __forceinline__ R rcp_wet(R h, R h_tol)
 // which double precision absorbs and single precision does not.
 template <typename R>
 constexpr bool kJumpForm = sizeof(R) == 4;
+
+// At N <= 4 the double-precision stage kernel reads each node's two
+// coordinates (relative to its element's first node) instead of its four
+// metric terms and forms the metric terms itself, with the sums of
+// geometry_kernel in the same order (so bit for bit the stored values): 16
+// fewer bytes per node and stage for 4(N+1) multiply-adds and two more
+// workgroup barriers.  Measured on the stage kernel: 3-7% faster at N = 2..4,
+// 5-7% slower at N = 5..8, where the registers it holds across the face
+// prefetch cost occupancy or spills.  In single precision the four metric
+// terms take as many bytes as the two float64 coordinates.
+template <int N, typename R>
+constexpr bool kMetricInKernel = sizeof(R) == 8 && N <= 4;
 
 // Rotated numerical interface flux along the unit normal (nx, ny), '-' =
 // own trace, '+' = neighbour (appendix B): EC part plus, for the entropy
@@ -311,7 +326,7 @@ __device__ __forceinline__ void interface_flux_delta(R hm, R um, R vm, R bm, R h
 // ------------------------------------------------------------------------
 template <int N, typename R>
 __global__ void geometry_kernel(int64_t K, const double *__restrict__ x, const double *__restrict__ y,
-                                R *Ax, R *Cx, R *Ae, R *Ce, int *bad, Tab<double> tab)
+                                R *Ax, R *Cx, R *Ae, R *Ce, double *xr, double *yr, int *bad, Tab<double> tab)
 {
     constexpr int nf = N + 1, np = nf * nf;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,6 +348,12 @@ __global__ void geometry_kernel(int64_t K, const double *__restrict__ x, const d
     }
     const double J = xxi * yeta - xeta * yxi;
     if (!(J > 0.0)) atomicOr(bad, 1);
+    // the differenced coordinates themselves, for the float64 stage kernel,
+    // which forms the same sums from them (the same values bit for bit)
+    if (xr) {
+        xr[q] = xe[p] - x0;
+        yr[q] = ye[p] - y0;
+    }
     Ax[q] = (R)yeta;
     Cx[q] = (R)(-xeta);
     Ae[q] = (R)(-yxi);
@@ -1048,9 +1069,14 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     const bool av = a.eps != nullptr;
 
     R h = 0, hu = 0, hv = 0, Ax = 0, Cx = 0, Ae = 0, Ce = 0;
+    double xr = 0, yr = 0;
     if (act) {
         h = a.h[q]; hu = a.hu[q]; hv = a.hv[q];
-        Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
+        if constexpr (kMetricInKernel<N, R>) {
+            xr = a.m.xr[q]; yr = a.m.yr[q];
+        } else {
+            Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
+        }
     }
     // The face slots' neighbour traces and face bathymetry are loaded here,
     // with the element's own data, so that their latency is not paid a second
@@ -1072,6 +1098,30 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     s_h[st] = h;
     s_q[st] = V2{hu, hv};
     s_w[st] = V2{u, v};
+    if constexpr (kMetricInKernel<N, R>) {
+        // metric terms from the staged coordinates: J grad(xi) = (y_eta, -x_eta),
+        // J grad(eta) = (-y_xi, x_xi), each a derivative-matrix sum along a line
+        // (eq. NablaRelation); D (with its diagonal) sits in the face-flux
+        // slots until the face loop needs them
+        static_assert(3 * NF >= nf * nf, "D in the face-flux slots");
+        R *const s_D = &s_fl[0][0];
+        s_a[st] = V2{xr, yr};
+        for (int c = t; c < nf * nf; c += T) s_D[c] = a.tg->D[(c / nf) * kMaxNF + (c - (c / nf) * nf)];
+        lds_sync<T>();
+        const int base = el * PS;
+        R xxi = 0, yxi = 0, xeta = 0, yeta = 0;
+#pragma unroll 2
+        for (int m = 0; m < nf; ++m) {
+            const R di = s_D[i * nf + m], dj = s_D[j * nf + m];
+            const V2 ci = s_a[base + m * RS + j], cj = s_a[base + i * RS + m];
+            xxi += di * ci.x;
+            yxi += di * ci.y;
+            xeta += dj * cj.x;
+            yeta += dj * cj.y;
+        }
+        Ax = yeta; Cx = -xeta; Ae = -yxi; Ce = xxi;
+        lds_sync<T>();   // every lane's coordinate reads done before the metric replaces them
+    }
     s_a[st] = V2{Ax, Cx};
     s_b[st] = V2{Ae, Ce};
     if constexpr (MODE != kModeRhs)

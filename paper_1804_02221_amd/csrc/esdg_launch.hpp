@@ -14,6 +14,7 @@ struct Bufs {
     int N = 0;
     int64_t K = 0;
     double *x = nullptr, *y = nullptr;      // float64 coordinates
+    double *xr = nullptr, *yr = nullptr;    // the same less each element's first node (float64 contexts)
     void *Ax = nullptr, *Cx = nullptr, *Ae = nullptr, *Ce = nullptr;
     void *bx = nullptr, *by = nullptr, *bface = nullptr, *b = nullptr;
     int32_t *nbr = nullptr;

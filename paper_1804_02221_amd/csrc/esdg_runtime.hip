@@ -78,11 +78,36 @@ __global__ void fill_int_kernel(int *p, int v, int n)
 
 // Step status flags: [0] negative element mean, [1] limited elements,
 // [2] no admissible step, [3] J <= 0 at mesh upload (kept), [4] non-finite
-// stage output.  Clears all but [3].
+// stage output, [5] step above twice the bounds of its result.  Clears all
+// but [3].
 __global__ void reset_flags_kernel(int *flags)
 {
     const int t = threadIdx.x;
     if (t < kNumFlags && t != kFlagBadJ) flags[t] = 0;
+}
+
+// A-posteriori check of an adaptive step (reading of the remark that the
+// step is adjusted when a smaller one is found to be needed, section 6): the
+// dt pass has just reduced the CFL and viscous bounds of the state the step
+// produced into the slots; a step above kStepBoundFactor times the smaller of
+// the two (the factors cfl and cfl_visc are inside the bounds) raises
+// kFlagStepBound.  Like dt_finalize_kernel it resets the slots; the step in
+// dt[0] is left as it was (a retry halves it).
+constexpr double kStepBoundFactor = 2.0;
+__global__ void step_check_kernel(unsigned long long *slots, double *dt, int *flags)
+{
+    __shared__ double s[2][kDtSlots];
+    const int t = threadIdx.x;
+    const unsigned long long inf = 0x7FF0000000000000ull;
+    for (int c = 0; c < 2; ++c) s[c][t] = __longlong_as_double((long long)slots[c * kDtSlots + t]);
+    for (int c = 0; c < 3; ++c) slots[c * kDtSlots + t] = inf;
+    __syncthreads();
+    for (int st = kDtSlots / 2; st > 0; st >>= 1) {
+        if (t < st)
+            for (int c = 0; c < 2; ++c) s[c][t] = fmin(s[c][t], s[c][t + st]);
+        __syncthreads();
+    }
+    if (t == 0 && dt[0] > kStepBoundFactor * fmin(s[0][0], s[1][0])) atomicOr(&flags[kFlagStepBound], 1);
 }
 
 // Retry support: step <- f * step, time corrected by the removed part.
@@ -370,7 +395,7 @@ void free_bufs(esdg_ctx *c)
     }
     ++c->graph_gen;
     Bufs &B = c->B;
-    void *ps[] = {B.x, B.y, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
+    void *ps[] = {B.x, B.y, B.xr, B.yr, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
                   B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.frec, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
                   B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2], B.inst, B.cstart, B.cinst};
     for (void *p : ps)
@@ -932,6 +957,10 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     const size_t r = rsz(ctx);
     TRY(alloc(ctx, &B.x, n * sizeof(double)));
     TRY(alloc(ctx, &B.y, n * sizeof(double)));
+    if (ctx->prec == 64) {
+        TRY(alloc(ctx, &B.xr, n * sizeof(double)));
+        TRY(alloc(ctx, &B.yr, n * sizeof(double)));
+    }
     void **rn[] = {&B.Ax, &B.Cx, &B.Ae, &B.Ce, &B.bx, &B.by, &B.b, &B.dU[0], &B.dU[1], &B.dU[2],
                    &B.Rb[0], &B.Rb[1], &B.Rb[2]};
     for (void **p : rn) TRY(alloc(ctx, p, n * r));
@@ -1159,14 +1188,28 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 ctx->cur = base;
                 TRY(launch_one_step(ctx, dt, false));
             }
+            if (!(dt > 0.0)) {
+                // adaptive step: check it against the bounds of the state it produced
+                // (the last stage left them; the next step's dt pass recomputes them)
+                TRY(dispatch(ctx, [&](auto L, auto r) {
+                    using R = decltype(r);
+                    return decltype(L)::dt(ctx->B, ctx->cur, ctx->P.av_on != 0, true, phys<R>(ctx), ctx->stream,
+                                           Ev{});
+                }));
+                hipLaunchKernelGGL(step_check_kernel, dim3(1), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
+                                   ctx->B.dscal, ctx->B.flags);
+                CK(hipGetLastError());
+            }
             int flags[kNumFlags];
             TRY(read_flags(ctx, flags));
             if (flags[kFlagNonFinite]) break;   // reported below; halving the step cannot help
-            if (!flags[kFlagNegMean] || attempt >= retries) {
+            if (!(flags[kFlagNegMean] || flags[kFlagStepBound]) || attempt >= retries) {
+                // out of retries a step above the bounds of its result is kept
                 if (flags[kFlagNegMean]) status = ESDG_ENEGMEAN;
                 break;
             }
-            // negative mean: restart from W^n (untouched) with half the step
+            // negative mean, or a step above the bounds of its result: restart
+            // from W^n (untouched) with half the step
             ctx->cur = base;
             hipLaunchKernelGGL(scale_step_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->B.dscal, 0.5,
                                ctx->B.dscal + 4);

@@ -177,3 +177,41 @@ def test_dt_retry_against_oracle(esdg, orc, integrator):
         assert np.array_equal(a_, b_)
     for g_, o_ in zip(got, (h, hu, hv)):
         assert np.abs(g_ - o_).max() <= 1e-9 * max(1.0, np.abs(o_).max())
+
+
+@pytest.mark.parametrize("integrator,cfl,halvings", [(1, 0.5, 1), (0, 0.5, 0), (1, 1.0, 0)])
+def test_adaptive_step_check_against_oracle(esdg, orc, integrator, cfl, halvings):
+    """An adaptive step above twice the CFL / viscous bound of the state it
+    produced is redone at half the size (SSPRK(3,3) from a dam break at rest:
+    once); steps within it are kept (LSRK(5,4); SSPRK(3,3) with cfl = 1 at
+    1.2 times its result's bound).  The device takes the oracle's decisions:
+    the accepted step (to 1e-12), the time after three steps and the states
+    agree (to 1e-9, as in the retry test above: the limiter's theta near
+    zero means amplifies rounding; measured 5e-12 for the time at cfl = 1),
+    and the accepted step equals a direct fixed step of that size
+    (bitwise)."""
+    w = dam_break(6, 3, seed=4, rotate_seed=3)
+    kw = dict(av_on=1, limiter_on=1, eps0=0.05, integrator=integrator, cfl=cfl, max_dt_retries=4)
+    s, P = _solver(esdg, w, **kw)
+    Po = orc.params(3, **P.as_dict())
+    dt0 = orc.dt(Po, w.mesh, w.b, w.h, w.hu, w.hv)[0]
+    t1, st = s.step(1, 0.0)
+    got = s.get_state()
+    t3, _ = s.step(2, 0.0)
+    got3 = s.get_state()
+    s.close()
+    assert st == 0
+    assert abs(t1 - dt0 / 2 ** halvings) <= 1e-12 * dt0
+    h, hu, hv, to1, _ = orc.step(Po, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
+    h3, hu3, hv3, to3, _ = orc.step(Po, w.mesh, w.b, h, hu, hv, 2, 0.0, t0=to1)
+    # the first step starts from the common state; the later ones from states
+    # that agree to 1e-9 (limited elements), so their steps agree to that
+    assert abs(t1 - to1) <= 1e-12 * to1 and abs(t3 - to3) <= 1e-9 * to3
+    s, _ = _solver(esdg, w, **{**kw, "max_dt_retries": 0})
+    s.step(1, t1)
+    direct = s.get_state()
+    s.close()
+    for c in range(3):
+        assert np.array_equal(got[c], direct[c])
+    for g_, o_ in zip(got + got3, (h, hu, hv, h3, hu3, hv3)):
+        assert np.abs(g_ - o_).max() <= 1e-9 * max(1.0, np.abs(o_).max())
