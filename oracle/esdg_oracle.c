@@ -874,8 +874,10 @@ int orc_limit(const orc_params *P, const orc_mesh *m, double *h, double *hu, dou
 /* Time step: advective CFL, viscous bound, Lemma 2 positivity bounds        */
 /* ------------------------------------------------------------------------ */
 /* Spectral radius of the 1D BR1 operator at dx = 1, eps = 1, per N (derived
- * numerically for N = 2..8; parity unpinned by the paper), and the real-axis
- * stability limit of LSRK(5,4). */
+ * numerically for N = 2..8; the paper gives no values), and the real-axis
+ * stability limit of LSRK(5,4) rounded down.  Both are checked against their
+ * definitions by a CPU test that assembles the operator and the stability
+ * function independently. */
 static const double ORC_BR1_RADIUS[9] = {0, 0, 25.6, 82.9, 203.0, 425.0, 800.0, 1383.0, 2244.0};
 static const double ORC_LSRK_REAL_LIMIT = 4.6;
 
