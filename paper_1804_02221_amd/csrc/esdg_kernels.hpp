@@ -642,10 +642,16 @@ __device__ R element_viscosity(const R *sh, R *red, const R *vinv, const Phys<R>
 {
     constexpr int nf = N + 1, np = nf * nf;
     const int i = p / nf, j = p - i * nf;
+    // single precision transforms h - c (c the element's first nodal height):
+    // the higher modes of a smooth element are small against h itself, and
+    // in h their FP32 rounding would move the energy ratios, hence eps on
+    // the ramp.  A constant has the one mode (0, 0), of coefficient 2c (the
+    // orthonormal Legendre L_0 = 1/sqrt(2) in both directions), restored below.
+    const R c0 = (kJumpForm<R> && lane) ? sh[el * np] : R(0);
     R Tq = 0;
     if (lane) {
 #pragma unroll
-        for (int r = 0; r < nf; ++r) Tq += vinv[i * nf + r] * sh[el * np + r * nf + j];
+        for (int r = 0; r < nf; ++r) Tq += vinv[i * nf + r] * (sh[el * np + r * nf + j] - c0);
     }
     red[5 * T + t] = Tq;
     lds_sync<T>();
@@ -654,6 +660,8 @@ __device__ R element_viscosity(const R *sh, R *red, const R *vinv, const Phys<R>
 #pragma unroll
         for (int c = 0; c < nf; ++c) Qh += red[5 * T + el * np + i * nf + c] * vinv[j * nf + c];
     }
+    if constexpr (kJumpForm<R>)
+        if (p == 0) Qh += R(2) * c0;
     const R q2 = Qh * Qh;
     const int mx = i > j ? i : j;
     // the energy of all modes is the top shell's plus that of the modes up to N-1
