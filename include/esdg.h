@@ -93,10 +93,10 @@ typedef struct {
     int limiter_on;    /* positivity limiter after every stage (eq. PosPres),
                           and the Lemma 2 bound enters the adaptive step     */
     int integrator;    /* 0: LSRK(5,4) 2N-storage, 1: SSPRK(3,3)              */
-    int max_dt_retries;/* redo a step from W^n with dt/2, at most this many
-                          times, when it meets a negative element mean or,
-                          for an adaptive step, exceeds twice the smaller of
-                          the CFL and viscous bounds of the state it
+    int max_dt_retries;/* redo a step (fixed or adaptive) from W^n with
+                          dt/2, at most this many times, when it meets a
+                          negative element mean or exceeds twice the smaller
+                          of the CFL and viscous bounds of the state it
                           produced (each step then synchronises with the
                           host)                                             */
 } esdg_params;
@@ -180,11 +180,11 @@ int esdg_compute_dt(esdg_ctx *ctx, double out[4]);
  * values; the state then holds them.
  * With max_dt_retries > 0 a step is also checked after the fact (section 6:
  * the CFL step is adjusted when a smaller one proves necessary): a negative
- * element mean in the limiter, or an adaptive step larger than twice the
- * smaller of the CFL and viscous bounds of the state it produced (its wave
- * speeds or viscosity grew that much within the step), restarts the step
- * from W^n with half its size.  Out of retries the step is kept; only a
- * negative mean is then reported.
+ * element mean in the limiter, or a step (fixed or adaptive) larger than
+ * twice the smaller of the CFL and viscous bounds of the state it produced
+ * (its wave speeds or viscosity grew that much within the step), restarts
+ * the step from W^n with half its size.  Out of retries the step is kept;
+ * only a negative mean is then reported.
  */
 int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out);
 

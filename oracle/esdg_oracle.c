@@ -1052,15 +1052,16 @@ static int one_step(const orc_params *P, const orc_ops *op, const orc_mesh *m,
 
 /* nsteps steps; dt_fixed > 0 gives a fixed step, otherwise the step is
  * min(CFL, viscous, positivity) bound evaluated at the start of each step.
- * The step is redone from W^n with half its size, at most max_dt_retries
- * times, when it proves too large (reading of the section 6 remark that the
- * step is adjusted when a smaller one is found to be needed):
- *   - a negative element mean in the limiter (any step);
- *   - an adaptive step larger than ORC_STEP_BOUND_FACTOR times the smaller
- *     of the CFL and viscous bounds of the state it produced (the bounds
- *     hold the factors cfl and cfl_visc), i.e. the wave speeds or the
- *     viscosity grew so much within the step that its CFL number, measured
- *     on its result, is above twice the one it was chosen for.
+ * The step (adaptive or fixed) is redone from W^n with half its size, at
+ * most max_dt_retries times, when it proves too large (reading of the
+ * section 6 remark that the step is adjusted when a smaller one is found to
+ * be needed):
+ *   - a negative element mean in the limiter;
+ *   - a step larger than ORC_STEP_BOUND_FACTOR times the smaller of the CFL
+ *     and viscous bounds of the state it produced (the bounds hold the
+ *     factors cfl and cfl_visc), i.e. the wave speeds or the viscosity grew
+ *     so much within the step that its CFL number, measured on its result,
+ *     is above twice the one an adaptive step is chosen for.
  * Out of retries the step is kept (a negative mean is reported).  t (in/out)
  * accumulates the time. */
 #define ORC_STEP_BOUND_FACTOR 2.0
@@ -1096,8 +1097,8 @@ int orc_step(const orc_params *P, const orc_mesh *m, const double *b, double *h,
         for (;;) {
             st = one_step(P, &op, m, &G, b, h, hu, hv, dt, work);
             int redo = st == ORC_ENEGMEAN;
-            if (!redo && st == ORC_OK && adaptive && P->max_dt_retries > 0) {
-                /* the bounds of the result: the check, and the next step */
+            if (!redo && st == ORC_OK && P->max_dt_retries > 0) {
+                /* the bounds of the result: the check, and the next adaptive step */
                 dt_impl(P, &op, m, &G, b, h, hu, hv, next);
                 have_next = 1;
                 redo = dt > ORC_STEP_BOUND_FACTOR * fmin(next[1], next[2]);

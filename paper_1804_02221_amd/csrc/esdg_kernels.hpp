@@ -112,7 +112,7 @@ constexpr int kDtSlots = 64;
 // Device status flags of a context: negative element mean, limited
 // elements, no admissible step, J <= 0 at mesh upload, non-finite output.
 constexpr int kFlagNegMean = 0, kFlagLimited = 1, kFlagDtPos = 2, kFlagBadJ = 3, kFlagNonFinite = 4;
-// an adaptive step that exceeded twice the CFL / viscous bound of the state it produced
+// a step that exceeded twice the CFL / viscous bound of the state it produced
 constexpr int kFlagStepBound = 5;
 constexpr int kNumFlags = 8;
 

@@ -86,11 +86,11 @@ __global__ void reset_flags_kernel(int *flags)
     if (t < kNumFlags && t != kFlagBadJ) flags[t] = 0;
 }
 
-// A-posteriori check of an adaptive step (reading of the remark that the
-// step is adjusted when a smaller one is found to be needed, section 6): the
-// dt pass has just reduced the CFL and viscous bounds of the state the step
-// produced into the slots; a step above kStepBoundFactor times the smaller of
-// the two (the factors cfl and cfl_visc are inside the bounds) raises
+// A-posteriori check of a step (reading of the remark that the step is
+// adjusted when a smaller one is found to be needed, section 6): the dt pass
+// has just reduced the CFL and viscous bounds of the state the step produced
+// into the slots; a step above kStepBoundFactor times the smaller of the two
+// (the factors cfl and cfl_visc are inside the bounds) raises
 // kFlagStepBound.  Like dt_finalize_kernel it resets the slots; the step in
 // dt[0] is left as it was (a retry halves it).
 constexpr double kStepBoundFactor = 2.0;
@@ -1188,9 +1188,9 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                 ctx->cur = base;
                 TRY(launch_one_step(ctx, dt, false));
             }
-            if (!(dt > 0.0)) {
-                // adaptive step: check it against the bounds of the state it produced
-                // (the last stage left them; the next step's dt pass recomputes them)
+            {
+                // check the step against the bounds of the state it produced (the
+                // last stage left them; the next step's dt pass recomputes them)
                 TRY(dispatch(ctx, [&](auto L, auto r) {
                     using R = decltype(r);
                     return decltype(L)::dt(ctx->B, ctx->cur, ctx->P.av_on != 0, true, phys<R>(ctx), ctx->stream,

@@ -147,9 +147,13 @@ def _solver(esdg, w, **kw):
 @pytest.mark.parametrize("integrator", [0, 1])
 def test_dt_retry_against_oracle(esdg, orc, integrator):
     """A fixed step 16x the Lemma 2 bound makes an element mean negative; with
-    three retries the step is halved until it is admissible (2x for LSRK,
-    4x for SSPRK on this state).  The retried step must equal a direct step
-    of the accepted size (bitwise, on each side), and the two sides agree.
+    three retries the step is halved while it meets a negative mean or
+    exceeds twice the bounds of its result, at most three times: on this
+    state the negative mean clears after three halvings for LSRK and after
+    two for SSPRK, where the step check asks for the third; the kept step is
+    still 38-42 times the bound of its result (out of retries).  The retried
+    step must equal a direct step of the accepted size (bitwise, on each
+    side), and the two sides agree.
     The accepted step is still far above the bound and limits elements whose
     mean is close to zero, where theta = mean / (mean - min h) amplifies
     rounding; the cross-check tolerance is 1e-9 of the field size."""

@@ -1,6 +1,6 @@
 """Pins of the oracle's step adjustment (section 6: the step is chosen by a
 CFL condition and adjusted when a smaller one proves necessary).  Reading:
-an adaptive step is redone from W^n with half its size, at most
+a step (adaptive or fixed) is redone from W^n with half its size, at most
 max_dt_retries times, when the limiter meets a negative element mean or when
 the step is larger than twice the smaller of the CFL and viscous bounds of
 the state it produced.  Each accepted or rejected size is re-derived here
@@ -65,18 +65,25 @@ def test_adaptive_step_kept_when_admissible_for_its_result(orc, integrator, cfl,
     assert st == 0 and t == dt0
 
 
-@pytest.mark.parametrize("retries", [0, 4])
-def test_fixed_step_and_no_retries_are_not_checked(orc, retries):
-    """A caller's fixed step is taken as given (only a negative mean would
-    redo it), and without retries an adaptive step is never redone."""
+def test_fixed_step_is_checked_too(orc):
+    """A caller's fixed step meets the same check: the SSPRK(3,3) step the
+    start state allows, given as a fixed step, is redone once at half the
+    size (callers clip the step to reach an end time this way)."""
     w = dam_break(6, 3, seed=4, rotate_seed=3)
-    P = _params(orc, w, integrator=1, max_dt_retries=retries)
+    P = _params(orc, w, integrator=1, max_dt_retries=4)
     dt0 = orc.dt(P, w.mesh, w.b, w.h, w.hu, w.hv)[0]
     _, _, _, t, _ = orc.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 1, dt0)
+    assert t == dt0 / 2
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+def test_no_retries_no_check(orc, fixed):
+    """Without retries a step is never redone, adaptive or fixed."""
+    w = dam_break(6, 3, seed=4, rotate_seed=3)
+    P = _params(orc, w, integrator=1, max_dt_retries=0)
+    dt0 = orc.dt(P, w.mesh, w.b, w.h, w.hu, w.hv)[0]
+    _, _, _, t, _ = orc.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 1, dt0 if fixed else 0.0)
     assert t == dt0
-    if retries == 0:
-        _, _, _, t, _ = orc.step(P, w.mesh, w.b, w.h, w.hu, w.hv, 1, 0.0)
-        assert t == dt0
 
 
 def test_next_step_takes_the_bounds_of_the_kept_state(orc):
