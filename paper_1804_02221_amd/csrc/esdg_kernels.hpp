@@ -66,9 +66,9 @@ struct TileShape {
 //      (more registers, no spills where the default spills);
 //   3  the default tile with the other partner-loop unroll (full where the
 //      default unrolls partly, by two where it unrolls fully);
-//   4  the default tile with the staged fields' LDS rows padded by one node
-//      (the paper's LDS padding, appendix C: the eta-direction partner reads
-//      of a wave no longer share banks), at the cost of more LDS per tile.
+//   4  the default tile with bank-conflict-free staging rows: padded by one
+//      node (the paper's LDS padding, appendix C), or at N = 7 XOR-swizzled
+//      columns (no more LDS; StageCfg::SWZ).
 // Default register budget in the FP64 update modes: six waves per SIMD at
 // N = 6, five otherwise (N = 7 reaches six by its partner-loop unroll); no
 // constraint in FP32 and in the right-hand-side mode.  Default unroll: fully,
@@ -84,10 +84,24 @@ struct StageCfg {
     static constexpr int waves = V == 2 ? base_waves - 1 : base_waves;
     static constexpr int vu_default = (N == 7 && T == 64) ? 2 : (N == 8 ? 3 : (N == 6 ? 2 : N + 1));
     static constexpr int VU = V == 3 ? (vu_default == N + 1 ? 2 : N + 1) : vu_default;
-    // LDS row padding of the staged fields (one spare node per row of N + 1):
-    // the eta-direction partner reads of a wave then fall on different banks
-    static constexpr int PAD = V == 4 ? 1 : 0;
+    // Variant 4 avoids the LDS bank conflicts of the eta-direction partner
+    // reads (a wave reads column mm of every row, rows 16(N+1) bytes apart in
+    // FP64: at N = 7 eight rows on two bank groups).  At N = 7 the columns of
+    // row i are XOR-swizzled (node (i, j) in column j ^ (i >> 1)), which puts
+    // the eight rows' reads on distinct banks in both directions with no more
+    // LDS; at the other degrees, whose N + 1 is no power of two, each row is
+    // padded by one node.
+    static constexpr bool SWZ = V == 4 && N == 7;
+    static constexpr int PAD = (V == 4 && !SWZ) ? 1 : 0;
 };
+
+// Column of node (i, j) in its LDS staging row (see StageCfg::SWZ).
+template <int N, int V>
+__device__ __forceinline__ int stage_col(int i, int j)
+{
+    if constexpr (StageCfg<N, V>::SWZ) return j ^ (i >> 1);
+    else return j;
+}
 
 template <int N, typename R, int MODE, int V>
 struct StageWaves {
@@ -1048,8 +1062,9 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     using V2 = typename Vec2<R>::type;
     // one contiguous staging region: reused as reduction scratch at the end.
     // Pairs read together are stored together (one 16-byte LDS read in FP64).
-    // Node (i, j) of tile element el sits at el*PS + i*RS + j (RS = N + 1 +
-    // PAD); lanes past the tile's nodes write to spare slots after them.
+    // Node (i, j) of tile element el sits at el*PS + i*RS + stage_col(i, j)
+    // (RS = N + 1 + PAD); lanes past the tile's nodes write to spare slots
+    // after them.
     constexpr int RS = nf + StageCfg<N, V>::PAD, PS = nf * RS, LEN = E * PS + (T - E * np);
     static_assert(LEN >= T, "staging rows");
     __shared__ __align__(16) R s_st[9 * LEN];
@@ -1102,7 +1117,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     const R eps_e = (av && act) ? a.eps[e] : R(0);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
-    const int st = lane ? el * PS + i * RS + j : E * PS + (t - E * np);
+    const int st = lane ? el * PS + i * RS + stage_col<N, V>(i, j) : E * PS + (t - E * np);
     s_h[st] = h;
     s_q[st] = V2{hu, hv};
     s_w[st] = V2{u, v};
@@ -1121,7 +1136,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
 #pragma unroll 2
         for (int m = 0; m < nf; ++m) {
             const R di = s_D[i * nf + m], dj = s_D[j * nf + m];
-            const V2 ci = s_a[base + m * RS + j], cj = s_a[base + i * RS + m];
+            const V2 ci = s_a[base + m * RS + stage_col<N, V>(m, j)], cj = s_a[base + i * RS + stage_col<N, V>(i, m)];
             xxi += di * ci.x;
             yxi += di * ci.y;
             xeta += dj * cj.x;
@@ -1149,7 +1164,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         if (fe < a.m.K) {
             int fi, fj;
             side_node<N>(s, k, fi, fj);
-            const int lp = fel * PS + fi * RS + fj;
+            const int lp = fel * PS + fi * RS + stage_col<N, V>(fi, fj);
             const int64_t en = pfr.en;
             const int ns = pfr.ns(), kk = pfr.kk();
             int ni, nj;
@@ -1166,7 +1181,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             R hn, un, vn, bo, bn;
             if (ql >= 0 && ql < E * np) {
                 const int qe = (int)ql / np, qp = (int)ql - qe * np;
-                const int qs = qe * PS + (qp / nf) * RS + (qp - (qp / nf) * nf);
+                const int qs = qe * PS + (qp / nf) * RS + stage_col<N, V>(qp / nf, qp - (qp / nf) * nf);
                 hn = s_h[qs];
                 const V2 w = s_w[qs];
                 un = w.x;
@@ -1235,7 +1250,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             const R tA = R(2) * Ax, tC = R(2) * Cx;
 #pragma unroll VU
             for (int mm = 0; mm < nf; ++mm) {
-                const int qq = base + mm * RS + j;
+                const int qq = base + mm * RS + stage_col<N, V>(mm, j);
                 const R d = s_dz[i * nf + mm];
                 const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
                 const R hm = s_h[qq];
@@ -1255,7 +1270,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             const R tA = R(2) * Ae, tC = R(2) * Ce;
 #pragma unroll VU
             for (int mm = 0; mm < nf; ++mm) {
-                const int qq = base + i * RS + mm;
+                const int qq = base + i * RS + stage_col<N, V>(i, mm);
                 const R d = s_dz[j * nf + mm];
                 const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
                 const R hm = s_h[qq];
@@ -1278,7 +1293,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
             // the self pair has coefficient 0 (no branch: D~ has a zero diagonal)
-            const int qq = base + mm * RS + j;
+            const int qq = base + mm * RS + stage_col<N, V>(mm, j);
             const R d = s_dz[i * nf + mm];
             const V2 am = s_a[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ax + am.x, sC = Cx + am.y;
@@ -1292,7 +1307,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         }
 #pragma unroll VU
         for (int mm = 0; mm < nf; ++mm) {
-            const int qq = base + i * RS + mm;
+            const int qq = base + i * RS + stage_col<N, V>(i, mm);
             const R d = s_dz[j * nf + mm];
             const V2 bm = s_b[qq], qm = s_q[qq], wm = s_w[qq];
             const R sA = Ae + bm.x, sC = Ce + bm.y;
