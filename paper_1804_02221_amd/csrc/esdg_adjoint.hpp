@@ -144,6 +144,40 @@ struct AdjArgs {
     int64_t ntiles;
 };
 
+// Face slot data of the reverse stage, loaded with the element's own data
+// ahead of the LDS staging so that their latency is paid once (as in the
+// forward stage kernel): the neighbour's trace, cotangent inputs and metric
+// at the shared node, and the face bathymetry of both sides.
+struct AdjFacePrefetch {
+    bool wall = false;
+    double hn = 0, hun = 0, hvn = 0;
+    double c0 = 0, c1 = 0, c2 = 0, a0 = 0, a1 = 0, a2 = 0;
+    double nAx = 0, nCx = 0, nAe = 0, nCe = 0;
+    double bo = 0, bn = 0;
+};
+
+template <int N>
+__device__ __forceinline__ void adj_prefetch_face(const AdjArgs &a, int f, int64_t e0, AdjFacePrefetch &pf)
+{
+    constexpr int nf = N + 1;
+    if (f >= Shape<N>::NFACE) return;
+    const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
+    const int64_t fe = e0 + fel;
+    if (fe >= a.m.K) return;
+    int ns, kk;
+    int64_t en;
+    const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
+    pf.wall = is_wall(a.m, fe, s);
+    pf.hn = a.h[qn]; pf.hun = a.hu[qn]; pf.hvn = a.hv[qn];
+    if (!pf.wall) {
+        pf.nAx = a.m.Ax[qn]; pf.nCx = a.m.Cx[qn]; pf.nAe = a.m.Ae[qn]; pf.nCe = a.m.Ce[qn];
+        if (a.c[0]) { pf.c0 = a.c[0][qn]; pf.c1 = a.c[1][qn]; pf.c2 = a.c[2][qn]; }
+        if (a.a[0]) { pf.a0 = a.a[0][qn]; pf.a1 = a.a[1][qn]; pf.a2 = a.a[2][qn]; }
+    }
+    pf.bo = a.m.bface[(fe * 4 + s) * nf + k];
+    pf.bn = a.m.bface[(en * 4 + ns) * nf + kk];
+}
+
 // Register budget of four waves per SIMD (128 VGPRs, 4 spilled): unbounded
 // it takes 132 VGPRs and three waves; measured at 128^2, N = 5, 2.5% faster
 // per launch (five waves spill 36 VGPRs and run 40% slower).
@@ -175,8 +209,14 @@ __global__ __launch_bounds__(Shape<N>::T, 4) void adjoint_stage_kernel(AdjArgs a
         Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
         if (a.a[0]) { A0 = a.a[0][q]; A1 = a.a[1][q]; A2 = a.a[2][q]; }
         if (a.c[0]) { l0 = a.c[0][q]; l1 = a.c[1][q]; l2 = a.c[2][q]; }
-        l0 += a.cb * A0; l1 += a.cb * A1; l2 += a.cb * A2;
     }
+    // one face slot per lane: its loads go out with the element's own (with
+    // two per lane, at N = 2, holding both would spill; they load after the
+    // staging as the slots are evaluated)
+    constexpr int NS = (NF + T - 1) / T;
+    AdjFacePrefetch pf0;
+    if constexpr (NS == 1) adj_prefetch_face<N>(a, t, e0, pf0);
+    if (act) { l0 += a.cb * A0; l1 += a.cb * A1; l2 += a.cb * A2; }
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
     const R J = Ce * Ax - Cx * Ae;
@@ -192,41 +232,38 @@ __global__ __launch_bounds__(Shape<N>::T, 4) void adjoint_stage_kernel(AdjArgs a
     lds_sync<T>();
 
     // ---- interface: own term w.r.t. the '-' trace, neighbour's term w.r.t. its '+' trace ----
-    for (int f = t; f < NF; f += T) {
+    auto face_slot = [&](const int f, const AdjFacePrefetch &pfr) {
         const int fel = f / (4 * nf), s = (f / nf) & 3, k = f - (f / nf) * nf;
         const int64_t fe = e0 + fel;
         R gh = 0, gu = 0, gv = 0, gb = 0;
         if (fe < a.m.K) {
-            int fi, fj, ns, kk;
-            int64_t en;
+            int fi, fj;
             side_node<N>(s, k, fi, fj);
             const int lp = fel * np + fi * nf + fj;
-            const int64_t qn = nbr_node<N>(a.m, fe, s, k, en, ns, kk);
             // own outward normal and surface Jacobian
             const double2 dir = (s & 1) ? s_a[lp] : s_b[lp];
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
             const R snx = sg * dir.x, sny = sg * dir.y;
             const R js = sqrt(snx * snx + sny * sny);
             const R nx = snx / js, ny = sny / js;
-            const bool wall = is_wall(a.m, fe, s);
+            const bool wall = pfr.wall;
             // neighbour's trace and cotangent mu_n = -l_n / J_n (a wall: the
             // own trace, mirrored, and no neighbour term)
-            const R hn = a.h[qn];
+            const R hn = pfr.hn;
             const R inn = rcp_wet(hn, P.h_tol);
-            R un = a.hu[qn] * inn, vn = a.hv[qn] * inn;
+            R un = pfr.hun * inn, vn = pfr.hvn * inn;
             R nm0 = 0, nm1 = 0, nm2 = 0;
             if (wall) {
                 wall_mirror(nx, ny, un, vn);
             } else {
-                const R nJ = a.m.Ce[qn] * a.m.Ax[qn] - a.m.Cx[qn] * a.m.Ae[qn];
-                R nl0 = 0, nl1 = 0, nl2 = 0;
-                if (a.c[0]) { nl0 = a.c[0][qn]; nl1 = a.c[1][qn]; nl2 = a.c[2][qn]; }
-                if (a.a[0]) { nl0 += a.cb * a.a[0][qn]; nl1 += a.cb * a.a[1][qn]; nl2 += a.cb * a.a[2][qn]; }
+                const R nJ = pfr.nCe * pfr.nAx - pfr.nCx * pfr.nAe;
+                R nl0 = pfr.c0, nl1 = pfr.c1, nl2 = pfr.c2;
+                if (a.a[0]) { nl0 += a.cb * pfr.a0; nl1 += a.cb * pfr.a1; nl2 += a.cb * pfr.a2; }
                 const R inJ = R(1) / nJ;
                 nm0 = nl0 * inJ; nm1 = nl1 * inJ; nm2 = nl2 * inJ;
             }
-            const R bo = a.m.bface[(fe * 4 + s) * nf + k];
-            const R bn = a.m.bface[(en * 4 + ns) * nf + kk];
+            const R bo = pfr.bo;
+            const R bn = pfr.bn;
             const R ho = s_h[lp];
             const double2 wo = s_w[lp];
             // Own term (J^surf / w_0) mu . F*(own, nbr, n) and the neighbour's
@@ -256,6 +293,15 @@ __global__ __launch_bounds__(Shape<N>::T, 4) void adjoint_stage_kernel(AdjArgs a
             }
         }
         s_fg[0][f] = gh; s_fg[1][f] = gu; s_fg[2][f] = gv; s_fg[3][f] = gb;
+    };
+    if constexpr (NS == 1) {
+        if (t < NF) face_slot(t, pf0);
+    } else {
+        for (int f = t; f < NF; f += T) {
+            AdjFacePrefetch pfl;
+            adj_prefetch_face<N>(a, f, e0, pfl);
+            face_slot(f, pfl);
+        }
     }
 
     // ---- volume: pairs along xi and eta; z = Dz_im mu_i + Dz_mi mu_m (D~ = 2 Dz).
