@@ -178,11 +178,20 @@ __device__ __forceinline__ void adj_prefetch_face(const AdjArgs &a, int f, int64
     pf.bn = a.m.bface[(en * 4 + ns) * nf + kk];
 }
 
-// Register budget of four waves per SIMD (128 VGPRs, 4 spilled): unbounded
-// it takes 132 VGPRs and three waves; measured at 128^2, N = 5, 2.5% faster
-// per launch (five waves spill 36 VGPRs and run 40% slower).
+// Register budget of four waves per SIMD (128 VGPRs, a few spilled) for
+// N >= 3: unbounded it takes 132-134 VGPRs and three waves; measured 2.5%
+// faster per launch at 128^2, N = 5, and 2.7% at 192^2, N = 3 (five waves
+// spill 36 VGPRs and run 40% slower).  N = 2, with two face slots per lane,
+// spills 20 VGPRs under that budget and runs 14% slower: no budget there
+// (with each slot's loads grouped ahead of its evaluation it runs 12%
+// faster than before, 40.8 against 46.4 us at 256^2).
 template <int N>
-__global__ __launch_bounds__(Shape<N>::T, 4) void adjoint_stage_kernel(AdjArgs a)
+struct AdjWaves {
+    static constexpr int value = N == 2 ? 1 : 4;
+};
+
+template <int N>
+__global__ __launch_bounds__(Shape<N>::T, AdjWaves<N>::value) void adjoint_stage_kernel(AdjArgs a)
 {
     using S = Shape<N>;
     using R = double;
