@@ -1105,15 +1105,12 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     // with the element's own data, so that their latency is not paid a second
     // time after the LDS staging; a lane holds NS slots (two at N = 2, where
     // seven elements' 84 face nodes outnumber the 64 lanes).
+    // With more slots than lanes (N = 2) only the first slot is prefetched;
+    // the few lanes with a further slot load it when they evaluate it.
     constexpr int NS = (NF + T - 1) / T;
-    FacePrefetch<R> pf[NS];
-    if constexpr (NS == 1) {
-        // (a one-trip loop here costs a VGPR and a dozen spilled SGPRs at N = 7)
-        prefetch_face<N, R, E, NF>(a, t, e0, pf[0]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < NS; ++r) prefetch_face<N, R, E, NF>(a, t + r * T, e0, pf[r]);
-    }
+    FacePrefetch<R> pf0;
+    // (a one-trip loop here costs a VGPR and a dozen spilled SGPRs at N = 7)
+    prefetch_face<N, R, E, NF>(a, t, e0, pf0);
     const R eps_e = (av && act) ? a.eps[e] : R(0);
     const R ih = rcp_wet(h, P.h_tol);
     const R u = hu * ih, v = hv * ih;
@@ -1219,12 +1216,13 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         }
         s_fl[0][f] = c0; s_fl[1][f] = c1; s_fl[2][f] = c2;
     };
-    if constexpr (NS == 1) {
-        for (int f = t; f < NF; f += T) face_slot(f, pf[0]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < NS; ++r)
-            if (t + r * T < NF) face_slot(t + r * T, pf[r]);
+    if (t < NF) face_slot(t, pf0);
+    if constexpr (NS > 1) {
+        for (int f = t + T; f < NF; f += T) {
+            FacePrefetch<R> pfl;
+            prefetch_face<N, R, E, NF>(a, f, e0, pfl);
+            face_slot(f, pfl);
+        }
     }
 
     // ---- volume: sum_m 2 D_im F~(i,m) + sum_m 2 D_jm G~(j,m) (D~ has a zero
