@@ -205,7 +205,7 @@ def ensemble_bench(esdg, dev, members, steps: int):
     ens.build()
     stages = 3 if members[0].params.get("integrator", 0) == 1 else 5
     ens.step(1, raise_negmean=False)  # warm-up (also builds the time-step bounds)
-    tuned = ens.autotune(5)
+    tuned = ens.autotune(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st_ens = ens.step(steps, raise_negmean=False)
@@ -225,7 +225,7 @@ def ensemble_bench(esdg, dev, members, steps: int):
     for w in members:
         s = esdg.solver_for(w, dev)
         s.step(1, 0.0, raise_negmean=False)
-        s.autotune(5)
+        s.autotune(20)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, st = s.step(steps, 0.0, raise_negmean=False)
@@ -615,7 +615,7 @@ def main():
         else:
             R = None
         s.step(warmup, 0.0)
-        choice, tune_ms = s.autotune(5) if args.autotune else (0, None)
+        choice, tune_ms = s.autotune(20) if args.autotune else (0, None)
         s.step(3, 0.0)        # one step from each state buffer: the step graphs are captured here
         torch.cuda.synchronize()
         # the timed steps: each step one graph replay (esdg_set_graphs)
