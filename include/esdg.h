@@ -323,12 +323,19 @@ int esdg_abi_version(void);
  * esdg_ensemble_add copies the instance (host pointers only; arrays as in
  * esdg_upload_mesh, esdg_set_bathymetry and esdg_set_state) and returns
  * its id (0, 1, ...).  Instances of one degree must have identical
- * parameters; max_dt_retries must be 0 (ESDG_EINVAL otherwise).
+ * parameters.  With max_dt_retries > 0 every instance takes the step check
+ * of esdg_step on its own: an instance whose step met a negative element
+ * mean or exceeds twice the CFL / viscous bound of its result redoes it with
+ * half its step; the degree group's step is relaunched from W^n, and the
+ * other instances redo theirs bit for bit (each degree group then waits for
+ * its step's checks, one host synchronisation per step).
  * esdg_ensemble_build uploads everything (done by the first step or query
  * if not called); no instance can be added afterwards.
  * esdg_ensemble_step advances every instance by nsteps adaptive steps and
  * returns when they are done (ESDG_ENEGMEAN / ESDG_EDTPOS if any instance
- * met a negative element mean / had no admissible step).
+ * kept a step that met a negative element mean -- with retries, after them
+ * -- / had no admissible step; with retries ESDG_ENONFINITE and ESDG_EDTPOS
+ * end the call at the step where they occur).
  * esdg_ensemble_get_state / _get_time return one instance's state (mem:
  * 0 host, 1 device destination) and time.
  */

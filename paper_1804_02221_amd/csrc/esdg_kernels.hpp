@@ -1011,6 +1011,7 @@ struct StageArgs {
     const double *dt;            // per instance k: the current step at dt[8k]
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
     int *flags;                  // status flags (kFlag*)
+    int *iflags;                 // ensembles with step retries: per-instance flags (1: negative mean), else nullptr
     int64_t ntiles;
     int variant;                 // compiled variant 0..kStageVariants-1 (launch side)
 };
@@ -1380,6 +1381,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
                     if (mh < R(0)) {
                         th = R(0);
                         atomicOr(&a.flags[kFlagNegMean], 1);
+                        if (a.iflags) atomicOr(&a.iflags[a.inst ? a.inst[e] : 0], 1);
                     } else {
                         th = mh / (mh - mn);
                         th = th < R(1) ? th : R(1);

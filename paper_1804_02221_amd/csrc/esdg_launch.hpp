@@ -41,6 +41,8 @@ struct Bufs {
     int32_t *cinst = nullptr;   // [nchunks] instance of each chunk
     int64_t nchunks = 0;
     int *flags = nullptr;    // status flags (kFlag* in esdg_kernels.hpp)
+    int *iflags = nullptr;   // [n_inst] per-instance step flags (ensembles): 1 negative mean, 2 step above its result's bounds
+    int *imask = nullptr;    // [n_inst] instances whose step is redone at half the size (ensembles)
     double *part = nullptr;  // diagnostics partial sums
     int64_t part_cap = 0;
 };

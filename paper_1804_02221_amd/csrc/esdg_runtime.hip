@@ -93,10 +93,14 @@ __global__ void reset_flags_kernel(int *flags)
 // (the factors cfl and cfl_visc are inside the bounds) raises
 // kFlagStepBound.  Like dt_finalize_kernel it resets the slots; the step in
 // dt[0] is left as it was (a retry halves it).
+// One workgroup per instance (slots [instance][3][kDtSlots], step at
+// dt[8k]); with iflags (ensembles) the instance's flag gets bit 2.
 constexpr double kStepBoundFactor = 2.0;
-__global__ void step_check_kernel(unsigned long long *slots, double *dt, int *flags)
+__global__ void step_check_kernel(unsigned long long *slots_all, double *dt_all, int *flags, int *iflags)
 {
     __shared__ double s[2][kDtSlots];
+    unsigned long long *slots = slots_all + (int64_t)blockIdx.x * 3 * kDtSlots;
+    const double *dt = dt_all + 8 * (int64_t)blockIdx.x;
     const int t = threadIdx.x;
     const unsigned long long inf = 0x7FF0000000000000ull;
     for (int c = 0; c < 2; ++c) s[c][t] = __longlong_as_double((long long)slots[c * kDtSlots + t]);
@@ -107,7 +111,23 @@ __global__ void step_check_kernel(unsigned long long *slots, double *dt, int *fl
             for (int c = 0; c < 2; ++c) s[c][t] = fmin(s[c][t], s[c][t + st]);
         __syncthreads();
     }
-    if (t == 0 && dt[0] > kStepBoundFactor * fmin(s[0][0], s[1][0])) atomicOr(&flags[kFlagStepBound], 1);
+    if (t == 0 && dt[0] > kStepBoundFactor * fmin(s[0][0], s[1][0])) {
+        atomicOr(&flags[kFlagStepBound], 1);
+        if (iflags) atomicOr(&iflags[blockIdx.x], 2);
+    }
+}
+
+// Ensemble retry support: step <- f * step for the instances k with mask[k],
+// their time corrected by the removed part.
+__global__ void scale_steps_masked_kernel(double *dt_all, const int *mask, double f, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && mask[k]) {
+        double *dt = dt_all + 8 * (int64_t)k;
+        const double old = dt[0];
+        dt[0] = old * f;
+        dt[4] -= old * (1.0 - f);
+    }
 }
 
 // Retry support: step <- f * step, time corrected by the removed part.
@@ -397,7 +417,8 @@ void free_bufs(esdg_ctx *c)
     Bufs &B = c->B;
     void *ps[] = {B.x, B.y, B.xr, B.yr, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
                   B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.frec, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
-                  B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2], B.inst, B.cstart, B.cinst};
+                  B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2], B.inst, B.cstart, B.cinst,
+                  B.iflags, B.imask};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (auto &w : B.W)
@@ -1000,6 +1021,9 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
         cst.push_back(K);
         B.nchunks = (int64_t)cin.size();
         TRY(alloc(ctx, &B.inst, K * sizeof(int32_t)));
+        TRY(alloc(ctx, &B.iflags, ni * sizeof(int)));
+        TRY(alloc(ctx, &B.imask, ni * sizeof(int)));
+        CK(hipMemsetAsync(B.iflags, 0, ni * sizeof(int), ctx->stream));
         TRY(alloc(ctx, &B.cstart, cst.size() * sizeof(int64_t)));
         TRY(alloc(ctx, &B.cinst, cin.size() * sizeof(int32_t)));
         CK(hipMemcpyAsync(B.inst, inst_of.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
@@ -1197,7 +1221,7 @@ int esdg_step(esdg_ctx *ctx, int nsteps, double dt, double *t_out)
                                            Ev{});
                 }));
                 hipLaunchKernelGGL(step_check_kernel, dim3(1), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
-                                   ctx->B.dscal, ctx->B.flags);
+                                   ctx->B.dscal, ctx->B.flags, (int *)nullptr);
                 CK(hipGetLastError());
             }
             int flags[kNumFlags];
@@ -1549,6 +1573,7 @@ struct esdg_ensemble {
         hipStream_t stream = nullptr;
         std::vector<int> members;
         double *scratch = nullptr;   // [3][nodes] device copy of the union state (get_state)
+        int *hflags = nullptr;       // pinned host ints (step retries): step flags, instance flags, retry mask
     };
     int device = 0, prec = 64;
     std::vector<Inst> inst;
@@ -1674,6 +1699,7 @@ int esdg_ensemble_destroy(esdg_ensemble *en)
         if (G.stream) (void)hipStreamSynchronize(G.stream);
         if (G.ctx) esdg_destroy(G.ctx);
         if (G.scratch) (void)hipFree(G.scratch);
+        if (G.hflags) (void)hipHostFree(G.hflags);
         if (G.stream) (void)hipStreamDestroy(G.stream);
     }
     delete en;
@@ -1689,7 +1715,6 @@ int esdg_ensemble_add(esdg_ensemble *en, const esdg_params *p, int N, int64_t K,
     if (!p || !x || !y || !nbr_elem || !nbr_side || !flip || !b || !h || !hu || !hv)
         return efail(en, ESDG_EINVAL, "null pointer");
     if (N < 2 || N > kMaxN || K < 1) return efail(en, ESDG_EINVAL, "N or K out of range");
-    if (p->max_dt_retries > 0) return efail(en, ESDG_EINVAL, "dt retries need a single instance");
     for (int64_t f = 0; f < 4 * K; ++f)
         if (nbr_elem[f] < -1 || nbr_elem[f] >= K) return efail(en, ESDG_EMESH, "face map entry out of range");
     esdg_ensemble::Inst I;
@@ -1713,6 +1738,56 @@ int esdg_ensemble_build(esdg_ensemble *en)
     return ensemble_build(en);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Ensemble steps with the after-the-fact check per instance (the section 6
+// step adjustment, as esdg_step does for one instance): an instance whose
+// step met a negative element mean or exceeds twice the CFL / viscous bound
+// of its result redoes it with half its step, at most `retries` times.  W^n
+// stays untouched in its buffer, so a degree group's step is relaunched from
+// it and its instances that keep their step redo it bit for bit.  All groups
+// launch their step and its check on their own streams before the host waits
+// for any, so the degrees still overlap.
+
+// Launch one attempt of a group's step (the first by graph replay when
+// ready), its check, and the copies of the flags to the group's pinned
+// host buffer: [kNumFlags] step flags, then [ni] instance flags.
+int group_attempt(esdg_ctx *ctx, int base, bool first, int *hflags)
+{
+    const int ni = n_inst(ctx);
+    if (first) {
+        TRY(graph_ready(ctx, 0.0) ? graph_step(ctx, 0.0) : launch_one_step(ctx, 0.0));
+    } else {
+        ctx->cur = base;
+        TRY(launch_one_step(ctx, 0.0, false));
+    }
+    TRY(dispatch(ctx, [&](auto L, auto r) {
+        using R = decltype(r);
+        return decltype(L)::dt(ctx->B, ctx->cur, ctx->P.av_on != 0, true, phys<R>(ctx), ctx->stream, Ev{});
+    }));
+    hipLaunchKernelGGL(step_check_kernel, dim3((unsigned)ni), dim3(kDtSlots), 0, ctx->stream, ctx->B.slots,
+                       ctx->B.dscal, ctx->B.flags, ctx->B.iflags);
+    CK(hipGetLastError());
+    CK(hipMemcpyAsync(hflags, ctx->B.flags, kNumFlags * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(hflags + kNumFlags, ctx->B.iflags, ni * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    return ESDG_OK;
+}
+
+int clear_step_flags(esdg_ctx *ctx)
+{
+    const int ni = n_inst(ctx);
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0, ctx->stream,
+                       ctx->B.iflags, 0, ni);
+    CK(hipGetLastError());
+    return reset_flags(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
 int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
 {
     if (!en) return ESDG_EINVAL;
@@ -1724,20 +1799,82 @@ int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
         if (st) return efail_ctx(en, G.ctx, st);
     }
     // interleave the degrees step by step; each degree's launches are
-    // ordered on its own stream
-    for (int it = 0; it < nsteps; ++it)
-        for (auto &G : en->groups) {
-            const int st = graph_ready(G.ctx, 0.0) ? graph_step(G.ctx, 0.0) : launch_one_step(G.ctx, 0.0);
+    // ordered on its own stream.  Groups with step retries launch their step
+    // and its check first; then the host waits for each and relaunches the
+    // groups with instances to redo, until none is left.
+    bool negmean = false;
+    const size_t ng = en->groups.size();
+    std::vector<int> base(ng);
+    std::vector<std::vector<int>> tries(ng);
+    for (size_t g = 0; g < ng; ++g) {
+        auto &G = en->groups[g];
+        if (G.ctx->P.max_dt_retries > 0 && !G.hflags) {
+            const size_t nb = (kNumFlags + 2 * (size_t)n_inst(G.ctx)) * sizeof(int);
+            if (hipHostMalloc((void **)&G.hflags, nb, hipHostMallocDefault) != hipSuccess)
+                return efail(en, ESDG_ENOMEM, "hipHostMalloc failed");
+        }
+    }
+    for (int it = 0; it < nsteps; ++it) {
+        std::vector<size_t> pending;
+        for (size_t g = 0; g < ng; ++g) {
+            auto &G = en->groups[g];
+            int st;
+            if (G.ctx->P.max_dt_retries > 0) {
+                base[g] = G.ctx->cur;
+                tries[g].assign(n_inst(G.ctx), 0);
+                st = clear_step_flags(G.ctx);
+                if (!st) st = group_attempt(G.ctx, base[g], true, G.hflags);
+                pending.push_back(g);
+            } else {
+                st = graph_ready(G.ctx, 0.0) ? graph_step(G.ctx, 0.0) : launch_one_step(G.ctx, 0.0);
+            }
             if (st) return efail_ctx(en, G.ctx, st);
         }
-    int status = ESDG_OK;
+        while (!pending.empty()) {
+            std::vector<size_t> again;
+            for (size_t g : pending) {
+                auto &G = en->groups[g];
+                esdg_ctx *c = G.ctx;
+                if (hipStreamSynchronize(c->stream) != hipSuccess)
+                    return efail(en, ESDG_EHIP, "hipStreamSynchronize failed");
+                const int ni = n_inst(c);
+                const int *fl = G.hflags, *ifl = G.hflags + kNumFlags;
+                int *mask = G.hflags + kNumFlags + ni;
+                if (fl[kFlagNonFinite]) return efail(en, ESDG_ENONFINITE, "non-finite value in a stage output");
+                if (fl[kFlagDtPos]) return efail(en, ESDG_EDTPOS, "no admissible time step");
+                bool any = false;
+                for (int k = 0; k < ni; ++k) {
+                    mask[k] = (ifl[k] != 0 && tries[g][k] < c->P.max_dt_retries) ? 1 : 0;
+                    any = any || mask[k];
+                }
+                if (!any) {
+                    for (int k = 0; k < ni; ++k)
+                        if (ifl[k] & 1) negmean = true;
+                    continue;
+                }
+                for (int k = 0; k < ni; ++k) tries[g][k] += mask[k];
+                int st = ESDG_OK;
+                if (hipMemcpyAsync(c->B.imask, mask, ni * sizeof(int), hipMemcpyHostToDevice, c->stream) !=
+                    hipSuccess)
+                    return efail(en, ESDG_EHIP, "hipMemcpyAsync failed");
+                hipLaunchKernelGGL(scale_steps_masked_kernel, dim3((unsigned)((ni + 255) / 256)), dim3(256), 0,
+                                   c->stream, c->B.dscal, c->B.imask, 0.5, ni);
+                st = clear_step_flags(c);
+                if (!st) st = group_attempt(c, base[g], false, G.hflags);
+                if (st) return efail_ctx(en, c, st);
+                again.push_back(g);
+            }
+            pending.swap(again);
+        }
+    }
+    int status = negmean ? ESDG_ENEGMEAN : ESDG_OK;
     for (auto &G : en->groups) {
         int flags[kNumFlags];
         const int st = read_flags(G.ctx, flags);
         if (st) return efail_ctx(en, G.ctx, st);
         if (flags[kFlagNonFinite]) return efail(en, ESDG_ENONFINITE, "non-finite value in a stage output");
         if (flags[kFlagDtPos]) return efail(en, ESDG_EDTPOS, "no admissible time step");
-        if (flags[kFlagNegMean]) status = ESDG_ENEGMEAN;
+        if (flags[kFlagNegMean] && G.ctx->P.max_dt_retries <= 0) status = ESDG_ENEGMEAN;
     }
     if (status) return efail(en, status, "negative element mean in the limiter");
     return ESDG_OK;

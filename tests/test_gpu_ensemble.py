@@ -116,9 +116,6 @@ def test_ensemble_against_oracle(esdg, orc):
 def test_ensemble_argument_errors(esdg):
     w = dam_break(3, 3, seed=1)
     ens = esdg.Ensemble(0, 64)
-    with pytest.raises(esdg.EsdgError) as ei:
-        ens.add_workload(w, max_dt_retries=2)
-    assert ei.value.code == esdg.EINVAL
     ens.add_workload(w, eps0=0.05)
     ens.add_workload(dam_break(4, 3, seed=2), eps0=0.025)   # same degree, other parameters
     with pytest.raises(esdg.EsdgError) as ei:
@@ -219,3 +216,38 @@ def test_adaptive_step_check_against_oracle(esdg, orc, integrator, cfl, halvings
         assert np.array_equal(got[c], direct[c])
     for g_, o_ in zip(got + got3, (h, hu, hv, h3, hu3, hv3)):
         assert np.abs(g_ - o_).max() <= 1e-9 * max(1.0, np.abs(o_).max())
+
+
+def test_ensemble_step_retries_equal_single_solves(esdg):
+    """Ensembles take the step check per instance: with SSPRK(3,3) and three
+    retries, the dam break at rest redoes its first step at half the size
+    (its result outruns its own CFL bound) while the other instances keep
+    theirs; the degree group's step is relaunched from W^n, so every
+    instance equals its single solve with the same retries bitwise, time
+    included, over several steps and two degree groups."""
+    kw = dict(av_on=1, limiter_on=1, eps0=0.05, integrator=1, max_dt_retries=3)
+    ws = [dam_break(6, 3, seed=4, rotate_seed=3), smooth_sweep(4, 3, seed=21), dam_break(5, 3, seed=22),
+          dam_break(4, 5, seed=23, rotate_seed=1), smooth_sweep(3, 5, seed=24)]
+    ens = esdg.Ensemble(0, 64)
+    ids = [ens.add_workload(w, **kw) for w in ws]
+    ens.step(1, raise_negmean=False)
+    t1 = [ens.get_time(i) for i in ids]
+    ens.step(3, raise_negmean=False)
+    for w, i, t in zip(ws, ids, t1):
+        ref1, r1 = single(esdg, w, 1, **kw)
+        assert t == r1
+        ref, t_ref = single(esdg, w, 4, **kw)
+        got = ens.get_state(i)
+        for c in range(3):
+            assert np.array_equal(got[c], ref[c]), (i, w.mesh.N, c, np.abs(got[c] - ref[c]).max())
+        assert ens.get_time(i) == t_ref
+    # the first instance's first step was halved: against its own bound at the start
+    s = esdg.Solver(0, 64)
+    s.upload_mesh(ws[0].mesh)
+    s.set_params(esdg.default_params(3, **kw))
+    s.set_bathymetry(ws[0].b)
+    s.set_state(ws[0].h, ws[0].hu, ws[0].hv)
+    dt0 = s.compute_dt()[0]
+    s.close()
+    assert t1[0] == pytest.approx(dt0 / 2, rel=1e-14)
+    ens.close()
