@@ -282,10 +282,10 @@ int esdg_profile_read_kernels(esdg_ctx *ctx, double ms[6], int64_t launches[6]);
  * columns instead (no more LDS).
  * esdg_autotune times reps launches of each on the context's mesh and
  * current state, twice, in the form the integrator uses (an interior
- * LSRK(5,4) stage, which reads and writes the LSRK register, or an SSPRK(3,3)
- * stage).  Trial stages write a scratch state buffer and, for LSRK, the
- * register, whose content is not used across steps; the state and the time
- * are unchanged, and esdg_profile does not count them.  esdg_autotune keeps
+ * LSRK(5,4) stage, which reads the LSRK register, or an SSPRK(3,3) stage).
+ * Trial stages write only a scratch state buffer: the state, the LSRK
+ * register and the time are unchanged, and esdg_profile does not count
+ * them.  esdg_autotune keeps
  * the fastest for all later launches and returns the
  * choice and the mean launch times in ms, ms[0..ESDG_STAGE_VARIANTS-1]
  * (either output may be NULL).  esdg_set_stage_variant sets the choice

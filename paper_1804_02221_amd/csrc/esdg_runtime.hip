@@ -1380,9 +1380,9 @@ int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[ESDG_STAGE_VAR
     if (av) TRY(launch_viscous(ctx, base, -1));
     // trial stages in the integrator's own form, W^n -> o1, each variant timed
     // over reps launches, twice, alternating: for LSRK(5,4) an interior stage
-    // (it reads and writes the register dU, as stages 2-4 do; between steps
-    // dU is dead, the first stage has a_1 = 0), for SSPRK(3,3) an SSP stage
-    // (W^n untouched)
+    // that reads the register dU (as stages 2-5 do) but does not write it --
+    // repeated in place, d <- a_3 d + dt R with |a_3| > 1 would grow without
+    // bound -- for SSPRK(3,3) an SSP stage (W^n untouched)
     const bool ssp = ctx->P.integrator == 1;
     if (!ctx->tune_ev[0]) {
         CK(hipEventCreate(&ctx->tune_ev[0]));
@@ -1403,7 +1403,7 @@ int esdg_autotune(esdg_ctx *ctx, int reps, int *choice, double ms[ESDG_STAGE_VAR
                 hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.count + o1, 0, 1);
                 StageCall sc = ssp ? StageCall{kModeSsp, av, base, o1, base, false, 0.0, 1.0, false, false, v}
                                    : StageCall{kModeLsrk, av, base, o1, base, false, kLsrkA[2], kLsrkB[2], false,
-                                               true, v};
+                                               false, v};
                 const int st = launch_stage(ctx, sc);
                 if (st) {
                     ctx->stage_variant = keep;
