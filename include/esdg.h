@@ -40,11 +40,13 @@
  *    are asynchronous on the context stream; host-pointer transfers return
  *    after the data has arrived.
  *  - The ABI is float64 everywhere.  A precision-32 context converts on
- *    upload/download and computes in float32; its volume and interface
- *    terms are formed from jumps to the own node (the two-point sums less
- *    the own flux), so that its right-hand side is limited by the FP32
- *    rounding of the stored state and metric terms rather than by
- *    cancellation in the flux differencing.
+ *    upload/download and computes in float32 (the bathymetry is taken in
+ *    float64; its derivatives and face values are rounded); its volume,
+ *    interface and viscous terms are formed from jumps to the own node (the
+ *    two-point sums less the own flux), and each element's metric terms are
+ *    stored relative to those of its middle node, so that its right-hand
+ *    side is limited by the FP32 rounding of the stored state rather than
+ *    by cancellation in the flux differencing.
  *  - Return value: ESDG_OK or a negative esdg_status; esdg_last_error()
  *    describes the last failure of a context.  No entry point throws.
  *  - A context is not thread-safe; use one per host thread.

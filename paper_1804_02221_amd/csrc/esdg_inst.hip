@@ -25,6 +25,7 @@ static Mesh<R> mesh_view(const Bufs &B)
     m.Ce = (const R *)B.Ce;
     m.bx = (const R *)B.bx;
     m.by = (const R *)B.by;
+    m.mref = (const R *)B.mref;
     m.xr = B.xr;
     m.yr = B.yr;
     m.bface = (const R *)B.bface;
@@ -70,7 +71,7 @@ hipError_t Launch<N, R>::geometry(const Bufs &B, const Tab<double> &td, hipStrea
     const int64_t n = B.K * np;
     const int bs = 256;
     hipLaunchKernelGGL((geometry_kernel<N, R>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, B.K,
-                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, B.xr, B.yr, B.flags + kFlagBadJ,
+                       B.x, B.y, (R *)B.Ax, (R *)B.Cx, (R *)B.Ae, (R *)B.Ce, (R *)B.mref, B.xr, B.yr, B.flags + kFlagBadJ,
                        td);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

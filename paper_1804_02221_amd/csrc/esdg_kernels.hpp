@@ -70,8 +70,10 @@ struct TileShape {
 //      node (the paper's LDS padding, appendix C), or at N = 7 XOR-swizzled
 //      columns (no more LDS; StageCfg::SWZ).
 // Default register budget in the FP64 update modes: six waves per SIMD at
-// N = 6, five otherwise (N = 7 reaches six by its partner-loop unroll); no
-// constraint in FP32 and in the right-hand-side mode.  Default unroll: fully,
+// N = 6, five otherwise (N = 7 reaches six by its partner-loop unroll); in
+// the FP32 update modes eight (seven for variant 2, none for variant 1): left
+// free, the compiler gave some FP32 variants 100-120 registers; no
+// constraint in the right-hand-side mode.  Default unroll: fully,
 // except at N = 7 with one-wave tiles (by two: 79 VGPRs and six waves per
 // SIMD instead of five), N = 6 (by two) and N = 8 (by three: five waves).
 constexpr int kStageVariants = 5;
@@ -105,7 +107,8 @@ __device__ __forceinline__ int stage_col(int i, int j)
 
 template <int N, typename R, int MODE, int V>
 struct StageWaves {
-    static constexpr int value = (sizeof(R) == 8 && MODE != 0) ? StageCfg<N, V>::waves : 1;
+    static constexpr int value =
+        MODE == 0 ? 1 : (sizeof(R) == 8 ? StageCfg<N, V>::waves : (V == 1 ? 1 : (V == 2 ? 7 : 8)));
 };
 
 // Workgroup barrier for exchanges through LDS only: orders LDS accesses
@@ -168,11 +171,34 @@ struct Mesh {
     const R *Ae, *Ce;   // J grad(eta) = (-y_xi,   x_xi)   [K][np]
     const R *bx, *by;   // split-form bathymetry derivatives (eq. SourceDisc)
     const double *xr, *yr;  // float64 coordinates less the element's first node [K][np] (float64 contexts)
+    const R *mref;      // float32 contexts: [K][4] (Ax, Cx, Ae, Ce) of each element's middle node
     const R *bface;     // bathymetry on the faces [K][4][nf]
     const int32_t *nbr; // [K][4] neighbour element
     const int8_t *code; // [K][4] neighbour side | flip << 2 | wall << 3 (a wall names the element itself)
     int walls;          // some side is a wall (else the wall bit is never looked at)
 };
+
+// Single precision stores the metric terms of each node less those of its
+// element's middle node (Mesh::mref): differences between an element's
+// nodes, which the jump-form volume sums take, are then rounded at the size
+// of the terms' variation across the element rather than of the terms.  On a
+// fine mesh the terms vary little across an element, and their rounding at
+// full size breaks the discrete metric identities by far more than the
+// arithmetic's own rounding.  The terms themselves are the sums.
+template <typename R>
+constexpr bool kMetricRel = sizeof(R) == 4;
+
+// Metric terms J grad(xi) = (Ax, Cx), J grad(eta) = (Ae, Ce) at node q of
+// element e.
+template <typename R>
+__device__ __forceinline__ void metric_at(const Mesh<R> &m, int64_t q, int64_t e, R &Ax, R &Cx, R &Ae, R &Ce)
+{
+    Ax = m.Ax[q]; Cx = m.Cx[q]; Ae = m.Ae[q]; Ce = m.Ce[q];
+    if constexpr (kMetricRel<R>) {
+        const R *r = m.mref + 4 * e;
+        Ax += r[0]; Cx += r[1]; Ae += r[2]; Ce += r[3];
+    }
+}
 
 template <typename R>
 struct Phys {
@@ -340,7 +366,8 @@ __device__ __forceinline__ void interface_flux_delta(R hm, R um, R vm, R bm, R h
 // ------------------------------------------------------------------------
 template <int N, typename R>
 __global__ void geometry_kernel(int64_t K, const double *__restrict__ x, const double *__restrict__ y,
-                                R *Ax, R *Cx, R *Ae, R *Ce, double *xr, double *yr, int *bad, Tab<double> tab)
+                                R *Ax, R *Cx, R *Ae, R *Ce, R *mref, double *xr, double *yr, int *bad,
+                                Tab<double> tab)
 {
     constexpr int nf = N + 1, np = nf * nf;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -368,10 +395,35 @@ __global__ void geometry_kernel(int64_t K, const double *__restrict__ x, const d
         xr[q] = xe[p] - x0;
         yr[q] = ye[p] - y0;
     }
-    Ax[q] = (R)yeta;
-    Cx[q] = (R)(-xeta);
-    Ae[q] = (R)(-yxi);
-    Ce[q] = (R)xxi;
+    if constexpr (kMetricRel<R>) {
+        // the middle node's terms by the same sums, rounded, and each node's
+        // terms less them (kMetricRel)
+        constexpr int c = N / 2;
+        double cxxi = 0, cxeta = 0, cyxi = 0, cyeta = 0;
+#pragma unroll
+        for (int m = 0; m < nf; ++m) {
+            cxxi += tab.D[c * kMaxNF + m] * (xe[m * nf + c] - x0);
+            cyxi += tab.D[c * kMaxNF + m] * (ye[m * nf + c] - y0);
+            cxeta += tab.D[c * kMaxNF + m] * (xe[c * nf + m] - x0);
+            cyeta += tab.D[c * kMaxNF + m] * (ye[c * nf + m] - y0);
+        }
+        const R r0 = (R)cyeta, r1 = (R)(-cxeta), r2 = (R)(-cyxi), r3 = (R)cxxi;
+        if (p == 0) {
+            mref[4 * e + 0] = r0;
+            mref[4 * e + 1] = r1;
+            mref[4 * e + 2] = r2;
+            mref[4 * e + 3] = r3;
+        }
+        Ax[q] = (R)(yeta - (double)r0);
+        Cx[q] = (R)(-xeta - (double)r1);
+        Ae[q] = (R)(-yxi - (double)r2);
+        Ce[q] = (R)(xxi - (double)r3);
+    } else {
+        Ax[q] = (R)yeta;
+        Cx[q] = (R)(-xeta);
+        Ae[q] = (R)(-yxi);
+        Ce[q] = (R)xxi;
+    }
 }
 
 // Split-form bathymetry derivatives (eq. SourceDisc, read with D) and face
@@ -714,13 +766,18 @@ __device__ __forceinline__ void viscous_flux_at(int i, int j, const R *su, const
     constexpr int nf = N + 1;
     const R u0 = su[i * nf + j], v0 = sv[i * nf + j];
     R dxu = 0, dxv = 0, deu = 0, dev = 0;
+    // single precision: the sums over the jumps from the node's own values
+    // (D's rows sum to zero), so that neither the rounding of the table's
+    // row sums nor that of products at the size of the values themselves
+    // enters the derivatives (kJumpForm)
+    const R ou = kJumpForm<R> ? u0 : R(0), ov = kJumpForm<R> ? v0 : R(0);
 #pragma unroll
     for (int m = 0; m < nf; ++m) {
         const R di = tab.D[i * kMaxNF + m], dj = tab.D[j * kMaxNF + m];
-        dxu += di * su[m * nf + j];
-        dxv += di * sv[m * nf + j];
-        deu += dj * su[i * nf + m];
-        dev += dj * sv[i * nf + m];
+        dxu += di * (su[m * nf + j] - ou);
+        dxv += di * (sv[m * nf + j] - ov);
+        deu += dj * (su[i * nf + m] - ou);
+        dev += dj * (sv[i * nf + m] - ov);
     }
     const R iw = tab.iw0;
     // BR1 lift (U* - u)/w on the faces the node lies on
@@ -864,10 +921,11 @@ __global__ __launch_bounds__(Shape<N>::T) void av_faces_kernel(ListArgs<N, R> a)
             side_node<N>(s, k, fi, fj);
             const int lp = fel * np + fi * nf + fj;
             const int64_t qo = fe * np + fi * nf + fj;
-            R Fv2, Fv3, Gv2, Gv3;
+            R Fv2, Fv3, Gv2, Gv3, oAx, oCx, oAe, oCe;
+            metric_at(a.m, qo, fe, oAx, oCx, oAe, oCe);
             viscous_flux_at<N, R>(fi, fj, s_u + fel * np, s_v + fel * np, s_us + fel * 4 * nf,
-                                  s_vs + fel * 4 * nf, a.m.Ax[qo], a.m.Cx[qo], a.m.Ae[qo], a.m.Ce[qo],
-                                  s_h[lp] * a.eps[fe], *a.tg, Fv2, Fv3, Gv2, Gv3);
+                                  s_vs + fel * 4 * nf, oAx, oCx, oAe, oCe, s_h[lp] * a.eps[fe], *a.tg, Fv2, Fv3,
+                                  Gv2, Gv3);
             R *o = a.vtr + ((fe * 4 + s) * nf + k) * 4;
             o[0] = Fv2;
             o[1] = Fv3;
@@ -919,7 +977,7 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
         }
         R Ax = 0, Cx = 0, Ae = 0, Ce = 0, Fv2 = 0, Fv3 = 0, Gv2 = 0, Gv3 = 0;
         if (act) {
-            Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
+            metric_at(a.m, q, e, Ax, Cx, Ae, Ce);
             viscous_flux_at<N, R>(i, j, s_u + el * np, s_v + el * np, s_us + el * 4 * nf, s_vs + el * 4 * nf,
                                   Ax, Cx, Ae, Ce, h * a.eps[e], *a.tg, Fv2, Fv3, Gv2, Gv3);
         }
@@ -932,11 +990,15 @@ __global__ __launch_bounds__(Shape<N>::T) void av_div_kernel(ListArgs<N, R> a)
         if (act) {
             R Lv2 = 0, Lv3 = 0;
             const int base = el * np;
+            // (single precision: over the jumps from the own fluxes, as in
+            // viscous_flux_at)
+            const R o0 = kJumpForm<R> ? s_Fv[0][t] : R(0), o1 = kJumpForm<R> ? s_Fv[1][t] : R(0);
+            const R o2 = kJumpForm<R> ? s_Fv[2][t] : R(0), o3 = kJumpForm<R> ? s_Fv[3][t] : R(0);
 #pragma unroll
             for (int mm = 0; mm < nf; ++mm) {
                 const R di = a.tg->D[i * kMaxNF + mm], dj = a.tg->D[j * kMaxNF + mm];
-                Lv2 += di * s_Fv[0][base + mm * nf + j] + dj * s_Fv[2][base + i * nf + mm];
-                Lv3 += di * s_Fv[1][base + mm * nf + j] + dj * s_Fv[3][base + i * nf + mm];
+                Lv2 += di * (s_Fv[0][base + mm * nf + j] - o0) + dj * (s_Fv[2][base + i * nf + mm] - o2);
+                Lv3 += di * (s_Fv[1][base + mm * nf + j] - o1) + dj * (s_Fv[3][base + i * nf + mm] - o3);
             }
             // faces: (1/(2 w_0)) n_s . (Fv_nbr - Fv_own), n_s outward scaled normal
             const R hw = R(0.5) * a.tab.iw0;
@@ -1078,6 +1140,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     __shared__ R s_lim[4 * E];
     __shared__ R s_vinv[nf * nf];       // V^{-1} for the indicator epilogue (with AV)
     __shared__ R s_dz[nf * nf];         // D with a zero diagonal (volume term)
+    __shared__ R s_mref[kMetricRel<R> ? 4 * E : 1];  // the tile elements' Mesh::mref (single precision)
 
     const int64_t tile = xcd_tile(a.ntiles);
     if (tile < 0) return;
@@ -1100,6 +1163,16 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             xr = a.m.xr[q]; yr = a.m.yr[q];
         } else {
             Ax = a.m.Ax[q]; Cx = a.m.Cx[q]; Ae = a.m.Ae[q]; Ce = a.m.Ce[q];
+        }
+    }
+    // single precision: the stored terms are relative to the element's
+    // middle node (kMetricRel); staged and held as they are until the volume
+    // sums, the element's reference in LDS (s_mref)
+    if constexpr (kMetricRel<R>) {
+        if (act && p == 0) {
+            const R *r = a.m.mref + 4 * e;
+            s_mref[4 * el + 0] = r[0]; s_mref[4 * el + 1] = r[1];
+            s_mref[4 * el + 2] = r[2]; s_mref[4 * el + 3] = r[3];
         }
     }
     // The face slots' neighbour traces and face bathymetry are loaded here,
@@ -1169,7 +1242,11 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             side_node<N>(ns, kk, ni, nj);
             const int64_t qn = en * np + ni * nf + nj;
             // outward scaled normal: +-J grad(xi) on xi = +-1, +-J grad(eta) on eta = +-1
-            const V2 dir = (s & 1) ? s_a[lp] : s_b[lp];
+            V2 dir = (s & 1) ? s_a[lp] : s_b[lp];
+            if constexpr (kMetricRel<R>) {
+                dir.x += s_mref[4 * fel + ((s & 1) ? 0 : 2)];
+                dir.y += s_mref[4 * fel + ((s & 1) ? 1 : 3)];
+            }
             const R sg = (s == 0 || s == 3) ? R(-1) : R(1);
             const R snx = sg * dir.x, sny = sg * dir.y;
             const R js = sqrt(snx * snx + sny * sny);
@@ -1245,8 +1322,13 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         // own-flux parts the face slots subtract (interface_flux_delta).
         const int base = el * PS;
         constexpr int VU = StageCfg<N, V>::VU;
+        // (the staged and own terms are relative to the element's middle
+        // node: the jumps from the own relative terms, t from the absolute
+        // ones, the sums from the own plus twice the reference)
+        const R *const mr = s_mref + 4 * el;
         {
-            const R tA = R(2) * Ax, tC = R(2) * Cx;
+            const R tA = R(2) * (Ax + mr[0]), tC = R(2) * (Cx + mr[1]);
+            const R pA = Ax + R(2) * mr[0], pC = Cx + R(2) * mr[1];
 #pragma unroll VU
             for (int mm = 0; mm < nf; ++mm) {
                 const int qq = base + mm * RS + stage_col<N, V>(mm, j);
@@ -1255,7 +1337,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
                 const R hm = s_h[qq];
                 const R dA = am.x - Ax, dC = am.y - Cx, dh = hm - h;
                 const R s1 = hu + qm.x, s2 = hv + qm.y;
-                const R F1 = s1 * (Ax + am.x) + s2 * (Cx + am.y);
+                const R F1 = s1 * (pA + am.x) + s2 * (pC + am.y);
                 const R dF1 = s1 * dA + s2 * dC + tA * (qm.x - hu) + tC * (qm.y - hv);
                 const R dF = d * F1;
                 A1 += d * dF1;
@@ -1266,7 +1348,8 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
             }
         }
         {
-            const R tA = R(2) * Ae, tC = R(2) * Ce;
+            const R tA = R(2) * (Ae + mr[2]), tC = R(2) * (Ce + mr[3]);
+            const R pA = Ae + R(2) * mr[2], pC = Ce + R(2) * mr[3];
 #pragma unroll VU
             for (int mm = 0; mm < nf; ++mm) {
                 const int qq = base + i * RS + stage_col<N, V>(i, mm);
@@ -1275,7 +1358,7 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
                 const R hm = s_h[qq];
                 const R dA = bm.x - Ae, dC = bm.y - Ce, dh = hm - h;
                 const R s1 = hu + qm.x, s2 = hv + qm.y;
-                const R F1 = s1 * (Ae + bm.x) + s2 * (Ce + bm.y);
+                const R F1 = s1 * (pA + bm.x) + s2 * (pC + bm.y);
                 const R dF1 = s1 * dA + s2 * dC + tA * (qm.x - hu) + tC * (qm.y - hv);
                 const R dF = d * F1;
                 A1 += d * dF1;
@@ -1330,6 +1413,11 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
         if (i == N) { L1 += s_fl[0][fb + 1 * nf + j]; L2 += s_fl[1][fb + 1 * nf + j]; L3 += s_fl[2][fb + 1 * nf + j]; }
         if (j == N) { L1 += s_fl[0][fb + 2 * nf + i]; L2 += s_fl[1][fb + 2 * nf + i]; L3 += s_fl[2][fb + 2 * nf + i]; }
         if (i == 0) { L1 += s_fl[0][fb + 3 * nf + j]; L2 += s_fl[1][fb + 3 * nf + j]; L3 += s_fl[2][fb + 3 * nf + j]; }
+    }
+    if constexpr (kMetricRel<R>) {
+        // the own terms absolute from here on
+        const R *const mr = s_mref + 4 * el;
+        Ax += mr[0]; Cx += mr[1]; Ae += mr[2]; Ce += mr[3];
     }
     const R J = Ce * Ax - Cx * Ae;
 
@@ -1473,7 +1561,9 @@ __global__ __launch_bounds__(Shape<N>::T) void limit_kernel(Mesh<R> m, Phys<R> P
     R nh = 0, nhu = 0, nhv = 0, J = 0;
     if (act) {
         nh = h_[q]; nhu = hu_[q]; nhv = hv_[q];
-        J = m.Ce[q] * m.Ax[q] - m.Cx[q] * m.Ae[q];
+        R Ax, Cx, Ae, Ce;
+        metric_at(m, q, e, Ax, Cx, Ae, Ce);
+        J = Ce * Ax - Cx * Ae;
     }
     const R wq = act ? J * tab.w[i] * tab.w[j] : R(0);
     R vals[5] = {wq, wq * nh, wq * nhu, wq * nhv, act ? nh : R(3.0e38)};
@@ -1560,7 +1650,8 @@ __global__ void gmax_kernel(Mesh<R> m, R *gmax)
     R gm = R(0);
     for (int p = 0; p < np; ++p) {
         const int64_t q = e * np + p;
-        const R Ax = m.Ax[q], Cx = m.Cx[q], Ae = m.Ae[q], Ce = m.Ce[q];
+        R Ax, Cx, Ae, Ce;
+        metric_at(m, q, e, Ax, Cx, Ae, Ce);
         const R J = Ce * Ax - Cx * Ae;
         const R gg = (Ax * Ax + Cx * Cx + Ae * Ae + Ce * Ce) / (J * J);
         gm = gg > gm ? gg : gm;
@@ -1581,7 +1672,8 @@ __global__ void face_geometry_kernel(Mesh<R> m, R w0, R *fgeo)
     int i, j;
     side_node<N>(s, k, i, j);
     const int64_t q = e * np + i * nf + j;
-    const R Ax = m.Ax[q], Cx = m.Cx[q], Ae = m.Ae[q], Ce = m.Ce[q];
+    R Ax, Cx, Ae, Ce;
+    metric_at(m, q, e, Ax, Cx, Ae, Ce);
     R snx, sny;
     if (s == 1) { snx = Ax; sny = Cx; }
     else if (s == 3) { snx = -Ax; sny = -Cx; }
@@ -1697,7 +1789,8 @@ __device__ __forceinline__ R lemma2_min(const DtArgs<R> &a, XcdRange r)
 template <int N, typename R>
 __device__ __forceinline__ R cfl_node(const DtArgs<R> &a, int64_t q)
 {
-    const R Ax = a.m.Ax[q], Cx = a.m.Cx[q], Ae = a.m.Ae[q], Ce = a.m.Ce[q];
+    R Ax, Cx, Ae, Ce;
+    metric_at(a.m, q, q / ((N + 1) * (N + 1)), Ax, Cx, Ae, Ce);
     return cfl_bound<N, R>(a.h[q], a.hu[q], a.hv[q], Ax, Cx, Ae, Ce, Ce * Ax - Cx * Ae, a.P);
 }
 
@@ -1828,7 +1921,9 @@ __global__ __launch_bounds__(Shape<N>::T) void diag_kernel(Mesh<R> m, Phys<R> P,
     double v[8] = {0, 0, 0, 0, 0, 1e300, -1e300, 0};
     if (q < m.K * np) {
         const int p = (int)(q % np), i = p / nf, j = p - i * nf;
-        const double J = (double)m.Ce[q] * m.Ax[q] - (double)m.Cx[q] * m.Ae[q];
+        R Ax, Cx, Ae, Ce;
+        metric_at(m, q, q / np, Ax, Cx, Ae, Ce);
+        const double J = (double)Ce * Ax - (double)Cx * Ae;
         const double wq = J * tab.w[i] * tab.w[j];
         const double h = h_[q], hu = hu_[q], hv = hv_[q], b = b_[q];
         const double ih = h > P.h_tol ? 1.0 / h : 0.0;

@@ -16,6 +16,7 @@ struct Bufs {
     double *x = nullptr, *y = nullptr;      // float64 coordinates
     double *xr = nullptr, *yr = nullptr;    // the same less each element's first node (float64 contexts)
     void *Ax = nullptr, *Cx = nullptr, *Ae = nullptr, *Ce = nullptr;
+    void *mref = nullptr;                   // float32 contexts: [K][4] metric terms of each element's middle node
     void *bx = nullptr, *by = nullptr, *bface = nullptr, *b = nullptr;
     int32_t *nbr = nullptr;
     int8_t *code = nullptr;

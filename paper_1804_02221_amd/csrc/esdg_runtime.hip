@@ -171,7 +171,7 @@ __global__ void scatter_kernel(const A *__restrict__ src, B *__restrict__ dst, c
 
 // Metric terms in the ABI's layout and order: x_xi, x_eta, y_xi, y_eta, J (float64).
 template <typename R>
-__global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const R *Ce, double *out,
+__global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const R *Ce, const R *mref, double *out,
                                     const int32_t *perm, int64_t K, int np)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,7 +179,10 @@ __global__ void geometry_out_kernel(const R *Ax, const R *Cx, const R *Ae, const
     if (q >= n) return;
     const int64_t e = q / np;
     const int64_t o = (int64_t)perm[e] * np + (q - e * np);
-    const double ax = Ax[q], cx = Cx[q], ae = Ae[q], ce = Ce[q];
+    // (single precision: the stored terms less the element's reference)
+    R rax = Ax[q], rcx = Cx[q], rae = Ae[q], rce = Ce[q];
+    if (mref) { rax += mref[4 * e]; rcx += mref[4 * e + 1]; rae += mref[4 * e + 2]; rce += mref[4 * e + 3]; }
+    const double ax = rax, cx = rcx, ae = rae, ce = rce;
     out[o] = ce;             // x_xi
     out[n + o] = -cx;        // x_eta
     out[2 * n + o] = -ae;    // y_xi
@@ -415,7 +418,7 @@ void free_bufs(esdg_ctx *c)
     }
     ++c->graph_gen;
     Bufs &B = c->B;
-    void *ps[] = {B.x, B.y, B.xr, B.yr, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
+    void *ps[] = {B.x, B.y, B.xr, B.yr, B.mref, B.Ax, B.Cx, B.Ae, B.Ce, B.bx, B.by, B.bface, B.b, B.nbr, B.code, B.count,
                   B.vtr, B.gmax, B.dtc, B.dtv, B.fgeo, B.frec, B.tabg, B.lv[0], B.lv[1], B.dscal, B.slots, B.flags, B.part, c->stage_d,
                   B.eps[0], B.eps[1], B.eps[2], B.list[0], B.list[1], B.list[2], B.inst, B.cstart, B.cinst,
                   B.iflags, B.imask};
@@ -981,6 +984,8 @@ int upload_mesh_impl(esdg_ctx *ctx, int N, int64_t K, const double *x, const dou
     if (ctx->prec == 64) {
         TRY(alloc(ctx, &B.xr, n * sizeof(double)));
         TRY(alloc(ctx, &B.yr, n * sizeof(double)));
+    } else {
+        TRY(alloc(ctx, &B.mref, K * 4 * sizeof(float)));
     }
     void **rn[] = {&B.Ax, &B.Cx, &B.Ae, &B.Ce, &B.bx, &B.by, &B.b, &B.dU[0], &B.dU[1], &B.dU[2],
                    &B.Rb[0], &B.Rb[1], &B.Rb[2]};
@@ -1356,11 +1361,13 @@ int esdg_get_geometry(esdg_ctx *ctx, double *xxi, double *xeta, double *yxi, dou
     if (ctx->prec == 64)
         hipLaunchKernelGGL((geometry_out_kernel<double>), dim3(g), dim3(256), 0, ctx->stream,
                            (const double *)ctx->B.Ax, (const double *)ctx->B.Cx, (const double *)ctx->B.Ae,
-                           (const double *)ctx->B.Ce, ctx->stage_d, ctx->perm, ctx->K, npn);
+                           (const double *)ctx->B.Ce, (const double *)nullptr, ctx->stage_d, ctx->perm, ctx->K,
+                           npn);
     else
         hipLaunchKernelGGL((geometry_out_kernel<float>), dim3(g), dim3(256), 0, ctx->stream,
                            (const float *)ctx->B.Ax, (const float *)ctx->B.Cx, (const float *)ctx->B.Ae,
-                           (const float *)ctx->B.Ce, ctx->stage_d, ctx->perm, ctx->K, npn);
+                           (const float *)ctx->B.Ce, (const float *)ctx->B.mref, ctx->stage_d, ctx->perm, ctx->K,
+                           npn);
     CK(hipGetLastError());
     double *outs[5] = {xxi, xeta, yxi, yeta, J};
     const hipMemcpyKind k = mem ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;

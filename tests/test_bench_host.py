@@ -33,14 +33,16 @@ def test_stage_bytes_counts_each_datum_once():
 def test_stage_bytes_low_degree_fp64_reads_coordinates():
     """In FP64 at N <= 4 the stage kernel forms the metric terms from two
     coordinates per node instead of reading four metric terms; FP32 and
-    N >= 5 read the four."""
+    N >= 5 read the four, FP32 also the four of each element's middle node
+    (the stored ones are relative to them)."""
     K = 3
     for N in (2, 3, 4, 5, 8):
         npn = (N + 1) ** 2
-        for rb, geo in ((8, 2 if N <= 4 else 4), (4, 4)):
-            want = ((3 + 3 + geo + 2 + 3 + 3) * npn * K + (4 * (N + 1) + 1) * K) * rb
+        for rb, geo, geo_e in ((8, 2 if N <= 4 else 4, 0), (4, 4, 4)):
+            per_elem = 4 * (N + 1) + geo_e + 1
+            want = ((3 + 3 + geo + 2 + 3 + 3) * npn * K + per_elem * K) * rb
             assert bench.stage_bytes(N, K, True, rb, 2) == want
-            assert bench.rhs_bytes(N, K, True, rb) == ((3 + geo + 2 + 3) * npn * K + (4 * (N + 1) + 1) * K) * rb
+            assert bench.rhs_bytes(N, K, True, rb) == ((3 + geo + 2 + 3) * npn * K + per_elem * K) * rb
 
 
 def test_dt_pass_bytes():

@@ -373,6 +373,42 @@ def test_fp32_variant(esdg, orc, N):
         assert err <= TOL32 * mx
 
 
+@pytest.mark.parametrize("av", ["off", "on"])
+@pytest.mark.parametrize("N", [3, 7])
+def test_fp32_fine_curvilinear_mesh(esdg, orc, N, av):
+    """The throughput recipe at 256 x 256 curvilinear elements (a quarter
+    of the benchmark's element size): the FP32 R against the FP64 oracle on
+    the FP32-rounded state and bathymetry within 1e-5 of max |R| per field
+    (measured 3e-7 to 3.3e-6).  On elements this small the metric terms vary
+    little across an element; rounded at their own size they would move R by
+    some 1e-4 of max |R| (the discrete metric identities the volume sums rely
+    on would hold only to that rounding), stored relative to each element's
+    middle node they are rounded at the size of their variation.  AV off, or
+    on with the benchmark's parameters (no element of this smooth state gets
+    viscosity, on either side).  With every element at eps0 the viscous term,
+    a second derivative of the velocity, turns the FP32 rounding of u = hu/h
+    into errors growing like 1 / element size^2: up to 5% of the viscous term
+    at element corners here (4e-4 of max |R|), 0.3% at 64 x 64; that case is
+    left to the coarse meshes of the tests below."""
+    w = smooth_sweep(256, N, seed=3)
+    b, h, hu, hv = _f32(w.b), _f32(w.h), _f32(w.hu), _f32(w.hv)
+    kw = dict(av_on=0) if av == "off" else dict(av_on=1, eps0=0.025)
+    s = esdg.Solver(0, 32)
+    s.upload_mesh(w.mesh)
+    P = esdg.default_params(N, limiter_on=1, **kw)
+    s.set_params(P)
+    s.set_bathymetry(b)
+    s.set_state(h, hu, hv)
+    got = s.rhs()
+    s.close()
+    Ro = orc.rhs(oparams(orc, P), w.mesh, b, h, hu, hv)
+    for c in range(3):
+        mx = np.abs(Ro[c]).max()
+        rel = np.abs(got[c] - Ro[c]).max() / mx
+        print(f"[parity] fp32 256x256 N={N} av={av} field {c}: err/max {rel:.2e}", flush=True)
+        assert rel <= TOL32
+
+
 @pytest.mark.parametrize("av", ["off", "saturated"])
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8])
 def test_fp32_arithmetic(esdg, orc, N, av):
