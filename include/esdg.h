@@ -328,9 +328,10 @@ int esdg_abi_version(void);
  * parameters.  With max_dt_retries > 0 every instance takes the step check
  * of esdg_step on its own: an instance whose step met a negative element
  * mean or exceeds twice the CFL / viscous bound of its result redoes it with
- * half its step; the degree group's step is relaunched from W^n, and the
- * other instances redo theirs bit for bit (each degree group then waits for
- * its step's checks, one host synchronisation per step).
+ * half its step; the degree group's step is relaunched from W^n for the
+ * instances to redo only (the others keep their step's results, the same
+ * bit for bit; each degree group then waits for its step's checks, one host
+ * synchronisation per round of redos).
  * esdg_ensemble_build uploads everything (done by the first step or query
  * if not called); no instance can be added afterwards.
  * esdg_ensemble_step advances every instance by nsteps adaptive steps and

@@ -223,6 +223,7 @@ hipError_t Launch<N, R>::stage(const Bufs &B, const StageCall &c, const Phys<R> 
     a.cb = (R)c.cb;
     a.flags = B.flags;
     a.iflags = B.iflags;
+    a.imask = (c.masked && a.inst) ? B.imask : nullptr;
     a.variant = c.variant;
     if (c.mode == kModeRhs) launch_stage<N, R, kModeRhs>(a, B.K, s, ev);
     else if (c.mode == kModeLsrk) launch_stage<N, R, kModeLsrk>(a, B.K, s, ev);

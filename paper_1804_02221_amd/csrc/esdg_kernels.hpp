@@ -1074,6 +1074,8 @@ struct StageArgs {
     R ca, cb;                    // LSRK a_k, b_k; SSP alpha_k, beta_k
     int *flags;                  // status flags (kFlag*)
     int *iflags;                 // ensembles with step retries: per-instance flags (1: negative mean), else nullptr
+    const int *imask;            // with inst: only elements of instances k with imask[k] != 0 (a retry of
+                                 // some instances), else nullptr
     int64_t ntiles;
     int variant;                 // compiled variant 0..kStageVariants-1 (launch side)
 };
@@ -1150,7 +1152,10 @@ __global__ __launch_bounds__((StageCfg<N, V>::T), (StageWaves<N, R, MODE, V>::va
     const bool lane = t < E * np;
     const int el = lane ? t / np : E - 1, p = lane ? t - el * np : 0, i = p / nf, j = p - i * nf;
     const int64_t e0 = tile * E, e = e0 + el;
-    const bool act = lane && (e < a.m.K);
+    const bool act = lane && (e < a.m.K) && (!a.imask || a.imask[a.inst[e]] != 0);
+    // a retry of some instances: tiles with none of their elements leave
+    // every output as it is
+    if (a.imask && !block_any<T>(act)) return;
     const int64_t q = e * np + p;
     const Phys<R> &P = a.P;
     const bool av = a.eps != nullptr;

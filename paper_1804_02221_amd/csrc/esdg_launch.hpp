@@ -62,6 +62,7 @@ struct StageCall {
     bool dt_next;      // last stage of a step: leave the output's dt bounds in dtc/dtv
     bool store_du;     // LSRK: write the register dU (not needed after the last stage)
     int variant;       // stage-kernel workgroup size: 0 default, 1 alternative
+    bool masked = false;  // ensembles: only the elements of instances with imask set
 };
 
 // One reverse stage of the discrete adjoint (float64 contexts only).

@@ -76,6 +76,15 @@ __global__ void fill_int_kernel(int *p, int v, int n)
     if (t < n) p[t] = v;
 }
 
+// The viscous-element list of a state from its element viscosities (count
+// zeroed beforehand; the list order does not matter to the viscous passes).
+template <typename R>
+__global__ void relist_kernel(const R *eps, int32_t *list, int *count, int64_t K)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < K && eps[e] > R(0)) list[atomicAdd(count, 1)] = (int32_t)e;
+}
+
 // Step status flags: [0] negative element mean, [1] limited elements,
 // [2] no admissible step, [3] J <= 0 at mesh upload (kept), [4] non-finite
 // stage output, [5] step above twice the bounds of its result.  Clears all
@@ -261,6 +270,7 @@ struct esdg_ctx {
     bool eps_valid[3] = {false, false, false};   // viscosity/list of state buffer b are current
     int dtb_buf = -1;   // state buffer whose per-element dt bounds are in dtc/dtv (-1: none)
     int stage_variant = 0;   // compiled stage-kernel variant (esdg_autotune)
+    bool masked_attempt = false;  // stage launches cover only the instances set in B.imask
     // Executable graphs of one time step (esdg_step), one per start buffer:
     // the kernel sequence of a step is fixed once the viscosity of the start
     // state and (adaptive step) its dt bounds are current.  A graph is valid
@@ -519,6 +529,7 @@ int launch_viscous(esdg_ctx *ctx, int buf, int reset)
 int launch_stage(esdg_ctx *ctx, StageCall sc)
 {
     sc.variant = ctx->stage_variant;
+    sc.masked = ctx->masked_attempt;
     return timed(ctx, kProfStage, [&](Ev ev) {
         return dispatch(ctx, [&](auto L, auto r) {
             using R = decltype(r);
@@ -1767,8 +1778,29 @@ int group_attempt(esdg_ctx *ctx, int base, bool first, int *hflags)
     if (first) {
         TRY(graph_ready(ctx, 0.0) ? graph_step(ctx, 0.0) : launch_one_step(ctx, 0.0));
     } else {
+        // a redo covers only the instances in the mask: the stage kernels
+        // leave the other instances' elements, whose outputs of the step
+        // before are the same bit for bit, as they are.  Only the result's
+        // viscous-element list is rebuilt for all of them (each stage
+        // rebuilds its output's list from the elements it covers).
         ctx->cur = base;
-        TRY(launch_one_step(ctx, 0.0, false));
+        ctx->masked_attempt = ni > 1;
+        const int st = launch_one_step(ctx, 0.0, false);
+        ctx->masked_attempt = false;
+        TRY(st);
+        if (ni > 1 && ctx->P.av_on) {
+            const int o = ctx->cur;
+            hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->B.count + o, 0, 1);
+            CK(hipGetLastError());
+            const unsigned g = (unsigned)((ctx->K + 255) / 256);
+            if (ctx->prec == 64)
+                hipLaunchKernelGGL(relist_kernel<double>, dim3(g), dim3(256), 0, ctx->stream,
+                                   (const double *)ctx->B.eps[o], ctx->B.list[o], ctx->B.count + o, ctx->K);
+            else
+                hipLaunchKernelGGL(relist_kernel<float>, dim3(g), dim3(256), 0, ctx->stream,
+                                   (const float *)ctx->B.eps[o], ctx->B.list[o], ctx->B.count + o, ctx->K);
+            CK(hipGetLastError());
+        }
     }
     TRY(dispatch(ctx, [&](auto L, auto r) {
         using R = decltype(r);
@@ -1853,12 +1885,11 @@ int esdg_ensemble_step(esdg_ensemble *en, int nsteps)
                 for (int k = 0; k < ni; ++k) {
                     mask[k] = (ifl[k] != 0 && tries[g][k] < c->P.max_dt_retries) ? 1 : 0;
                     any = any || mask[k];
+                    // an instance out of retries keeps its step (a redo of
+                    // the others skips it, so its flags are taken here)
+                    if (!mask[k] && (ifl[k] & 1)) negmean = true;
                 }
-                if (!any) {
-                    for (int k = 0; k < ni; ++k)
-                        if (ifl[k] & 1) negmean = true;
-                    continue;
-                }
+                if (!any) continue;
                 for (int k = 0; k < ni; ++k) tries[g][k] += mask[k];
                 int st = ESDG_OK;
                 if (hipMemcpyAsync(c->B.imask, mask, ni * sizeof(int), hipMemcpyHostToDevice, c->stream) !=
