@@ -222,9 +222,11 @@ def test_ensemble_step_retries_equal_single_solves(esdg):
     """Ensembles take the step check per instance: with SSPRK(3,3) and three
     retries, the dam break at rest redoes its first step at half the size
     (its result outruns its own CFL bound) while the other instances keep
-    theirs; the degree group's step is relaunched from W^n, so every
-    instance equals its single solve with the same retries bitwise, time
-    included, over several steps and two degree groups."""
+    theirs; the redo covers only the instances in the retry mask (the stage
+    kernels skip the others, whose results stay), so every instance equals
+    its single solve with the same retries bitwise, time included, over
+    several steps and two degree groups (the group of N = 3 holds instances
+    that redo and instances that do not)."""
     kw = dict(av_on=1, limiter_on=1, eps0=0.05, integrator=1, max_dt_retries=3)
     ws = [dam_break(6, 3, seed=4, rotate_seed=3), smooth_sweep(4, 3, seed=21), dam_break(5, 3, seed=22),
           dam_break(4, 5, seed=23, rotate_seed=1), smooth_sweep(3, 5, seed=24)]
