@@ -785,7 +785,7 @@ def main():
             "bytes_per_launch": main_res["stage_bytes_per_launch"],
             "viscous_elements": main_res["n_visc"],
             "mean_launch_ms": main_res["stage_mean_ms"],
-            "fp64_vector": {"achieved_TFLOPs": main_res["stage_TFLOPs"],
+            f"fp{args.precision}_vector": {"achieved_TFLOPs": main_res["stage_TFLOPs"],
                             "peak_TFLOPs": 78.6 if args.precision == 64 else 157.3,
                             "flops_per_node": main_res["flops_per_node"],
                             "note": "algorithmic FLOPs of the method (bench.stage_flops)"},
